@@ -1,0 +1,130 @@
+/*
+ * rmb.h -- C ABI of the MI355X rigid-multiblob mobility library (librmb.so).
+ *
+ * The library solves the mobility problem of rigid bodies discretised as
+ * rigid multiblobs in Stokes flow (Balboa Usabiaga et al., "Hydrodynamics of
+ * suspensions of passive and active rigid particles: a rigid multiblob
+ * approach"):
+ *
+ *     [ M   -K ] [lambda]   [ slip ]
+ *     [-K^T  0 ] [  U   ] = [  -F  ]          (Sec. 2.1.2, eq:saddle_M)
+ *
+ * M is the 3Nb x 3Nb blob-blob mobility (free-space Rotne-Prager-Yamakawa,
+ * eq:RPYTensor, or RPY plus the Rotne-Prager-Blake single-wall correction,
+ * Sec. 2.1.1), K maps rigid-body motions to blob velocities
+ * (eq:noslip_rigid), F holds applied forces and torques, slip the active
+ * slip, U the body velocities and lambda the blob constraint forces.  The
+ * solver is right-preconditioned GMRES with the indefinite block-diagonal
+ * preconditioner (Sec. 2.2.2, eq:indef_block_P, eq:saddle_M_precon).
+ *
+ * Conventions shared by every entry point
+ *  - Units: viscosity eta and blob radius a are per system; the wall, when
+ *    present, is the plane z = 0 with fluid in z > 0.
+ *  - Layouts (row-major, C order):
+ *      blob positions, blob vectors (lambda, velocities, slip): [n_blobs][3]
+ *      body tracking points q:                                  [n_bodies][3]
+ *      body force/torque F and velocity U:      [n_bodies][6] = (f, tau), (u, omega)
+ *      saddle-point vectors: [lambda (3 n_blobs) ; U (6 n_bodies)]
+ *    Torques and angular velocities are about the tracking point q_p.
+ *  - Memory: every `double*` argument is a DEVICE pointer on the context's
+ *    device unless marked "host".  The caller owns every argument buffer;
+ *    the library never frees or retains them beyond the call (the server
+ *    entry points retain them until the request completes, as documented
+ *    there).  Output buffers must not alias inputs.
+ *  - Streams: `stream` is a hipStream_t (NULL = the null stream).  Calls
+ *    enqueue their work on it; calls that must return a status that depends
+ *    on device results (validation, factorisation failure, convergence)
+ *    synchronise that stream before returning.
+ *  - Errors: every call returns an rmb_status; no exception crosses the ABI.
+ *    On failure a message is available from rmb_last_error(ctx).
+ */
+#ifndef RMB_H
+#define RMB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RMB_OK = 0,
+    RMB_EINVAL = 1,   /* bad argument: a <= 0, eta <= 0, bad offsets, z <= 0 above a wall,
+                         non-finite positions, null pointer, unknown enum value */
+    RMB_ENOTSPD = 2,  /* a per-body mobility block is not positive definite (blobs overlapping
+                         the wall, Sec. 2.1.1 and Conclusions) or its Schur complement is
+                         singular */
+    RMB_ENOCONV = 3,  /* iteration limit reached; outputs hold the best iterate and the info
+                         struct the FP64 residual reached */
+    RMB_ENOMEM = 4,   /* the request does not fit the context's device-memory budget */
+    RMB_EDEVICE = 5,  /* a HIP runtime call failed */
+    RMB_EBUSY = 6     /* server: queue full */
+} rmb_status;
+
+enum { RMB_GEOM_FREE = 0, RMB_GEOM_WALL = 1 };
+
+/* Pair arithmetic of the blob mobility product.
+ *  RMB_PREC_FP64:       every pair block in FP64, FP64 sums.
+ *  RMB_PREC_FP32_PAIRS: r_i - r_j formed in FP64 and rounded once to FP32,
+ *                       pair blocks and products in FP32, sums of each
+ *                       target's velocity in FP32 over blocks of 64 sources
+ *                       and FP64 across blocks. */
+enum { RMB_PREC_FP64 = 0, RMB_PREC_FP32_PAIRS = 1 };
+
+typedef struct rmb_ctx_s *rmb_ctx;
+typedef struct rmb_precond_s *rmb_precond;
+typedef void *rmb_stream; /* hipStream_t */
+
+/* One suspension (Sec. 2.1: blobs B_p rigidly attached to bodies p). */
+typedef struct {
+    int64_t n_blobs;         /* Nb >= 1 */
+    int64_t n_bodies;        /* N >= 1 (the mobility product alone ignores bodies) */
+    const double *pos;       /* device [Nb][3] blob positions r_i (lab frame) */
+    const int64_t *body_off; /* HOST [N+1]: blobs of body p are [body_off[p], body_off[p+1]),
+                                body_off[0] = 0, strictly increasing, body_off[N] = Nb */
+    const double *q;         /* device [N][3] tracking points q_p */
+    double a;                /* blob hydrodynamic radius, > 0 */
+    double eta;              /* viscosity, > 0 */
+    int32_t geometry;        /* RMB_GEOM_FREE or RMB_GEOM_WALL (then every z_i > 0) */
+} rmb_system;
+
+/* ---------------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device`.  `hbm_budget_bytes` caps the
+ * device memory the library may hold for workspaces, factors and Krylov
+ * bases (0 = 16 GiB).  Memory is reserved lazily.  *out receives the
+ * handle.  Errors: RMB_EINVAL (null out, bad device), RMB_EDEVICE. */
+rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out);
+
+/* Releases every device allocation the context holds.  Safe on NULL. */
+void rmb_ctx_destroy(rmb_ctx ctx);
+
+/* Message of the last failed call on this context (never NULL; "" if none).
+ * Valid until the next call on the context. */
+const char *rmb_last_error(rmb_ctx ctx);
+
+/* Library version string. */
+const char *rmb_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Blob mobility product  v = M lambda   (Sec. 2.2.1; eq:RPYTensor and the
+ * wall-corrected form of Sec. 2.1.1 and Sec. 5)
+ * ------------------------------------------------------------------------- */
+
+/* vel[i] = sum_j M_ij lambda[j] over all blobs of `sys` (bodies are ignored;
+ * n_bodies, body_off and q may be 0/NULL).  lambda and vel: device
+ * [Nb][3] FP64, must not alias.  `precision` is an RMB_PREC_* value.
+ * Errors: RMB_EINVAL (bad system, z_i <= 0 in wall geometry, non-finite
+ * positions), RMB_ENOMEM, RMB_EDEVICE.  Synchronises `stream` once for
+ * validation. */
+rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
+                               const double *lambda, double *vel, rmb_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RMB_H */

@@ -1,0 +1,177 @@
+// Context management, validation and the blob mobility product entry point.
+#include <cmath>
+#include <cstring>
+
+#include "rmb_ctx.h"
+
+namespace rmb {
+
+rmb_status fail(rmb_ctx ctx, rmb_status st, const char *fmt, ...) {
+    if (ctx) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return st;
+}
+
+rmb_status enter(rmb_ctx ctx, hipStream_t s) {
+    RMB_HIP(ctx, hipSetDevice(ctx->device));
+    if (ctx->any_stream && ctx->last_stream != s) RMB_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+    ctx->last_stream = s;
+    ctx->any_stream = true;
+    ctx->err.clear();
+    return RMB_OK;
+}
+
+rmb_status scratch(rmb_ctx ctx, size_t bytes, void **out) {
+    if (bytes <= ctx->scratch_bytes) {
+        *out = ctx->scratch;
+        return RMB_OK;
+    }
+    // the old scratch may still be read by queued work on the current stream
+    if (ctx->scratch) {
+        RMB_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+        ctx->arena->free(ctx->scratch);
+        ctx->scratch = nullptr;
+        ctx->scratch_bytes = 0;
+    }
+    size_t want = bytes + bytes / 4;
+    void *p = ctx->arena->alloc(want);
+    if (!p) {
+        want = bytes;
+        p = ctx->arena->alloc(want);
+    }
+    if (!p)
+        return fail(ctx, RMB_ENOMEM, "scratch of %zu bytes exceeds the device-memory budget (%zu in use of %zu)",
+                    bytes, ctx->arena->in_use(), ctx->arena->budget());
+    ctx->scratch = p;
+    ctx->scratch_bytes = want;
+    *out = p;
+    return RMB_OK;
+}
+
+rmb_status pinned(rmb_ctx ctx, size_t bytes, void **out) {
+    if (bytes > ctx->pinned_bytes) {
+        if (ctx->pinned) {
+            RMB_HIP(ctx, hipStreamSynchronize(ctx->last_stream));
+            RMB_HIP(ctx, hipHostFree(ctx->pinned));
+            ctx->pinned = nullptr;
+            ctx->pinned_bytes = 0;
+        }
+        size_t want = std::max<size_t>(bytes, 1 << 16);
+        RMB_HIP(ctx, hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault));
+        ctx->pinned_bytes = want;
+    }
+    *out = ctx->pinned;
+    return RMB_OK;
+}
+
+rmb_status check_system(rmb_ctx ctx, const rmb_system *sys, bool need_bodies) {
+    if (!sys) return fail(ctx, RMB_EINVAL, "system is NULL");
+    if (sys->n_blobs < 1) return fail(ctx, RMB_EINVAL, "n_blobs must be >= 1 (got %lld)", (long long)sys->n_blobs);
+    if (sys->n_blobs > (int64_t(1) << 31) / 3)
+        return fail(ctx, RMB_EINVAL, "n_blobs %lld is above the supported maximum", (long long)sys->n_blobs);
+    if (!sys->pos) return fail(ctx, RMB_EINVAL, "pos is NULL");
+    if (!(sys->a > 0.0) || !std::isfinite(sys->a)) return fail(ctx, RMB_EINVAL, "blob radius a must be > 0");
+    if (!(sys->eta > 0.0) || !std::isfinite(sys->eta)) return fail(ctx, RMB_EINVAL, "viscosity eta must be > 0");
+    if (sys->geometry != RMB_GEOM_FREE && sys->geometry != RMB_GEOM_WALL)
+        return fail(ctx, RMB_EINVAL, "unknown geometry %d", sys->geometry);
+    if (need_bodies) {
+        if (sys->n_bodies < 1) return fail(ctx, RMB_EINVAL, "n_bodies must be >= 1");
+        if (!sys->body_off || !sys->q) return fail(ctx, RMB_EINVAL, "body_off and q are required");
+        if (sys->body_off[0] != 0) return fail(ctx, RMB_EINVAL, "body_off[0] must be 0");
+        for (int64_t p = 0; p < sys->n_bodies; ++p)
+            if (sys->body_off[p + 1] <= sys->body_off[p])
+                return fail(ctx, RMB_EINVAL, "body_off must be strictly increasing (body %lld)", (long long)p);
+        if (sys->body_off[sys->n_bodies] != sys->n_blobs)
+            return fail(ctx, RMB_EINVAL, "body_off[n_bodies] must equal n_blobs");
+    }
+    return RMB_OK;
+}
+
+rmb_status check_positions(rmb_ctx ctx, const rmb_system *sys, int *flag_dev, hipStream_t s) {
+    int *h = nullptr;
+    RMB_TRY(pinned(ctx, sizeof(int), (void **)&h));
+    RMB_HIP(ctx, hipMemsetAsync(flag_dev, 0, sizeof(int), s));
+    RMB_HIP(ctx, launch_validate_positions(sys->pos, sys->n_blobs, sys->geometry == RMB_GEOM_WALL, flag_dev, s));
+    RMB_HIP(ctx, hipMemcpyAsync(h, flag_dev, sizeof(int), hipMemcpyDeviceToHost, s));
+    RMB_HIP(ctx, hipStreamSynchronize(s));
+    if (*h & 1) return fail(ctx, RMB_EINVAL, "non-finite blob position");
+    if (*h & 2) return fail(ctx, RMB_EINVAL, "a blob has z <= 0 in wall geometry");
+    return RMB_OK;
+}
+
+}  // namespace rmb
+
+using namespace rmb;
+
+extern "C" {
+
+const char *rmb_version(void) { return "rmb 0.1 (gfx950)"; }
+
+rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
+    if (!out) return RMB_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return RMB_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return RMB_EDEVICE;
+    rmb_ctx c = new rmb_ctx_s();
+    c->device = device;
+    c->arena = new Arena(hbm_budget_bytes ? hbm_budget_bytes : (size_t(16) << 30));
+    *out = c;
+    return RMB_OK;
+}
+
+void rmb_ctx_destroy(rmb_ctx ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    delete ctx->arena;
+    delete ctx;
+}
+
+const char *rmb_last_error(rmb_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                               double *vel, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_system(ctx, sys, false));
+    if (precision != RMB_PREC_FP64 && precision != RMB_PREC_FP32_PAIRS)
+        return fail(ctx, RMB_EINVAL, "unknown precision %d", precision);
+    if (!lambda || !vel) return fail(ctx, RMB_EINVAL, "lambda and vel are required");
+    if ((const void *)lambda == (const void *)vel) return fail(ctx, RMB_EINVAL, "vel must not alias lambda");
+
+    const int64_t nb = sys->n_blobs;
+    PairJob J;
+    pair_job_init(&J, sys->pos, nullptr, nullptr, nb, sys->a);
+    const size_t rec = precision == RMB_PREC_FP32_PAIRS ? sizeof(SrcF32) : sizeof(SrcF64);
+    // scratch layout: [flag | job | sources | partials]
+    size_t off_job = 256, off_src = off_job + 256;
+    size_t off_part = off_src + (nb * rec + 255) / 256 * 256;
+    size_t total = off_part + (size_t)J.n_split * nb * 3 * sizeof(double);
+    char *base = nullptr;
+    RMB_TRY(scratch(ctx, total, (void **)&base));
+    RMB_TRY(check_positions(ctx, sys, (int *)base, s));
+
+    J.src = base + off_src;
+    J.partial = (double *)(base + off_part);
+    J.tile_begin = 0;
+    PairJob *hJ = nullptr;
+    RMB_TRY(pinned(ctx, sizeof(PairJob), (void **)&hJ));
+    *hJ = J;
+    RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(PairJob), hipMemcpyHostToDevice, s));
+    RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
+    RMB_HIP(ctx, launch_pair_tiles(precision, sys->geometry == RMB_GEOM_WALL, (const PairJob *)(base + off_job), 1,
+                                   (int64_t)J.n_tblock * J.n_split, s));
+    RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, nb, mobility_prefactor(sys->a, sys->eta), vel, s));
+    return RMB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Shared declarations of the rigid-multiblob GPU library (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/rmb.h"
+
+namespace rmb {
+
+// ---------------------------------------------------------------------------
+// pair-product work description
+// ---------------------------------------------------------------------------
+
+// Source record of the FP32-pair product: position in FP64 (the difference
+// r_i - r_j is formed in FP64 and rounded once), force and height in FP32.
+struct alignas(8) SrcF32 {
+    double x, y, z;
+    float fx, fy, fz, zf;
+};
+
+// Source record of the FP64 product.
+struct alignas(16) SrcF64 {
+    double x, y, z, fx, fy, fz;
+};
+
+constexpr int kPairBlock = 256;  // targets per workgroup (4 waves of 64)
+constexpr int kAccBlock = 64;    // FP32 sums are flushed to FP64 every 64 sources
+
+// One system's share of a pair-product launch.  Workgroups
+// [tile_begin, tile_begin + n_tblock * n_split) of the launch belong to it;
+// local workgroup w covers targets [(w % n_tblock) * 256, +256) against
+// sources [(w / n_tblock) * chunk, +chunk) and writes partial slot
+// w / n_tblock.
+struct PairJob {
+    const double *tpos;  // [nb][3] target positions
+    const void *src;     // [nb] SrcF32 or SrcF64 records
+    double *partial;     // [n_split][nb][3] per-split sums (no prefactor)
+    int64_t nb;
+    int64_t tile_begin;
+    int64_t chunk;
+    int32_t n_tblock;
+    int32_t n_split;
+    // RPY constants (eq:RPYTensor) in both precisions: a, 4a^2, 9/(32a), 3/(32a)
+    double a, four_a2, k_near_iso, k_near_rr;
+    float a_f, four_a2_f, k_near_iso_f, k_near_rr_f;
+};
+
+// Number of source splits and the split length for a system of nb blobs.
+// A function of nb only, so that a system's arithmetic does not depend on
+// what else shares the launch.
+void split_plan(int64_t nb, int32_t *n_split, int64_t *chunk, int32_t *n_tblock);
+
+// Fills the plan fields and constants of a PairJob.
+void pair_job_init(PairJob *J, const double *tpos, const void *src, double *partial, int64_t nb,
+                   double a);
+
+// Kernel launchers (rmb_pair.hip).
+hipError_t launch_pack_sources(int precision, const double *pos, const double *lam, int64_t nb,
+                               void *src, hipStream_t s);
+// jobs: device array of n_jobs PairJob with increasing tile_begin; n_tiles is
+// the total workgroup count.
+hipError_t launch_pair_tiles(int precision, bool wall, const PairJob *jobs, int32_t n_jobs,
+                             int64_t n_tiles, hipStream_t s);
+// v[i] = pref * sum_s partial[s][i]
+hipError_t launch_reduce_partials(const double *partial, int32_t n_split, int64_t nb, double pref,
+                                  double *v, hipStream_t s);
+// flag |= 1 for a non-finite coordinate, |= 2 for z <= 0 when wall != 0
+hipError_t launch_validate_positions(const double *pos, int64_t nb, int wall, int *flag,
+                                     hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// device memory
+// ---------------------------------------------------------------------------
+
+// First-fit sub-allocator over large hipMalloc blocks, capped at a budget.
+class Arena {
+  public:
+    explicit Arena(size_t budget) : budget_(budget) {}
+    ~Arena();
+    // Returns nullptr when the budget would be exceeded or hipMalloc fails.
+    void *alloc(size_t bytes);
+    void free(void *p);
+    size_t budget() const { return budget_; }
+    size_t in_use() const { return in_use_; }
+
+  private:
+    struct Seg {
+        size_t off, size;
+        bool used;
+    };
+    struct Block {
+        char *base;
+        size_t size;
+        std::vector<Seg> segs;
+    };
+    std::vector<Block> blocks_;
+    size_t budget_;
+    size_t reserved_ = 0;
+    size_t in_use_ = 0;
+};
+
+}  // namespace rmb

@@ -1,0 +1,61 @@
+// Library context and host-side helpers (internal).
+#pragma once
+
+#include <cstdarg>
+#include <string>
+
+#include "rmb_common.h"
+
+struct rmb_ctx_s {
+    int device = 0;
+    std::string err;
+    rmb::Arena *arena = nullptr;
+    // Scratch reused by every call on this context (grow-only).
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    // Pinned host staging for small uploads/downloads.
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipStream_t last_stream = nullptr;
+    bool any_stream = false;
+};
+
+namespace rmb {
+
+rmb_status fail(rmb_ctx ctx, rmb_status st, const char *fmt, ...);
+
+#define RMB_HIP(ctx, call)                                                                    \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return ::rmb::fail((ctx), RMB_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define RMB_TRY(expr)                   \
+    do {                                \
+        rmb_status st_ = (expr);        \
+        if (st_ != RMB_OK) return st_;  \
+    } while (0)
+
+// Makes the context's device current and orders this call after work the
+// previous call left on another stream (scratch and staging are reused).
+rmb_status enter(rmb_ctx ctx, hipStream_t s);
+
+// Grow-only scratch of at least `bytes` (device).
+rmb_status scratch(rmb_ctx ctx, size_t bytes, void **out);
+// Grow-only pinned host staging of at least `bytes`.
+rmb_status pinned(rmb_ctx ctx, size_t bytes, void **out);
+
+// Host-side checks of a system description.  need_bodies: body_off and q
+// must describe n_bodies bodies covering all blobs.
+rmb_status check_system(rmb_ctx ctx, const rmb_system *sys, bool need_bodies);
+
+// Device-side checks of positions (finite; z > 0 above a wall).  Uses
+// `flag_dev` (one int of device memory) and synchronises `s`.
+rmb_status check_positions(rmb_ctx ctx, const rmb_system *sys, int *flag_dev, hipStream_t s);
+
+inline double mobility_prefactor(double a, double eta) {
+    return 1.0 / (6.0 * 3.14159265358979323846 * eta * a);
+}
+
+}  // namespace rmb

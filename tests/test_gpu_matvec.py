@@ -1,0 +1,137 @@
+"""Parity of the HIP blob mobility product with the CPU FP64 oracle.
+
+Bar: relative 2-norm error over the whole (Nb, 3) result <= 1e-12 for FP64
+pairs and <= 1e-5 for FP32 pairs with FP64 accumulation.
+"""
+import numpy as np
+import pytest
+
+import suspensions as S
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def env(oracle_mod):
+    import torch
+    import paper_1602_02170_amd as rmb
+    ctx = rmb.Context(0)
+    yield rmb, torch, ctx, oracle_mod
+    ctx.close()
+
+
+def _run(env, sus, lam, prec):
+    rmb, torch, ctx, _ = env
+    sysd = rmb.System.from_suspension(sus) if sus.body_off is not None else None
+    lt = torch.tensor(lam, dtype=torch.float64, device="cuda")
+    v = rmb.mobility_matvec(ctx, sysd, lt, prec)
+    torch.cuda.synchronize()
+    return v.cpu().numpy()
+
+
+def _rel(v, ref):
+    return np.linalg.norm(v - ref) / np.linalg.norm(ref)
+
+
+def _cases():
+    out = []
+    s1 = S.spheres_free_space()
+    out.append(("free 8x12 icosahedra", s1, np.random.default_rng(11).standard_normal((96, 3))))
+    s2 = S.boomerangs_wall(n_bodies=203, lateral=90.0)  # 3045 blobs: ragged last tile
+    out.append(("wall 203 boomerangs", s2, np.random.default_rng(12).standard_normal((s2.n_blobs, 3))))
+    s3, l3 = S.icosahedra_monolayer(n_bodies=1100)  # 13200 blobs
+    out.append(("wall monolayer 1100 icosahedra", s3, l3))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", range(len(CASES)), ids=[c[0] for c in CASES])
+def test_matvec_parity(env, case, prec):
+    name, sus, lam = CASES[case]
+    print(f"[gpu] matvec parity {name} {prec} nb={sus.n_blobs}", flush=True)
+    ref = env[3].matvec(sus.pos, lam, sus.a, sus.eta, sus.wall)
+    v = _run(env, sus, lam, prec)
+    err = _rel(v, ref)
+    print(f"    rel err {err:.3e}", flush=True)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_matvec_full_monolayer_sampled_rows(env, prec):
+    """Full 16384 x 12 = 196,608-blob monolayer: sampled target rows against
+    the oracle's per-row sums."""
+    sus, lam = S.icosahedra_monolayer()
+    print(f"[gpu] full monolayer {prec} nb={sus.n_blobs}", flush=True)
+    v = _run(env, sus, lam, prec)
+    rows = np.random.default_rng(13).choice(sus.n_blobs, 96, replace=False)
+    rows = np.concatenate([rows, [0, sus.n_blobs - 1]])
+    ref = env[3].matvec_rows(sus.pos, lam, rows, sus.a, sus.eta, sus.wall)
+    err = _rel(v[rows], ref)
+    print(f"    sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL[prec]
+    assert np.all(np.isfinite(v))
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_matvec_edge_cases(env, prec):
+    rmb, torch, ctx, O = env
+    a = 0.5
+    # one blob: the self block alone, above the wall
+    for pos, wall in [(np.array([[0.3, -0.2, 1.7]]), True), (np.array([[0.0, 0.0, 0.0]]), False)]:
+        sus = S.Suspension(pos, np.array([0, 1]), pos.copy(), a, 1.0, wall)
+        lam = np.array([[1.0, -2.0, 0.5]])
+        v = _run(env, sus, lam, prec)
+        ref = O.matvec(pos, lam, a, 1.0, wall)
+        assert _rel(v, ref) <= TOL[prec]
+    # coincident blobs, a pair exactly at 2a, overlapping pairs, and 65 blobs
+    # (one full wave plus a ragged lane)
+    rng = np.random.default_rng(14)
+    pos = rng.uniform(0, 2.0, (65, 3))
+    pos[:, 2] += 0.6
+    pos[1] = pos[0]
+    pos[2] = pos[0] + np.array([2 * a, 0, 0])
+    sus = S.Suspension(pos, np.array([0, 65]), pos[:1].copy(), a, 1.0, True)
+    lam = rng.standard_normal((65, 3))
+    for wall in (True, False):
+        sus.wall = wall
+        v = _run(env, sus, lam, prec)
+        ref = O.matvec(pos, lam, a, 1.0, wall)
+        assert _rel(v, ref) <= TOL[prec]
+
+
+def test_matvec_deterministic_and_permutation_covariant(env):
+    rmb, torch, ctx, O = env
+    sus = S.boomerangs_wall(n_bodies=150, lateral=70.0)
+    lam = np.random.default_rng(15).standard_normal((sus.n_blobs, 3))
+    for prec in ("fp64", "fp32"):
+        v1 = _run(env, sus, lam, prec)
+        v2 = _run(env, sus, lam, prec)
+        assert np.array_equal(v1, v2)
+        perm = np.random.default_rng(16).permutation(sus.n_blobs)
+        sp = S.Suspension(sus.pos[perm], np.array([0, sus.n_blobs]), sus.q[:1], sus.a, 1.0, True)
+        vp = _run(env, sp, lam[perm], prec)
+        assert _rel(vp, v1[perm]) <= TOL[prec]
+
+
+def test_matvec_rejects_bad_input(env):
+    rmb, torch, ctx, O = env
+    pos = np.array([[0.0, 0.0, 1.0], [1.0, 0.0, -0.1]])
+    lam = np.ones((2, 3))
+    sus = S.Suspension(pos, np.array([0, 2]), pos[:1].copy(), 0.3, 1.0, True)
+    with pytest.raises(rmb.RmbError) as e:
+        _run(env, sus, lam, "fp64")
+    assert e.value.status == rmb.RMB_EINVAL and "z <= 0" in str(e.value)
+    pos[1, 2] = np.nan
+    sus.wall = False
+    with pytest.raises(rmb.RmbError) as e:
+        _run(env, sus, lam, "fp64")
+    assert e.value.status == rmb.RMB_EINVAL
+    sus = S.Suspension(np.array([[0.0, 0, 1]]), np.array([0, 1]), np.zeros((1, 3)), -1.0, 1.0, False)
+    with pytest.raises(rmb.RmbError) as e:
+        _run(env, sus, np.ones((1, 3)), "fp64")
+    assert e.value.status == rmb.RMB_EINVAL
