@@ -123,6 +123,118 @@ const char *rmb_version(void);
 rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
                                const double *lambda, double *vel, rmb_stream stream);
 
+
+/* ---------------------------------------------------------------------------
+ * Block-diagonal preconditioner (Sec. 2.2.2: eq:M_tilde_block_diag,
+ * eq:indef_block_P, eq:saddle_M_precon)
+ * ------------------------------------------------------------------------- */
+
+/* Assembles every body's 3n_p x 3n_p mobility block M_pp (same pair tensor
+ * as the product, wall included), factorises all of them in one launch,
+ * and forms Y_p = L_p^-1 K_p and the Cholesky factor of
+ * K_p^T M_pp^-1 K_p.  The factors hold device pointers into `sys->pos` and
+ * `sys->q`, which must stay valid and unchanged while *out is used.
+ * Errors: RMB_EINVAL (bad system), RMB_ENOTSPD (a block is not SPD, e.g.
+ * blobs overlapping the wall, or a body's K_p^T M_pp^-1 K_p is singular),
+ * RMB_ENOMEM, RMB_EDEVICE.  Synchronises `stream`. */
+rmb_status rmb_precond_factor(rmb_ctx ctx, const rmb_system *sys, rmb_precond *out, rmb_stream stream);
+
+/* out_r = P^-1 in_r for r < nrhs saddle vectors stored at in + r*(3Nb+6N)
+ * (device, FP64): per body, [M_pp -K_p; -K_p^T 0][lambda_p; U_p] =
+ * [in_lambda_p; in_U_p] is solved exactly.  `in` and `out` must not alias.
+ * Asynchronous on `stream`. */
+rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, const double *in,
+                             double *out, rmb_stream stream);
+
+/* Releases the factors (after work using them has completed).  Safe on NULL. */
+void rmb_precond_destroy(rmb_precond pc);
+
+/* ---------------------------------------------------------------------------
+ * Mobility solve (eq:saddle_M by right-preconditioned GMRES, Sec. 2.2)
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+    double tol;          /* target ||b - A x|| / ||b|| with the FP64 operator; 0 -> 1e-8 */
+    int32_t precision;   /* RMB_PREC_FP64: GMRES on the FP64 operator.
+                            RMB_PREC_FP32_PAIRS: inner GMRES cycles on the FP32-pair
+                            operator, each followed by an FP64 residual (iterative
+                            refinement); the stopping test always uses FP64. */
+    int32_t restart;     /* GMRES cycle length m in 1..255; 0 -> 100 */
+    int32_t max_iters;   /* Arnoldi steps over all cycles; 0 -> 1000 */
+    int32_t pad;
+    double inner_tol;    /* refinement: residual reduction asked of each inner cycle;
+                            0 -> 1e-5 */
+} rmb_solve_opts;
+
+typedef struct {
+    int32_t status;        /* rmb_status of this solve */
+    int32_t iterations;    /* Arnoldi steps */
+    int32_t cycles;        /* GMRES cycles (restarts and refinement sweeps) */
+    int32_t matvecs_fp64;  /* FP64 pair products, residual checks included */
+    int32_t matvecs_fp32;  /* FP32-pair products */
+    int32_t pad;
+    double rel_residual;   /* final ||b - A x|| / ||b|| with the FP64 operator */
+    double seconds;        /* host wall time from admission to completion */
+} rmb_solve_info;
+
+/* Mobility problem: given F (device [N][6], force then torque about q_p) and
+ * optional slip (device [Nb][3] or NULL), returns U (device [N][6]) and
+ * lambda (device [Nb][3]) with b = [slip; -F], x0 = 0.  `pc` may be a
+ * preconditioner built by rmb_precond_factor for this same system, or NULL
+ * (factorised internally).  opts may be NULL (defaults).  info may be NULL.
+ * Errors: RMB_EINVAL, RMB_ENOTSPD, RMB_ENOCONV (outputs hold the last
+ * iterate; info->rel_residual its FP64 residual), RMB_ENOMEM, RMB_EDEVICE.
+ * Blocks until the solve is complete (one stream synchronisation per
+ * Arnoldi step). */
+rmb_status rmb_solve_mobility(rmb_ctx ctx, const rmb_system *sys, const rmb_precond pc, const double *FT,
+                              const double *slip, double *U, double *lambda, const rmb_solve_opts *opts,
+                              rmb_solve_info *info, rmb_stream stream);
+
+/* `count` independent mobility problems solved together: every active
+ * system advances one Arnoldi step per batched launch, and systems are
+ * admitted as device memory frees up.  Arrays of length `count` (host
+ * arrays of device pointers; slip entries may be NULL).  Each system's
+ * result is bitwise identical to solving it alone with the same options.
+ * Returns RMB_OK if every solve succeeded, else the first failing status;
+ * per-system statuses are in infos[k].status (infos required). */
+rmb_status rmb_solve_batch(rmb_ctx ctx, int32_t count, const rmb_system *systems, const double *const *FT,
+                           const double *const *slip, double *const *U, double *const *lambda,
+                           const rmb_solve_opts *opts, rmb_solve_info *infos, rmb_stream stream);
+
+/* ---------------------------------------------------------------------------
+ * Continuous-batching server
+ * ------------------------------------------------------------------------- */
+
+typedef struct rmb_server_s *rmb_server;
+
+/* A request loop over one stream.  At most `max_active` systems run at once
+ * (0 -> 1024); admission is first-come first-served and by device-memory
+ * footprint within the context's budget. */
+rmb_status rmb_server_create(rmb_ctx ctx, int32_t max_active, rmb_stream stream, rmb_server *out);
+
+/* Queues one mobility problem.  The server copies `*sys` and its host
+ * body_off array; every device buffer it points to (pos, q, FT, slip, U,
+ * lambda) must stay valid until the request is returned by
+ * rmb_server_poll.  `tag` identifies the request in poll results.
+ * Errors: RMB_EINVAL (bad request), RMB_ENOMEM (the request can never fit
+ * the budget). */
+rmb_status rmb_server_submit(rmb_server srv, const rmb_system *sys, const double *FT, const double *slip,
+                             double *U, double *lambda, const rmb_solve_opts *opts, int64_t tag);
+
+/* Admits queued requests that fit, then advances every active request by
+ * one step (setup, an Arnoldi step, or a cycle's update and FP64 residual).
+ * Reports the number of active and queued requests.  Synchronises the
+ * server's stream once. */
+rmb_status rmb_server_step(rmb_server srv, int32_t *n_active, int32_t *n_queued);
+
+/* Returns up to max_out completed requests (tags and infos, host arrays)
+ * in completion order; *n_out receives the count. */
+rmb_status rmb_server_poll(rmb_server srv, int32_t max_out, int64_t *tags, rmb_solve_info *infos,
+                           int32_t *n_out);
+
+/* Destroys the server; requests still queued or active are abandoned. */
+void rmb_server_destroy(rmb_server srv);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,7 +28,9 @@ PREC_FP64, PREC_FP32_PAIRS = 0, 1
 
 # Exported symbols, as declared in include/rmb.h.
 EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
-           "rmb_mobility_matvec"]
+           "rmb_mobility_matvec", "rmb_precond_factor", "rmb_precond_apply", "rmb_precond_destroy",
+           "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
+           "rmb_server_step", "rmb_server_poll", "rmb_server_destroy"]
 
 
 class RmbError(RuntimeError):
@@ -41,6 +43,20 @@ class rmb_system(ctypes.Structure):
     _fields_ = [("n_blobs", ctypes.c_int64), ("n_bodies", ctypes.c_int64),
                 ("pos", ctypes.c_void_p), ("body_off", ctypes.c_void_p), ("q", ctypes.c_void_p),
                 ("a", ctypes.c_double), ("eta", ctypes.c_double), ("geometry", ctypes.c_int32)]
+
+
+class rmb_solve_opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("precision", ctypes.c_int32), ("restart", ctypes.c_int32),
+                ("max_iters", ctypes.c_int32), ("pad", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+
+
+class rmb_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
+                ("matvecs_fp64", ctypes.c_int32), ("matvecs_fp32", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
 
 
 _LIB = None
@@ -62,6 +78,20 @@ def library(path: str = LIB_PATH):
         L.rmb_last_error.restype = ctypes.c_char_p
         L.rmb_version.restype = ctypes.c_char_p
         L.rmb_mobility_matvec.argtypes = [vp, sysp, i32, vp, vp, vp]
+        optp, infop = ctypes.POINTER(rmb_solve_opts), ctypes.POINTER(rmb_solve_info)
+        L.rmb_precond_factor.argtypes = [vp, sysp, ctypes.POINTER(vp), vp]
+        L.rmb_precond_apply.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.rmb_precond_destroy.argtypes = [vp]
+        L.rmb_precond_destroy.restype = None
+        L.rmb_solve_mobility.argtypes = [vp, sysp, vp, vp, vp, vp, vp, optp, infop, vp]
+        L.rmb_solve_batch.argtypes = [vp, i32, sysp, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                      ctypes.POINTER(vp), ctypes.POINTER(vp), optp, infop, vp]
+        L.rmb_server_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
+        L.rmb_server_submit.argtypes = [vp, sysp, vp, vp, vp, vp, optp, i64]
+        L.rmb_server_step.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.rmb_server_poll.argtypes = [vp, i32, ctypes.POINTER(i64), infop, ctypes.POINTER(i32)]
+        L.rmb_server_destroy.argtypes = [vp]
+        L.rmb_server_destroy.restype = None
         _LIB = L
     return _LIB
 
@@ -155,3 +185,143 @@ def mobility_matvec(ctx: Context, system: System, lam: torch.Tensor, precision="
     ctx.check(ctx.lib.rmb_mobility_matvec(ctx.h, ctypes.byref(system.c), _prec(precision), lp, op,
                                           _stream(stream)))
     return out
+
+
+def solve_opts(tol=1e-8, precision="fp64", restart=100, max_iters=1000, inner_tol=1e-5):
+    return rmb_solve_opts(float(tol), _prec(precision), int(restart), int(max_iters), 0, float(inner_tol))
+
+
+def _vec(t, name, n):
+    if t is None:
+        return None
+    return _dev(t, name, (n, 3) if name in ("slip", "lambda") else (n, 6))
+
+
+class Precond:
+    """Block-diagonal preconditioner factors of one system (rmb_precond)."""
+
+    def __init__(self, ctx: Context, system: System, stream=None):
+        self.ctx, self.system = ctx, system
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rmb_precond_factor(ctx.h, ctypes.byref(system.c), ctypes.byref(h),
+                                             _stream(stream)))
+        self.h = h
+
+    def apply(self, rhs: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
+        """P^-1 applied to each row of rhs (nrhs, 3 Nb + 6 N)."""
+        n = 3 * self.system.n_blobs + 6 * self.system.n_bodies
+        if rhs.dim() == 1:
+            rhs = rhs.reshape(1, -1)
+        _dev(rhs, "rhs", (rhs.shape[0], n))
+        if out is None:
+            out = torch.empty_like(rhs)
+        _dev(out, "out", tuple(rhs.shape))
+        self.ctx.check(self.ctx.lib.rmb_precond_apply(self.ctx.h, self.h, rhs.shape[0],
+                                                      ctypes.c_void_p(rhs.data_ptr()),
+                                                      ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rmb_precond_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def solve_mobility(ctx: Context, system: System, FT: torch.Tensor, slip: torch.Tensor = None,
+                   precond: Precond = None, stream=None, raise_on_noconv=False, **opts):
+    """Mobility problem (eq:saddle_M) by preconditioned GMRES.  Returns
+    (U (N, 6), lambda (Nb, 3), info dict)."""
+    nb, N = system.n_blobs, system.n_bodies
+    FTp = _dev(FT, "FT", (N, 6))
+    sp = _vec(slip, "slip", nb)
+    U = torch.empty((N, 6), dtype=torch.float64, device=FT.device)
+    lam = torch.empty((nb, 3), dtype=torch.float64, device=FT.device)
+    o = solve_opts(**opts)
+    info = rmb_solve_info()
+    st = ctx.lib.rmb_solve_mobility(ctx.h, ctypes.byref(system.c), precond.h if precond else None, FTp, sp,
+                                    ctypes.c_void_p(U.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                    ctypes.byref(o), ctypes.byref(info), _stream(stream))
+    if st != RMB_OK and (st != RMB_ENOCONV or raise_on_noconv):
+        ctx.check(st)
+    return U, lam, info.as_dict()
+
+
+def solve_batch(ctx: Context, systems, FTs, slips=None, stream=None, **opts):
+    """Independent mobility problems solved together.  Returns a list of
+    (U, lambda, info) in input order; failed solves carry their status in
+    info['status']."""
+    k = len(systems)
+    arr = (rmb_system * k)(*[s.c for s in systems])
+    Us = [torch.empty((s.n_bodies, 6), dtype=torch.float64, device=FTs[i].device) for i, s in enumerate(systems)]
+    Ls = [torch.empty((s.n_blobs, 3), dtype=torch.float64, device=FTs[i].device) for i, s in enumerate(systems)]
+    vp = ctypes.c_void_p
+    FTa = (vp * k)(*[_dev(FTs[i], "FT", (s.n_bodies, 6)).value for i, s in enumerate(systems)])
+    Sa = None
+    if slips is not None:
+        Sa = (vp * k)(*[None if slips[i] is None else _dev(slips[i], "slip", (s.n_blobs, 3)).value
+                        for i, s in enumerate(systems)])
+    Ua = (vp * k)(*[u.data_ptr() for u in Us])
+    La = (vp * k)(*[l.data_ptr() for l in Ls])
+    infos = (rmb_solve_info * k)()
+    o = solve_opts(**opts)
+    st = ctx.lib.rmb_solve_batch(ctx.h, k, arr, FTa, Sa, Ua, La, ctypes.byref(o), infos, _stream(stream))
+    if st not in (RMB_OK, RMB_ENOCONV, RMB_ENOTSPD, RMB_EINVAL):
+        ctx.check(st)
+    return [(Us[i], Ls[i], infos[i].as_dict()) for i in range(k)]
+
+
+class Server:
+    """Continuous-batching request loop (rmb_server).  Keeps each request's
+    tensors alive until it is polled."""
+
+    def __init__(self, ctx: Context, max_active: int = 0, stream=None):
+        self.ctx = ctx
+        self.stream = stream
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rmb_server_create(ctx.h, max_active, _stream(stream), ctypes.byref(h)))
+        self.h = h
+        self.live = {}
+
+    def submit(self, tag: int, system: System, FT: torch.Tensor, slip: torch.Tensor = None, **opts):
+        nb, N = system.n_blobs, system.n_bodies
+        U = torch.empty((N, 6), dtype=torch.float64, device=FT.device)
+        lam = torch.empty((nb, 3), dtype=torch.float64, device=FT.device)
+        o = solve_opts(**opts)
+        self.ctx.check(self.ctx.lib.rmb_server_submit(self.h, ctypes.byref(system.c), _dev(FT, "FT", (N, 6)),
+                                                      _vec(slip, "slip", nb), ctypes.c_void_p(U.data_ptr()),
+                                                      ctypes.c_void_p(lam.data_ptr()), ctypes.byref(o), int(tag)))
+        self.live[int(tag)] = (system, FT, slip, U, lam)
+
+    def step(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.rmb_server_step(self.h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def poll(self, max_out: int = 1024):
+        tags = (ctypes.c_int64 * max_out)()
+        infos = (rmb_solve_info * max_out)()
+        n = ctypes.c_int32()
+        self.ctx.check(self.ctx.lib.rmb_server_poll(self.h, max_out, tags, infos, ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            t = int(tags[i])
+            system, FT, slip, U, lam = self.live.pop(t)
+            out.append((t, U, lam, infos[i].as_dict()))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.ctx.lib.rmb_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,109 @@
+// Per-body and Krylov kernel interfaces (internal).
+#pragma once
+
+#include "rmb_common.h"
+
+namespace rmb {
+
+// Largest 3n x 3n block handled by the LDS-resident per-body path.
+constexpr int kSmallBodyMaxM = 84;  // 28 blobs: build workspace (m^2 + 6m + 36 doubles) stays under 64 KiB of LDS
+
+// One body of one system, for preconditioner build and apply.
+struct BodyWork {
+    const double *pos;  // system's blob positions [nb][3]
+    const double *q;    // this body's tracking point (3 doubles)
+    double *factor;     // L (m x m, row-major lower), Y (m x 6), Sc (6 x 6)
+    int64_t blob0;      // first blob of the body
+    int32_t n_blobs;
+    int32_t body;       // body index within its system
+    int32_t wall;
+    int32_t pad;
+    double a, pref;     // blob radius, 1/(6 pi eta a)
+    int *flag;          // build status of the body's system (bits 4: not SPD, 8: singular)
+};
+
+inline int64_t factor_doubles(int64_t n_blobs) {
+    const int64_t m = 3 * n_blobs;
+    return m * m + 6 * m + 36;
+}
+
+// P^-1 applied to `nrhs` saddle vectors of one system (vector r at in + r*ld).
+struct PrecondApplyJob {
+    const BodyWork *items;  // the system's bodies
+    const double *in;
+    double *out;
+    int64_t ld;             // stride between right-hand sides
+    int64_t nb3;            // 3 * n_blobs (offset of the U block)
+    int64_t wg_begin;       // first workgroup of this system in the launch
+    int32_t n_items;
+    int32_t nrhs;
+};
+
+// Saddle-point operator rows around a finished pair product.
+struct SaddleJob {
+    const double *pos;
+    const double *q;
+    const int64_t *body_off;  // device [N+1]
+    const int32_t *blob_body; // device [nb]
+    const double *partial;    // [n_split][nb][3] pair sums
+    const double *x;          // input [lambda; U] (only U read for blob rows, lambda for body rows)
+    const double *b;          // NULL: y = A x; else y = b - A x
+    double *y;
+    int64_t nb;
+    int64_t blk_begin;        // first blob-row workgroup of this system
+    int64_t body_begin;       // first body-row workgroup of this system
+    int32_t n_split;
+    int32_t pad;
+    double pref;
+};
+
+hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s);
+hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
+                                      int32_t max_rhs, int max_m, hipStream_t s);
+hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_blocks, int64_t n_bodies,
+                         hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Krylov vector kernels
+// ---------------------------------------------------------------------------
+
+constexpr int kSeg = 2048;  // vector elements per workgroup (256 threads x 8)
+
+struct KrylovJob {
+    double *V;          // basis vectors, vector k at V + k*ldv
+    int64_t ldv;
+    double *w;          // vector being orthogonalised / normalised / combined into
+    double *vnext;      // normalised output (V + kk*ldv)
+    double *P1, *P2;    // partial dots [(kmax+1) x n_seg]
+    double *P3;         // partial squared norms [n_seg]
+    double *hcol;       // output: h[0..kk-1] then the norm at hcol[kk]
+    const double *coef; // combine coefficients (kk of them)
+    double *x;          // axpy target
+    const double *t;    // axpy source
+    int64_t n;
+    int64_t wg_begin;
+    int32_t n_seg;
+    int32_t kk;
+};
+
+// CGS2 orthogonalisation of w against V[0..kk-1] and normalisation into
+// vnext, writing hcol; kk = 0 normalises w alone.  Four launches.
+hipError_t launch_orthogonalise(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+// w = sum_{k<kk} coef[k] V[k]
+hipError_t launch_combine(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+// x += t
+hipError_t launch_axpy(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+// ||w||^2 partials then hcol[0] = ||w|| (no normalisation)
+hipError_t launch_norm(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// misc per-system kernels
+// ---------------------------------------------------------------------------
+
+// b = [slip or 0 ; -F]
+hipError_t launch_build_rhs(const double *FT, const double *slip, int64_t nb, int64_t N, double *b,
+                            hipStream_t s);
+// blob_body[i] = p for i in [off[p], off[p+1])
+hipError_t launch_blob_body(const int64_t *off, int64_t N, int32_t *blob_body, hipStream_t s);
+
+}  // namespace rmb

@@ -1,0 +1,367 @@
+// Per-body kernels: rigid kinematics K, K^T (eq:noslip_rigid,
+// eq:rigidSystem), the saddle-point operator's assembly (eq:saddle_M), and
+// the indefinite block-diagonal preconditioner (eq:M_tilde_block_diag,
+// eq:indef_block_P, eq:saddle_M_precon) for bodies small enough that a
+// body's 3n x 3n mobility block fits in LDS.
+//
+// Preconditioner of body p (m = 3 n_p):
+//   M_pp = L L^T,  Y = L^-1 K_p (m x 6),  S = Y^T Y = K_p^T M_pp^-1 K_p = Sc Sc^T
+// and for a right-hand side (s_p, bottom_p) with F_p = -bottom_p:
+//   t = L^-1 s,  U = S^-1 (F - Y^T t),  lambda = L^-T (t + Y U).
+#include <cmath>
+
+#include "rmb_body.h"
+
+namespace rmb {
+
+// ---------------------------------------------------------------------------
+// 3x3 pair block in FP64 (assembly of per-body blocks)
+// ---------------------------------------------------------------------------
+
+// M_ij without the 1/(6 pi eta a) prefactor; row = velocity of i, column =
+// force on j.  Same formulas as the pair kernels (eq:RPYTensor plus the
+// wall image correction).
+__device__ void pair_block_f64(const double ri[3], const double rj[3], double a, bool wall,
+                               double B[9]) {
+    const double rx = ri[0] - rj[0], ry = ri[1] - rj[1], rz = ri[2] - rj[2];
+    const double d2 = rx * rx + ry * ry + rz * rz;
+    const double d = sqrt(d2);
+    double ciso, crr;  // crr multiplies r r^T (already divided by d^2)
+    if (d > 2.0 * a) {
+        const double t = a / d, t2 = t * t;
+        ciso = t * (0.75 + 0.5 * t2);
+        crr = t * (0.75 - 1.5 * t2) / d2;
+    } else {
+        ciso = 1.0 - 9.0 * d / (32.0 * a);
+        crr = d > 0.0 ? 3.0 / (32.0 * a * d) : 0.0;
+    }
+    const double r[3] = {rx, ry, rz};
+    for (int p = 0; p < 3; ++p)
+        for (int q = 0; q < 3; ++q) B[3 * p + q] = (p == q ? ciso : 0.0) + crr * r[p] * r[q];
+    if (wall) {
+        const double R[3] = {rx, ry, ri[2] + rj[2]};
+        const double L = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
+        const double e[3] = {R[0] / L, R[1] / L, R[2] / L};
+        const double xw = a / L, hh = rj[2] / L, ez = e[2];
+        const double xw2 = xw * xw, xw4 = xw2 * xw2, ez2 = ez * ez;
+        const double T = hh * hh - ez * hh;
+        const double c1 = 0.25 * xw * (-3.0 + 6.0 * T + xw2 * (6.0 * ez2 - 2.0) + xw4 * (2.0 - 10.0 * ez2));
+        const double c2 = 0.25 * xw * (-3.0 - 18.0 * T + xw2 * (6.0 - 30.0 * ez2) + xw4 * (70.0 * ez2 - 10.0));
+        const double c3 = xw * (1.5 * hh * (1.0 - 6.0 * ez2 + 6.0 * ez * hh) +
+                                ez * (xw2 * (15.0 * ez2 - 3.0) + xw4 * (10.0 - 35.0 * ez2)));
+        const double c4 = xw * (1.5 * hh - 5.0 * ez * xw4);
+        const double c5 = xw * (-3.0 * (hh * hh + ez2 * xw2) + xw4 * (15.0 * ez2 - 2.0));
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q)
+                B[3 * p + q] += (p == q ? c1 : 0.0) + c2 * e[p] * e[q] + (q == 2 ? c3 * e[p] : 0.0) +
+                                (p == 2 ? c4 * e[q] : 0.0) + (p == 2 && q == 2 ? c5 : 0.0);
+    }
+}
+
+// K_p row block of blob i: velocity of blob i per unit body motion U_p,
+// K[c][k] for c in 0..2 (velocity component), k in 0..5 (u then omega):
+// u_c + (omega x d)_c with d = r_i - q_p.
+__device__ __forceinline__ double K_entry(const double d[3], int c, int k) {
+    if (k < 3) return c == k ? 1.0 : 0.0;
+    // (omega x d)_c = eps_{c,l,m} omega_l d_m ; derivative w.r.t. omega_l (l = k-3)
+    const int l = k - 3;
+    if (c == l) return 0.0;
+    const int m = 3 - c - l;
+    const double sgn = ((l - c + 3) % 3 == 1) ? 1.0 : -1.0;  // eps_{c,l,m}
+    return sgn * d[m];
+}
+
+// ---------------------------------------------------------------------------
+// small-body preconditioner: build
+// ---------------------------------------------------------------------------
+
+// One workgroup (one wave) per body; the body's block lives in LDS.
+__global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork *__restrict__ items,
+                                                                 int32_t n_items) {
+    extern __shared__ double lds[];
+    const BodyWork it = items[blockIdx.x];
+    const int n = it.n_blobs, m = 3 * n, tid = threadIdx.x;
+    double *A = lds;              // m x m, row-major
+    double *Y = A + m * m;        // m x 6
+    double *S = Y + 6 * m;        // 6 x 6
+    __shared__ int bad;
+    if (tid == 0) bad = 0;
+
+    // 1. assemble M_pp (with prefactor)
+    for (int pq = tid; pq < n * n; pq += blockDim.x) {
+        const int i = pq / n, j = pq % n;
+        const double *ri = it.pos + 3 * (int64_t)(it.blob0 + i);
+        const double *rj = it.pos + 3 * (int64_t)(it.blob0 + j);
+        double B[9];
+        const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
+        pair_block_f64(a_i, a_j, it.a, it.wall != 0, B);
+        for (int p = 0; p < 3; ++p)
+            for (int q = 0; q < 3; ++q) A[(3 * i + p) * m + 3 * j + q] = it.pref * B[3 * p + q];
+    }
+    __syncthreads();
+
+    // 2. right-looking Cholesky, lower triangle, in place
+    for (int j = 0; j < m; ++j) {
+        if (tid == 0) {
+            const double dj = A[j * m + j];
+            if (!(dj > 0.0)) bad = 1;
+            A[j * m + j] = sqrt(dj > 0.0 ? dj : 1.0);
+        }
+        __syncthreads();
+        const double ljj = A[j * m + j];
+        for (int i = j + 1 + tid; i < m; i += blockDim.x) A[i * m + j] /= ljj;
+        __syncthreads();
+        const int r = m - j - 1;  // trailing size
+        for (int e = tid; e < r * r; e += blockDim.x) {
+            const int i = j + 1 + e / r, k = j + 1 + e % r;
+            if (k <= i) A[i * m + k] -= A[i * m + j] * A[k * m + j];
+        }
+        __syncthreads();
+    }
+
+    // 3. Y = L^-1 K_p (forward substitution, 6 right-hand sides)
+    const double *q = it.q;
+    for (int e = tid; e < 6 * m; e += blockDim.x) {
+        const int row = e / 6, k = e % 6;
+        const int i = row / 3, c = row % 3;
+        const double *ri = it.pos + 3 * (int64_t)(it.blob0 + i);
+        const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
+        Y[row * 6 + k] = K_entry(d, c, k);
+    }
+    __syncthreads();
+    for (int l = 0; l < m; ++l) {
+        if (tid < 6) Y[l * 6 + tid] /= A[l * m + l];
+        __syncthreads();
+        const int r = m - l - 1;
+        for (int e = tid; e < 6 * r; e += blockDim.x) {
+            const int row = l + 1 + e / 6, k = e % 6;
+            Y[row * 6 + k] -= A[row * m + l] * Y[l * 6 + k];
+        }
+        __syncthreads();
+    }
+
+    // 4. S = Y^T Y, then its Cholesky factor (6 x 6)
+    if (tid < 36) {
+        const int r = tid / 6, c = tid % 6;
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += Y[l * 6 + r] * Y[l * 6 + c];
+        S[tid] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int j = 0; j < 6; ++j) {
+            double dj = S[j * 6 + j];
+            for (int k = 0; k < j; ++k) dj -= S[j * 6 + k] * S[j * 6 + k];
+            if (!(dj > 0.0)) {
+                bad |= 2;
+                dj = 1.0;
+            }
+            const double ljj = sqrt(dj);
+            S[j * 6 + j] = ljj;
+            for (int i = j + 1; i < 6; ++i) {
+                double v = S[i * 6 + j];
+                for (int k = 0; k < j; ++k) v -= S[i * 6 + k] * S[j * 6 + k];
+                S[i * 6 + j] = v / ljj;
+            }
+        }
+    }
+    __syncthreads();
+
+    // 5. store L (lower, row-major m x m), Y, Sc
+    double *out = it.factor;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+        const int i = e / m, k = e % m;
+        out[e] = k <= i ? A[e] : 0.0;
+    }
+    for (int e = tid; e < 6 * m; e += blockDim.x) out[m * m + e] = Y[e];
+    for (int e = tid; e < 36; e += blockDim.x) {
+        const int i = e / 6, k = e % 6;
+        out[m * m + 6 * m + e] = k <= i ? S[e] : 0.0;
+    }
+    // bit 4: M_pp not positive definite; bit 8: K_p^T M_pp^-1 K_p singular
+    if (tid == 0 && bad) atomicOr(it.flag, ((bad & 1) ? 4 : 0) | ((bad & 2) ? 8 : 0));
+}
+
+// ---------------------------------------------------------------------------
+// small-body preconditioner: apply (grid.y = right-hand side)
+// ---------------------------------------------------------------------------
+
+// Solves one body's [M_pp -K_p; -K_p^T 0][lambda; U] = [s; bottom] with the
+// body's L staged in LDS (lds: m*m doubles of L, then m doubles of t).
+__device__ void precond_body_apply(const BodyWork &it, const double *__restrict__ s_in,
+                                   const double *__restrict__ bot_in, double *__restrict__ lam_out,
+                                   double *__restrict__ U_out, double *lds, double *g) {
+    const int m = 3 * it.n_blobs, tid = threadIdx.x;
+    const double *fac = it.factor;
+    const double *Y = fac + m * m, *Sc = fac + m * m + 6 * m;
+    double *L = lds, *t = lds + m * m;
+    for (int e = tid; e < m * m; e += blockDim.x) L[e] = fac[e];
+    for (int e = tid; e < m; e += blockDim.x) t[e] = s_in[e];
+    __syncthreads();
+    // t = L^-1 s (column-oriented forward substitution)
+    for (int l = 0; l < m; ++l) {
+        const double tl = t[l] / L[l * m + l];
+        for (int r = l + 1 + tid; r < m; r += blockDim.x) t[r] -= L[r * m + l] * tl;
+        __syncthreads();
+        if (tid == 0) t[l] = tl;
+    }
+    __syncthreads();
+    // g = F - Y^T t, F = -bottom
+    if (tid < 6) {
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += Y[l * 6 + tid] * t[l];
+        g[tid] = -bot_in[tid] - acc;
+    }
+    __syncthreads();
+    // U = Sc^-T Sc^-1 g
+    if (tid == 0) {
+        double u[6];
+        for (int i = 0; i < 6; ++i) {
+            double v = g[i];
+            for (int k = 0; k < i; ++k) v -= Sc[i * 6 + k] * u[k];
+            u[i] = v / Sc[i * 6 + i];
+        }
+        for (int i = 5; i >= 0; --i) {
+            double v = u[i];
+            for (int k = i + 1; k < 6; ++k) v -= Sc[k * 6 + i] * g[k];
+            g[i] = v / Sc[i * 6 + i];
+        }
+    }
+    __syncthreads();
+    // w = t + Y U, then lambda = L^-T w (row-oriented backward substitution)
+    for (int e = tid; e < m; e += blockDim.x) {
+        double acc = t[e];
+        for (int k = 0; k < 6; ++k) acc += Y[e * 6 + k] * g[k];
+        t[e] = acc;
+    }
+    __syncthreads();
+    for (int l = m - 1; l >= 0; --l) {
+        const double tl = t[l] / L[l * m + l];
+        for (int r = tid; r < l; r += blockDim.x) t[r] -= L[l * m + r] * tl;
+        __syncthreads();
+        if (tid == 0) t[l] = tl;
+    }
+    __syncthreads();
+    for (int e = tid; e < m; e += blockDim.x) lam_out[e] = t[e];
+    if (tid < 6) U_out[tid] = g[tid];
+}
+
+__global__ __launch_bounds__(64) void precond_apply_small_kernel(const PrecondApplyJob *__restrict__ jobs,
+                                                                 int32_t n_jobs) {
+    extern __shared__ double lds[];
+    __shared__ double g[6];
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const PrecondApplyJob &J = jobs[lo];
+    const int64_t rhs = blockIdx.y;
+    if (rhs >= J.nrhs) return;
+    const BodyWork it = J.items[w - J.wg_begin];
+    const double *in = J.in + rhs * J.ld;
+    double *out = J.out + rhs * J.ld;
+    const int64_t b3 = 3 * it.blob0;
+    const int64_t u6 = J.nb3 + 6 * (int64_t)it.body;
+    precond_body_apply(it, in + b3, in + u6, out + b3, out + u6, lds, g);
+}
+
+// ---------------------------------------------------------------------------
+// saddle-point operator around the pair product
+// ---------------------------------------------------------------------------
+
+// Blob rows: y_lambda[i] = pref * sum_s partial[s][i] - (u_p + omega_p x (r_i - q_p)),
+// or with `resid`, r_lambda[i] = b_lambda[i] - y_lambda[i].
+__global__ void saddle_blob_kernel(const SaddleJob *__restrict__ jobs, int32_t n_jobs) {
+    // one workgroup covers 256 blobs of one job; job located by prefix
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].blk_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const SaddleJob &J = jobs[lo];
+    const int64_t i = (w - J.blk_begin) * 256 + threadIdx.x;
+    if (i >= J.nb) return;
+    double v[3] = {0.0, 0.0, 0.0};
+    const int64_t n3 = 3 * J.nb;
+    for (int32_t s = 0; s < J.n_split; ++s) {
+        const double *p = J.partial + s * n3 + 3 * i;
+        v[0] += p[0];
+        v[1] += p[1];
+        v[2] += p[2];
+    }
+    const int p = J.blob_body[i];
+    const double *U = J.x + n3 + 6 * (int64_t)p;
+    const double *q = J.q + 3 * (int64_t)p;
+    const double d[3] = {J.pos[3 * i] - q[0], J.pos[3 * i + 1] - q[1], J.pos[3 * i + 2] - q[2]};
+    const double ku[3] = {U[0] + U[4] * d[2] - U[5] * d[1], U[1] + U[5] * d[0] - U[3] * d[2],
+                          U[2] + U[3] * d[1] - U[4] * d[0]};
+    for (int c = 0; c < 3; ++c) {
+        const double y = J.pref * v[c] - ku[c];
+        J.y[3 * i + c] = J.b ? J.b[3 * i + c] - y : y;
+    }
+}
+
+// Body rows: y_U[p] = -(sum_i lambda_i, sum_i (r_i - q_p) x lambda_i), or the
+// residual b_U - y_U.  One wave per body.
+__global__ void saddle_body_kernel(const SaddleJob *__restrict__ jobs, int32_t n_jobs) {
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].body_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const SaddleJob &J = jobs[lo];
+    const int64_t p = w - J.body_begin;
+    const int64_t b0 = J.body_off[p], b1 = J.body_off[p + 1];
+    const double *q = J.q + 3 * p;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 64) {
+        const double l[3] = {J.x[3 * i], J.x[3 * i + 1], J.x[3 * i + 2]};
+        const double d[3] = {J.pos[3 * i] - q[0], J.pos[3 * i + 1] - q[1], J.pos[3 * i + 2] - q[2]};
+        acc[0] += l[0];
+        acc[1] += l[1];
+        acc[2] += l[2];
+        acc[3] += d[1] * l[2] - d[2] * l[1];
+        acc[4] += d[2] * l[0] - d[0] * l[2];
+        acc[5] += d[0] * l[1] - d[1] * l[0];
+    }
+    for (int k = 0; k < 6; ++k) {
+        double v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[k] = v;
+    }
+    if (threadIdx.x == 0) {
+        const int64_t o = 3 * J.nb + 6 * p;
+        for (int k = 0; k < 6; ++k) J.y[o + k] = J.b ? J.b[o + k] + acc[k] : -acc[k];
+    }
+}
+
+hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s) {
+    if (n_items <= 0) return hipSuccess;
+    size_t lds = ((size_t)max_m * max_m + 6 * (size_t)max_m + 36) * sizeof(double);
+    hipLaunchKernelGGL(precond_build_small_kernel, dim3(n_items), dim3(64), lds, s, items, n_items);
+    return hipGetLastError();
+}
+
+hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
+                                      int32_t max_rhs, int max_m, hipStream_t s) {
+    if (n_wg <= 0 || max_rhs <= 0) return hipSuccess;
+    size_t lds = ((size_t)max_m * max_m + max_m) * sizeof(double);
+    hipLaunchKernelGGL(precond_apply_small_kernel, dim3((unsigned)n_wg, max_rhs), dim3(64), lds, s, jobs,
+                       n_jobs);
+    return hipGetLastError();
+}
+
+hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_blocks, int64_t n_bodies,
+                         hipStream_t s) {
+    if (n_blob_blocks > 0)
+        hipLaunchKernelGGL(saddle_blob_kernel, dim3((unsigned)n_blob_blocks), dim3(256), 0, s, jobs, n_jobs);
+    if (n_bodies > 0)
+        hipLaunchKernelGGL(saddle_body_kernel, dim3((unsigned)n_bodies), dim3(64), 0, s, jobs, n_jobs);
+    return hipGetLastError();
+}
+
+}  // namespace rmb

@@ -59,7 +59,19 @@ void split_plan(int64_t nb, int32_t *n_split, int64_t *chunk, int32_t *n_tblock)
 void pair_job_init(PairJob *J, const double *tpos, const void *src, double *partial, int64_t nb,
                    double a);
 
+// Packing of source records for several systems in one launch.
+struct PackJob {
+    const double *pos;
+    const double *lam;  // lambda part of the operand (first 3 nb entries)
+    void *src;
+    int64_t nb;
+    int64_t wg_begin;   // first 256-blob workgroup of this system
+    int32_t precision;
+    int32_t pad;
+};
+
 // Kernel launchers (rmb_pair.hip).
+hipError_t launch_pack_table(const PackJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
 hipError_t launch_pack_sources(int precision, const double *pos, const double *lam, int64_t nb,
                                void *src, hipStream_t s);
 // jobs: device array of n_jobs PairJob with increasing tile_begin; n_tiles is

@@ -1,0 +1,844 @@
+// Solve engine: right-preconditioned GMRES on the saddle-point system
+// (eq:saddle_M) with the block-diagonal preconditioner (eq:indef_block_P),
+// optional FP32-pair inner cycles inside FP64 iterative refinement, and
+// continuous batching of independent systems.
+//
+// Every admitted system is a state machine advanced once per tick:
+//   SETUP  -> build b = [slip; -F], the preconditioner, and normalise b
+//   ITER   -> z = P^-1 v_k, w = A z, CGS2 against V[0..k], v_{k+1} = w/|w|
+//   FINISH -> x += P^-1 (V y), then r = b - A_64 x (FP64) and normalise r
+// A tick launches each kernel once for all systems that need it (tables of
+// per-system descriptors, one upload), copies every system's small results
+// back in one download, and synchronises the stream once.  The host then
+// applies Givens rotations, tests convergence and chooses each system's
+// next step.  A system's arithmetic never depends on which other systems
+// share a tick: tilings and reduction orders are functions of its own sizes.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <memory>
+
+#include "rmb_body.h"
+#include "rmb_ctx.h"
+
+using namespace rmb;
+
+struct rmb_precond_s {
+    rmb_ctx ctx = nullptr;
+    int64_t nb = 0, N = 0;
+    int max_m = 0;
+    char *dbuf = nullptr;
+    BodyWork *items_d = nullptr;
+    double *factor = nullptr;
+    int *flag_d = nullptr;
+};
+
+namespace rmb {
+
+static double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+static size_t al(size_t x) { return (x + 255) / 256 * 256; }
+
+// Host-side description of a system's bodies: factor offsets and sizes.
+static void body_items(const rmb_system &sys, const int64_t *off, double *factor, int *flag,
+                       std::vector<BodyWork> &items, int *max_m) {
+    items.resize(sys.n_bodies);
+    int64_t fo = 0;
+    *max_m = 0;
+    const double pref = mobility_prefactor(sys.a, sys.eta);
+    for (int64_t p = 0; p < sys.n_bodies; ++p) {
+        BodyWork &b = items[p];
+        b.pos = sys.pos;
+        b.q = sys.q + 3 * p;
+        b.factor = factor ? factor + fo : nullptr;
+        b.blob0 = off[p];
+        b.n_blobs = (int32_t)(off[p + 1] - off[p]);
+        b.body = (int32_t)p;
+        b.wall = sys.geometry == RMB_GEOM_WALL;
+        b.pad = 0;
+        b.a = sys.a;
+        b.pref = pref;
+        b.flag = flag;
+        fo += factor_doubles(b.n_blobs);
+        *max_m = std::max(*max_m, 3 * b.n_blobs);
+    }
+}
+
+static int64_t factor_total(const int64_t *off, int64_t N) {
+    int64_t t = 0;
+    for (int64_t p = 0; p < N; ++p) t += factor_doubles(off[p + 1] - off[p]);
+    return t;
+}
+
+static rmb_status check_body_sizes(rmb_ctx ctx, const int64_t *off, int64_t N) {
+    for (int64_t p = 0; p < N; ++p)
+        if (3 * (off[p + 1] - off[p]) > kSmallBodyMaxM)
+            return fail(ctx, RMB_EINVAL, "body %lld has %lld blobs; bodies above %d blobs are not supported yet",
+                        (long long)p, (long long)(off[p + 1] - off[p]), kSmallBodyMaxM / 3);
+    return RMB_OK;
+}
+
+// ---------------------------------------------------------------------------
+
+enum Phase { SETUP, START, ITER, FINISH, RESID, DONE };
+
+struct Job {
+    // request
+    int64_t tag = 0;
+    rmb_system sys{};
+    std::vector<int64_t> off;
+    const double *FT = nullptr, *slip = nullptr;
+    double *U_out = nullptr, *lam_out = nullptr;
+    double tol = 1e-8, inner_tol = 1e-5;
+    int prec = RMB_PREC_FP64, m = 100, max_iters = 1000;
+    rmb_precond pc = nullptr;  // external factors (not owned) or null
+    // sizes
+    int64_t nb = 0, N = 0, n = 0, ldv = 0, nseg = 0;
+    PairJob pj{};
+    int max_m = 0;
+    size_t bytes = 0;
+    // device
+    char *dbuf = nullptr;
+    int64_t *off_d = nullptr;
+    int32_t *blob_body = nullptr;
+    void *src = nullptr;
+    double *partial = nullptr, *factor = nullptr;
+    BodyWork *items_d = nullptr;
+    double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *V = nullptr;
+    double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
+    int slot = -1;
+    std::vector<BodyWork> items_h;
+    // state
+    Phase phase = SETUP;
+    int k = 0, iters = 0, cycles = 0, mv64 = 0, mv32 = 0;
+    double bnorm = 0, rel = 1, target = 0;
+    bool cycle_fp32 = false;
+    std::vector<double> R, cs, sn, g, y;
+    rmb_status status = RMB_OK;
+    std::string msg;
+    double t_admit = 0, t_done = 0;
+};
+
+static size_t job_bytes(Job &J) {
+    const int64_t nb = J.nb, N = J.N, n = J.n;
+    size_t t = 0;
+    t += al((N + 1) * 8) + al(nb * 4) + al(nb * sizeof(SrcF64)) + al((size_t)J.pj.n_split * nb * 24);
+    t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
+    t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8);
+    if (!J.pc) t += al(factor_total(J.off.data(), N) * 8) + al(N * sizeof(BodyWork));
+    return t;
+}
+
+static void job_carve(Job &J) {
+    char *p = J.dbuf;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += al(bytes);
+        return r;
+    };
+    const int64_t nb = J.nb, N = J.N, n = J.n;
+    J.off_d = (int64_t *)take((N + 1) * 8);
+    J.blob_body = (int32_t *)take(nb * 4);
+    J.src = take(nb * sizeof(SrcF64));
+    J.partial = (double *)take((size_t)J.pj.n_split * nb * 24);
+    J.x = (double *)take(n * 8);
+    J.b = (double *)take(n * 8);
+    J.w = (double *)take(n * 8);
+    J.z = (double *)take(n * 8);
+    J.V = (double *)take((size_t)(J.m + 1) * J.ldv * 8);
+    J.P1 = (double *)take((size_t)(J.m + 1) * J.nseg * 8);
+    J.P2 = (double *)take((size_t)(J.m + 1) * J.nseg * 8);
+    J.P3 = (double *)take(J.nseg * 8);
+    if (!J.pc) {
+        J.factor = (double *)take(factor_total(J.off.data(), N) * 8);
+        J.items_d = (BodyWork *)take(N * sizeof(BodyWork));
+    } else {
+        J.factor = J.pc->factor;
+        J.items_d = J.pc->items_d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+
+// Host staging of one tick's descriptor tables (pinned), uploaded at once.
+struct Staging {
+    std::vector<char> host;
+    size_t used = 0;
+    size_t put(const void *p, size_t bytes) {
+        size_t o = (used + 255) / 256 * 256;
+        if (host.size() < o + bytes) host.resize(std::max(o + bytes, host.size() * 2 + 4096));
+        memcpy(host.data() + o, p, bytes);
+        used = o + bytes;
+        return o;
+    }
+    void reset() { used = 0; }
+};
+
+struct Engine {
+    rmb_ctx ctx;
+    hipStream_t s;
+    int max_active;
+    std::deque<Job *> queue;
+    std::vector<Job *> active;
+    std::deque<Job *> done;
+    // mailbox: per slot, [flag word][hcol: restart + 2 doubles]
+    static constexpr int kSlot = 260;
+    double *mbox_d = nullptr, *mbox_h = nullptr;
+    std::vector<int> free_slots;
+    // staging
+    Staging st;
+    char *stage_h = nullptr, *stage_d = nullptr;
+    size_t stage_cap = 0;
+
+    Engine(rmb_ctx c, hipStream_t st_, int maxa) : ctx(c), s(st_), max_active(maxa) {}
+    ~Engine() {
+        (void)hipStreamSynchronize(s);
+        for (Job *j : active) release(j), delete j;
+        for (Job *j : queue) delete j;
+        for (Job *j : done) delete j;
+        if (mbox_d) ctx->arena->free(mbox_d);
+        if (mbox_h) (void)hipHostFree(mbox_h);
+        if (stage_d) ctx->arena->free(stage_d);
+        if (stage_h) (void)hipHostFree(stage_h);
+    }
+
+    rmb_status init() {
+        mbox_d = (double *)ctx->arena->alloc((size_t)max_active * kSlot * 8);
+        if (!mbox_d) return fail(ctx, RMB_ENOMEM, "server mailbox does not fit the budget");
+        RMB_HIP(ctx, hipHostMalloc(&mbox_h, (size_t)max_active * kSlot * 8, hipHostMallocDefault));
+        for (int i = max_active - 1; i >= 0; --i) free_slots.push_back(i);
+        return RMB_OK;
+    }
+
+    int *flag_d(Job *j) { return (int *)(mbox_d + (size_t)j->slot * kSlot); }
+    int flag_h(Job *j) { return *(int *)(mbox_h + (size_t)j->slot * kSlot); }
+    double *hcol_d(Job *j) { return mbox_d + (size_t)j->slot * kSlot + 1; }
+    double *hcol_h(Job *j) { return mbox_h + (size_t)j->slot * kSlot + 1; }
+
+    void release(Job *j) {
+        if (j->dbuf) ctx->arena->free(j->dbuf);
+        j->dbuf = nullptr;
+        if (j->slot >= 0) free_slots.push_back(j->slot);
+        j->slot = -1;
+    }
+
+    rmb_status submit(const rmb_system *sys, const double *FT, const double *slip, double *U, double *lam,
+                      const rmb_solve_opts *o, rmb_precond pc, int64_t tag, Job **out) {
+        RMB_TRY(check_system(ctx, sys, true));
+        if (!FT || !U || !lam) return fail(ctx, RMB_EINVAL, "FT, U and lambda are required");
+        RMB_TRY(check_body_sizes(ctx, sys->body_off, sys->n_bodies));
+        auto J = std::make_unique<Job>();
+        J->tag = tag;
+        J->sys = *sys;
+        J->off.assign(sys->body_off, sys->body_off + sys->n_bodies + 1);
+        J->sys.body_off = J->off.data();
+        J->FT = FT, J->slip = slip, J->U_out = U, J->lam_out = lam;
+        if (o) {
+            if (o->tol < 0 || o->inner_tol < 0 || o->restart < 0 || o->restart > 255 || o->max_iters < 0)
+                return fail(ctx, RMB_EINVAL, "bad solve options");
+            if (o->precision != RMB_PREC_FP64 && o->precision != RMB_PREC_FP32_PAIRS)
+                return fail(ctx, RMB_EINVAL, "unknown precision %d", o->precision);
+            if (o->tol > 0) J->tol = o->tol;
+            if (o->inner_tol > 0) J->inner_tol = o->inner_tol;
+            if (o->restart > 0) J->m = o->restart;
+            if (o->max_iters > 0) J->max_iters = o->max_iters;
+            J->prec = o->precision;
+        }
+        if (pc) {
+            if (pc->nb != sys->n_blobs || pc->N != sys->n_bodies)
+                return fail(ctx, RMB_EINVAL, "preconditioner was built for a different system");
+            J->pc = pc;
+        }
+        J->nb = sys->n_blobs, J->N = sys->n_bodies;
+        J->n = 3 * J->nb + 6 * J->N;
+        J->ldv = (J->n + 31) / 32 * 32;
+        J->nseg = (J->n + kSeg - 1) / kSeg;
+        pair_job_init(&J->pj, sys->pos, nullptr, nullptr, J->nb, sys->a);
+        J->bytes = job_bytes(*J);
+        if (J->bytes > ctx->arena->budget())
+            return fail(ctx, RMB_ENOMEM, "request needs %zu bytes of device memory, budget is %zu", J->bytes,
+                        ctx->arena->budget());
+        *out = J.get();
+        queue.push_back(J.release());
+        return RMB_OK;
+    }
+
+    // Admission: first come first served, by device-memory footprint.
+    void admit() {
+        while (!queue.empty() && (int)active.size() < max_active && !free_slots.empty()) {
+            Job *J = queue.front();
+            void *p = ctx->arena->alloc(J->bytes);
+            if (!p) {
+                if (active.empty()) {  // can never fit beside the server's own buffers
+                    queue.pop_front();
+                    J->status = RMB_ENOMEM;
+                    J->msg = "request does not fit the device-memory budget";
+                    J->phase = DONE;
+                    J->t_admit = J->t_done = now_s();
+                    done.push_back(J);
+                    continue;
+                }
+                break;
+            }
+            queue.pop_front();
+            J->dbuf = (char *)p;
+            job_carve(*J);
+            J->slot = free_slots.back();
+            free_slots.pop_back();
+            J->phase = SETUP;
+            J->t_admit = now_s();
+            J->pj.src = J->src;
+            J->pj.partial = J->partial;
+            if (!J->pc) body_items(J->sys, J->off.data(), J->factor, nullptr, J->items_h, &J->max_m);
+            else J->max_m = J->pc->max_m;
+            active.push_back(J);
+        }
+    }
+
+    rmb_status ensure_stage(size_t bytes) {
+        if (bytes <= stage_cap) return RMB_OK;
+        if (stage_d) ctx->arena->free(stage_d);
+        if (stage_h) RMB_HIP(ctx, hipHostFree(stage_h));
+        stage_d = nullptr, stage_h = nullptr;
+        size_t want = std::max<size_t>(bytes * 2, 1 << 20);
+        stage_d = (char *)ctx->arena->alloc(want);
+        if (!stage_d) return fail(ctx, RMB_ENOMEM, "staging buffer does not fit the budget");
+        RMB_HIP(ctx, hipHostMalloc(&stage_h, want, hipHostMallocDefault));
+        stage_cap = want;
+        return RMB_OK;
+    }
+
+    void begin_cycle(Job *J, double beta) {
+        J->k = 0;
+        J->cycles++;
+        J->cycle_fp32 = J->prec == RMB_PREC_FP32_PAIRS;
+        J->target = J->cycle_fp32 ? std::max(J->inner_tol * beta, 0.5 * J->tol * J->bnorm) : J->tol * J->bnorm;
+        J->R.assign((size_t)J->m * J->m, 0.0);
+        J->cs.assign(J->m, 0.0);
+        J->sn.assign(J->m, 0.0);
+        J->g.assign(J->m + 1, 0.0);
+        J->g[0] = beta;
+        J->phase = ITER;
+    }
+
+    void finish_job(Job *J, rmb_status st, const char *msg) {
+        J->status = st;
+        if (msg) J->msg = msg;
+        J->phase = DONE;
+    }
+
+    // ---------------------------------------------------------------------
+    rmb_status step() {
+        admit();
+        if (active.empty()) return RMB_OK;
+        st.reset();
+
+        std::vector<Job *> setup, finish, iter, resid;
+        for (Job *J : active) {
+            if (J->phase == SETUP) setup.push_back(J);
+            else if (J->phase == FINISH) finish.push_back(J);
+            else if (J->phase == ITER) iter.push_back(J);
+        }
+
+        // --- descriptor tables ------------------------------------------
+        // precond build items (setup jobs without external factors)
+        std::vector<BodyWork> build_items;
+        int build_max_m = 0;
+        for (Job *J : setup) {
+            if (J->pc) continue;
+            for (auto &b : J->items_h) {
+                b.flag = flag_d(J);
+                build_items.push_back(b);
+            }
+            build_max_m = std::max(build_max_m, J->max_m);
+        }
+        size_t o_build = build_items.empty() ? 0 : st.put(build_items.data(), build_items.size() * sizeof(BodyWork));
+        // setup items copies (persistent per job): offsets into staging
+        std::vector<size_t> o_items(setup.size(), 0), o_off(setup.size(), 0);
+        for (size_t i = 0; i < setup.size(); ++i) {
+            Job *J = setup[i];
+            if (!J->pc) {
+                for (auto &b : J->items_h) b.flag = flag_d(J);
+                o_items[i] = st.put(J->items_h.data(), J->items_h.size() * sizeof(BodyWork));
+            }
+            o_off[i] = st.put(J->off.data(), J->off.size() * sizeof(int64_t));
+        }
+
+        // combine (finish): coefficients y
+        std::vector<KrylovJob> comb;
+        std::vector<size_t> o_coef;
+        int64_t wg_comb = 0;
+        for (Job *J : finish) o_coef.push_back(st.put(J->y.data(), J->y.size() * 8));
+        // precond apply: finish (z -> w) then iter (V_k -> z)
+        std::vector<PrecondApplyJob> app;
+        int64_t wg_app = 0;
+        int app_max_m = 0;
+        auto add_app = [&](Job *J, const double *in, double *out) {
+            PrecondApplyJob a{};
+            a.items = J->items_d;
+            a.in = in;
+            a.out = out;
+            a.ld = J->n;
+            a.nb3 = 3 * J->nb;
+            a.wg_begin = wg_app;
+            a.n_items = (int32_t)J->N;
+            a.nrhs = 1;
+            app.push_back(a);
+            wg_app += J->N;
+            app_max_m = std::max(app_max_m, J->max_m);
+        };
+        for (Job *J : finish) add_app(J, J->z, J->w);
+        for (Job *J : iter) add_app(J, J->V + (size_t)J->k * J->ldv, J->z);
+
+        // matvec operands: iter (z, its cycle precision), finish/resid (x, FP64)
+        std::vector<Job *> mv = iter;
+        for (Job *J : finish) mv.push_back(J);
+        std::vector<PackJob> pk;
+        int64_t wg_pk = 0;
+        std::vector<PairJob> pairs[2][2];  // [fp32][wall]
+        int64_t tiles[2][2] = {{0, 0}, {0, 0}};
+        std::vector<SaddleJob> sd;
+        int64_t wg_sd_blob = 0, wg_sd_body = 0;
+        for (Job *J : mv) {
+            const bool is_iter = J->phase == ITER;
+            const bool f32 = is_iter && J->cycle_fp32;
+            const double *xin = is_iter ? J->z : J->x;
+            PackJob p{};
+            p.pos = J->sys.pos;
+            p.lam = xin;
+            p.src = J->src;
+            p.nb = J->nb;
+            p.wg_begin = wg_pk;
+            p.precision = f32 ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64;
+            pk.push_back(p);
+            wg_pk += (J->nb + 255) / 256;
+            const int wl = J->sys.geometry == RMB_GEOM_WALL;
+            PairJob pj = J->pj;
+            pj.tile_begin = tiles[f32][wl];
+            pairs[f32][wl].push_back(pj);
+            tiles[f32][wl] += (int64_t)pj.n_tblock * pj.n_split;
+            SaddleJob sj{};
+            sj.pos = J->sys.pos;
+            sj.q = J->sys.q;
+            sj.body_off = J->off_d;
+            sj.blob_body = J->blob_body;
+            sj.partial = J->partial;
+            sj.x = xin;
+            sj.b = is_iter ? nullptr : J->b;
+            sj.y = J->w;
+            sj.nb = J->nb;
+            sj.blk_begin = wg_sd_blob;
+            sj.body_begin = wg_sd_body;
+            sj.n_split = J->pj.n_split;
+            sj.pref = mobility_prefactor(J->sys.a, J->sys.eta);
+            sd.push_back(sj);
+            wg_sd_blob += (J->nb + 255) / 256;
+            wg_sd_body += J->N;
+            if (f32) J->mv32++; else J->mv64++;
+        }
+
+        // orthogonalisation / normalisation: iter (kk = k+1), finish->resid
+        // and setup->start (kk = 0)
+        std::vector<KrylovJob> orth;
+        int64_t wg_orth = 0;
+        auto kj = [&](Job *J, double *w, int kk, double *vnext, int64_t &wg) {
+            KrylovJob K{};
+            K.V = J->V;
+            K.ldv = J->ldv;
+            K.w = w;
+            K.vnext = vnext;
+            K.P1 = J->P1;
+            K.P2 = J->P2;
+            K.P3 = J->P3;
+            K.hcol = hcol_d(J);
+            K.n = J->n;
+            K.wg_begin = wg;
+            K.n_seg = (int32_t)J->nseg;
+            K.kk = kk;
+            wg += J->nseg;
+            return K;
+        };
+        for (Job *J : iter) orth.push_back(kj(J, J->w, J->k + 1, J->V + (size_t)(J->k + 1) * J->ldv, wg_orth));
+        for (Job *J : finish) orth.push_back(kj(J, J->w, 0, J->V, wg_orth));
+        for (Job *J : setup) orth.push_back(kj(J, J->b, 0, J->V, wg_orth));
+        // finish: combine then axpy tables
+        std::vector<KrylovJob> axp;
+        int64_t wg_axp = 0;
+        for (size_t i = 0; i < finish.size(); ++i) {
+            Job *J = finish[i];
+            KrylovJob K = kj(J, J->z, (int)J->y.size(), nullptr, wg_comb);
+            K.coef = (const double *)(uintptr_t)o_coef[i];  // patched below
+            comb.push_back(K);
+            KrylovJob A = kj(J, nullptr, 0, nullptr, wg_axp);
+            A.x = J->x;
+            A.t = J->w;
+            axp.push_back(A);
+        }
+
+        size_t o_app = app.empty() ? 0 : st.put(app.data(), app.size() * sizeof(PrecondApplyJob));
+        size_t o_pk = pk.empty() ? 0 : st.put(pk.data(), pk.size() * sizeof(PackJob));
+        size_t o_pair[2][2];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                o_pair[a][b] = pairs[a][b].empty() ? 0 : st.put(pairs[a][b].data(), pairs[a][b].size() * sizeof(PairJob));
+        size_t o_sd = sd.empty() ? 0 : st.put(sd.data(), sd.size() * sizeof(SaddleJob));
+        size_t o_orth = orth.empty() ? 0 : st.put(orth.data(), orth.size() * sizeof(KrylovJob));
+        size_t o_axp = axp.empty() ? 0 : st.put(axp.data(), axp.size() * sizeof(KrylovJob));
+        // combine table needs device addresses of the coefficients: patch after sizing
+        size_t o_comb = 0;
+        RMB_TRY(ensure_stage(st.used + comb.size() * sizeof(KrylovJob) + 4096));
+        for (auto &K : comb) K.coef = (const double *)(stage_d + (size_t)(uintptr_t)K.coef);
+        if (!comb.empty()) o_comb = st.put(comb.data(), comb.size() * sizeof(KrylovJob));
+        RMB_TRY(ensure_stage(st.used));
+        memcpy(stage_h, st.host.data(), st.used);
+        RMB_HIP(ctx, hipMemcpyAsync(stage_d, stage_h, st.used, hipMemcpyHostToDevice, s));
+        auto D = [&](size_t o) { return (void *)(stage_d + o); };
+
+        // --- launches -------------------------------------------------------
+        int max_slot = 0;
+        for (Job *J : active) max_slot = std::max(max_slot, J->slot + 1);
+        for (size_t i = 0; i < setup.size(); ++i) {
+            Job *J = setup[i];
+            RMB_HIP(ctx, hipMemsetAsync(flag_d(J), 0, sizeof(int), s));
+            RMB_HIP(ctx, launch_validate_positions(J->sys.pos, J->nb, J->sys.geometry == RMB_GEOM_WALL, flag_d(J), s));
+            RMB_HIP(ctx, hipMemcpyAsync(J->off_d, D(o_off[i]), J->off.size() * 8, hipMemcpyDeviceToDevice, s));
+            if (!J->pc)
+                RMB_HIP(ctx, hipMemcpyAsync(J->items_d, D(o_items[i]), J->items_h.size() * sizeof(BodyWork),
+                                            hipMemcpyDeviceToDevice, s));
+            RMB_HIP(ctx, launch_blob_body(J->off_d, J->N, J->blob_body, s));
+            RMB_HIP(ctx, launch_build_rhs(J->FT, J->slip, J->nb, J->N, J->b, s));
+            RMB_HIP(ctx, hipMemsetAsync(J->x, 0, J->n * 8, s));
+        }
+        if (!build_items.empty())
+            RMB_HIP(ctx, launch_precond_build_small((const BodyWork *)D(o_build), (int32_t)build_items.size(),
+                                                    build_max_m, s));
+        if (!comb.empty()) RMB_HIP(ctx, launch_combine((const KrylovJob *)D(o_comb), (int32_t)comb.size(), wg_comb, s));
+        if (!app.empty())
+            RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)D(o_app), (int32_t)app.size(), wg_app, 1,
+                                                    app_max_m, s));
+        if (!axp.empty()) RMB_HIP(ctx, launch_axpy((const KrylovJob *)D(o_axp), (int32_t)axp.size(), wg_axp, s));
+        if (!pk.empty()) RMB_HIP(ctx, launch_pack_table((const PackJob *)D(o_pk), (int32_t)pk.size(), wg_pk, s));
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                if (!pairs[a][b].empty())
+                    RMB_HIP(ctx, launch_pair_tiles(a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0,
+                                                   (const PairJob *)D(o_pair[a][b]), (int32_t)pairs[a][b].size(),
+                                                   tiles[a][b], s));
+        if (!sd.empty())
+            RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));
+        if (!orth.empty())
+            RMB_HIP(ctx, launch_orthogonalise((const KrylovJob *)D(o_orth), (int32_t)orth.size(), wg_orth, s));
+        RMB_HIP(ctx, hipMemcpyAsync(mbox_h, mbox_d, (size_t)max_slot * kSlot * 8, hipMemcpyDeviceToHost, s));
+        RMB_HIP(ctx, hipStreamSynchronize(s));
+
+        // --- host updates -------------------------------------------------
+        for (Job *J : setup) {
+            const int f = flag_h(J);
+            if (f & 3) { finish_job(J, RMB_EINVAL, (f & 1) ? "non-finite blob position" : "a blob has z <= 0 in wall geometry"); continue; }
+            if (f & 4) { finish_job(J, RMB_ENOTSPD, "a body's mobility block is not positive definite"); continue; }
+            if (f & 8) { finish_job(J, RMB_ENOTSPD, "a body's K^T M^-1 K block is singular"); continue; }
+            J->bnorm = hcol_h(J)[0];
+            if (!(J->bnorm > 0.0)) {
+                J->rel = 0.0;
+                finish_job(J, RMB_OK, nullptr);  // x = 0 solves b = 0
+                continue;
+            }
+            J->rel = 1.0;
+            begin_cycle(J, J->bnorm);
+        }
+        for (Job *J : finish) {
+            const double beta = hcol_h(J)[0];
+            J->rel = beta / J->bnorm;
+            if (J->rel <= J->tol) finish_job(J, RMB_OK, nullptr);
+            else if (J->iters >= J->max_iters) finish_job(J, RMB_ENOCONV, "iteration limit reached");
+            else begin_cycle(J, beta);
+        }
+        for (Job *J : iter) {
+            const double *h = hcol_h(J);
+            const int k = J->k;
+            std::vector<double> c(h, h + k + 2);
+            for (int i = 0; i < k; ++i) {
+                const double t = J->cs[i] * c[i] + J->sn[i] * c[i + 1];
+                c[i + 1] = -J->sn[i] * c[i] + J->cs[i] * c[i + 1];
+                c[i] = t;
+            }
+            const double den = std::hypot(c[k], c[k + 1]);
+            bool breakdown = !(den > 0.0);
+            if (!breakdown) {
+                J->cs[k] = c[k] / den;
+                J->sn[k] = c[k + 1] / den;
+                c[k] = den;
+                J->g[k + 1] = -J->sn[k] * J->g[k];
+                J->g[k] = J->cs[k] * J->g[k];
+            }
+            for (int i = 0; i <= k; ++i) J->R[(size_t)i * J->m + k] = c[i];
+            J->k = k + 1;
+            J->iters++;
+            const bool lucky = !(h[k + 1] > 1e-300 * std::max(1.0, J->bnorm));
+            if (breakdown || lucky || std::fabs(J->g[J->k]) <= J->target || J->k >= J->m || J->iters >= J->max_iters) {
+                // y = R^-1 g over the first kk columns (drop a singular last column)
+                int kk = J->k;
+                if (breakdown) kk = J->k - 1;
+                J->y.assign(kk, 0.0);
+                for (int i = kk - 1; i >= 0; --i) {
+                    double v = J->g[i];
+                    for (int j = i + 1; j < kk; ++j) v -= J->R[(size_t)i * J->m + j] * J->y[j];
+                    J->y[i] = v / J->R[(size_t)i * J->m + i];
+                }
+                J->phase = FINISH;
+            }
+        }
+
+        // --- completion ------------------------------------------------------
+        std::vector<Job *> fin;
+        for (Job *J : active)
+            if (J->phase == DONE) fin.push_back(J);
+        if (!fin.empty()) {
+            for (Job *J : fin) {
+                if (J->status == RMB_OK || J->status == RMB_ENOCONV) {
+                    RMB_HIP(ctx, hipMemcpyAsync(J->lam_out, J->x, 3 * J->nb * 8, hipMemcpyDeviceToDevice, s));
+                    RMB_HIP(ctx, hipMemcpyAsync(J->U_out, J->x + 3 * J->nb, 6 * J->N * 8, hipMemcpyDeviceToDevice, s));
+                }
+            }
+            RMB_HIP(ctx, hipStreamSynchronize(s));
+            const double t = now_s();
+            for (Job *J : fin) {
+                J->t_done = t;
+                release(J);
+                done.push_back(J);
+            }
+            active.erase(std::remove_if(active.begin(), active.end(), [](Job *J) { return J->phase == DONE; }),
+                         active.end());
+        }
+        return RMB_OK;
+    }
+
+    static void fill_info(const Job *J, rmb_solve_info *info) {
+        if (!info) return;
+        info->status = J->status;
+        info->iterations = J->iters;
+        info->cycles = J->cycles;
+        info->matvecs_fp64 = J->mv64;
+        info->matvecs_fp32 = J->mv32;
+        info->pad = 0;
+        info->rel_residual = J->rel;
+        info->seconds = J->t_done - J->t_admit;
+    }
+};
+
+}  // namespace rmb
+
+struct rmb_server_s {
+    rmb::Engine *eng = nullptr;
+};
+
+extern "C" {
+
+// ---------------------------------------------------------------------------
+// preconditioner entry points
+// ---------------------------------------------------------------------------
+
+rmb_status rmb_precond_factor(rmb_ctx ctx, const rmb_system *sys, rmb_precond *out, rmb_stream stream) {
+    if (!ctx || !out) return RMB_EINVAL;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_system(ctx, sys, true));
+    RMB_TRY(check_body_sizes(ctx, sys->body_off, sys->n_bodies));
+    auto pc = new rmb_precond_s();
+    pc->ctx = ctx;
+    pc->nb = sys->n_blobs;
+    pc->N = sys->n_bodies;
+    const size_t fbytes = al(factor_total(sys->body_off, sys->n_bodies) * 8);
+    const size_t ibytes = al(sys->n_bodies * sizeof(BodyWork));
+    pc->dbuf = (char *)ctx->arena->alloc(fbytes + ibytes + 256);
+    if (!pc->dbuf) {
+        delete pc;
+        return fail(ctx, RMB_ENOMEM, "preconditioner factors (%zu bytes) exceed the budget", fbytes + ibytes);
+    }
+    pc->factor = (double *)pc->dbuf;
+    pc->items_d = (BodyWork *)(pc->dbuf + fbytes);
+    pc->flag_d = (int *)(pc->dbuf + fbytes + ibytes);
+    std::vector<BodyWork> items;
+    body_items(*sys, sys->body_off, pc->factor, pc->flag_d, items, &pc->max_m);
+    auto cleanup = [&](rmb_status st) {
+        ctx->arena->free(pc->dbuf);
+        delete pc;
+        return st;
+    };
+    rmb_status st = check_positions(ctx, sys, pc->flag_d, s);
+    if (st != RMB_OK) return cleanup(st);
+    void *h = nullptr;
+    st = pinned(ctx, items.size() * sizeof(BodyWork), &h);
+    if (st != RMB_OK) return cleanup(st);
+    memcpy(h, items.data(), items.size() * sizeof(BodyWork));
+    if (hipMemsetAsync(pc->flag_d, 0, sizeof(int), s) != hipSuccess ||
+        hipMemcpyAsync(pc->items_d, h, items.size() * sizeof(BodyWork), hipMemcpyHostToDevice, s) != hipSuccess ||
+        launch_precond_build_small(pc->items_d, (int32_t)items.size(), pc->max_m, s) != hipSuccess)
+        return cleanup(fail(ctx, RMB_EDEVICE, "preconditioner build launch failed"));
+    int *hf = nullptr;
+    if (pinned(ctx, sizeof(int), (void **)&hf) != RMB_OK ||
+        hipMemcpyAsync(hf, pc->flag_d, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(fail(ctx, RMB_EDEVICE, "preconditioner build failed"));
+    if (*hf & 4) return cleanup(fail(ctx, RMB_ENOTSPD, "a body's mobility block is not positive definite"));
+    if (*hf & 8) return cleanup(fail(ctx, RMB_ENOTSPD, "a body's K^T M^-1 K block is singular"));
+    *out = pc;
+    return RMB_OK;
+}
+
+rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, const double *in, double *out,
+                             rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    if (!pc || pc->ctx != ctx) return fail(ctx, RMB_EINVAL, "preconditioner is NULL or from another context");
+    if (nrhs < 0 || nrhs > 65535) return fail(ctx, RMB_EINVAL, "nrhs out of range");
+    if (nrhs == 0) return RMB_OK;
+    if (!in || !out || in == out) return fail(ctx, RMB_EINVAL, "in and out must be distinct device buffers");
+    PrecondApplyJob a{};
+    a.items = pc->items_d;
+    a.in = in;
+    a.out = out;
+    a.ld = 3 * pc->nb + 6 * pc->N;
+    a.nb3 = 3 * pc->nb;
+    a.wg_begin = 0;
+    a.n_items = (int32_t)pc->N;
+    a.nrhs = nrhs;
+    void *d = nullptr, *h = nullptr;
+    RMB_TRY(scratch(ctx, sizeof a, &d));
+    RMB_TRY(pinned(ctx, sizeof a, &h));
+    memcpy(h, &a, sizeof a);
+    RMB_HIP(ctx, hipMemcpyAsync(d, h, sizeof a, hipMemcpyHostToDevice, s));
+    RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)d, 1, pc->N, nrhs, pc->max_m, s));
+    return RMB_OK;
+}
+
+void rmb_precond_destroy(rmb_precond pc) {
+    if (!pc) return;
+    (void)hipDeviceSynchronize();
+    pc->ctx->arena->free(pc->dbuf);
+    delete pc;
+}
+
+// ---------------------------------------------------------------------------
+// solves
+// ---------------------------------------------------------------------------
+
+rmb_status rmb_server_create(rmb_ctx ctx, int32_t max_active, rmb_stream stream, rmb_server *out) {
+    if (!ctx || !out) return RMB_EINVAL;
+    *out = nullptr;
+    if (max_active < 0) return fail(ctx, RMB_EINVAL, "max_active must be >= 0");
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    auto srv = new rmb_server_s();
+    srv->eng = new Engine(ctx, s, max_active ? max_active : 1024);
+    rmb_status st = srv->eng->init();
+    if (st != RMB_OK) {
+        delete srv->eng;
+        delete srv;
+        return st;
+    }
+    *out = srv;
+    return RMB_OK;
+}
+
+rmb_status rmb_server_submit(rmb_server srv, const rmb_system *sys, const double *FT, const double *slip, double *U,
+                             double *lambda, const rmb_solve_opts *opts, int64_t tag) {
+    if (!srv) return RMB_EINVAL;
+    Job *J = nullptr;
+    return srv->eng->submit(sys, FT, slip, U, lambda, opts, nullptr, tag, &J);
+}
+
+rmb_status rmb_server_step(rmb_server srv, int32_t *n_active, int32_t *n_queued) {
+    if (!srv) return RMB_EINVAL;
+    Engine *E = srv->eng;
+    RMB_TRY(enter(E->ctx, E->s));
+    rmb_status st = E->step();
+    if (n_active) *n_active = (int32_t)E->active.size();
+    if (n_queued) *n_queued = (int32_t)E->queue.size();
+    return st;
+}
+
+rmb_status rmb_server_poll(rmb_server srv, int32_t max_out, int64_t *tags, rmb_solve_info *infos, int32_t *n_out) {
+    if (!srv || !n_out) return RMB_EINVAL;
+    Engine *E = srv->eng;
+    int32_t n = 0;
+    while (n < max_out && !E->done.empty()) {
+        Job *J = E->done.front();
+        E->done.pop_front();
+        if (tags) tags[n] = J->tag;
+        if (infos) Engine::fill_info(J, &infos[n]);
+        delete J;
+        ++n;
+    }
+    *n_out = n;
+    return RMB_OK;
+}
+
+void rmb_server_destroy(rmb_server srv) {
+    if (!srv) return;
+    delete srv->eng;
+    delete srv;
+}
+
+static rmb_status run_batch(rmb_ctx ctx, int32_t count, const rmb_system *systems, const rmb_precond *pcs,
+                            const double *const *FT, const double *const *slip, double *const *U,
+                            double *const *lambda, const rmb_solve_opts *opts, rmb_solve_info *infos,
+                            hipStream_t s) {
+    Engine E(ctx, s, std::max(1, std::min<int32_t>(count, 1024)));
+    RMB_TRY(E.init());
+    std::vector<Job *> jobs(count, nullptr);
+    for (int32_t i = 0; i < count; ++i) {
+        rmb_status st = E.submit(&systems[i], FT[i], slip ? slip[i] : nullptr, U[i], lambda[i], opts,
+                                 pcs ? pcs[i] : nullptr, i, &jobs[i]);
+        if (st != RMB_OK) return st;
+    }
+    std::vector<rmb_status> status(count, RMB_OK);
+    int32_t left = count;
+    while (left > 0) {
+        RMB_TRY(E.step());
+        while (!E.done.empty()) {
+            Job *J = E.done.front();
+            E.done.pop_front();
+            if (infos) Engine::fill_info(J, &infos[J->tag]);
+            status[J->tag] = J->status;
+            if (J->status != RMB_OK && !J->msg.empty()) ctx->err = J->msg;
+            delete J;
+            --left;
+        }
+    }
+    for (int32_t i = 0; i < count; ++i)
+        if (status[i] != RMB_OK) return status[i];
+    return RMB_OK;
+}
+
+rmb_status rmb_solve_mobility(rmb_ctx ctx, const rmb_system *sys, const rmb_precond pc, const double *FT,
+                              const double *slip, double *U, double *lambda, const rmb_solve_opts *opts,
+                              rmb_solve_info *info, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    rmb_solve_info tmp{};
+    rmb_precond pcs[1] = {pc};
+    const double *slips[1] = {slip};
+    return run_batch(ctx, 1, sys, pc ? pcs : nullptr, &FT, slips, &U, &lambda, opts, info ? info : &tmp, s);
+}
+
+rmb_status rmb_solve_batch(rmb_ctx ctx, int32_t count, const rmb_system *systems, const double *const *FT,
+                           const double *const *slip, double *const *U, double *const *lambda,
+                           const rmb_solve_opts *opts, rmb_solve_info *infos, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    if (count < 0 || !systems || !FT || !U || !lambda || !infos)
+        return fail(ctx, RMB_EINVAL, "bad batch arguments");
+    if (count == 0) return RMB_OK;
+    return run_batch(ctx, count, systems, nullptr, FT, slip, U, lambda, opts, infos, s);
+}
+
+}  // extern "C"

@@ -102,6 +102,36 @@ hipError_t launch_pack_sources(int precision, const double *pos, const double *l
     return hipGetLastError();
 }
 
+__global__ void pack_table_kernel(const PackJob *__restrict__ jobs, int32_t n_jobs) {
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const PackJob &J = jobs[lo];
+    const int64_t j = (w - J.wg_begin) * 256 + threadIdx.x;
+    if (j >= J.nb) return;
+    const double x = J.pos[3 * j], y = J.pos[3 * j + 1], z = J.pos[3 * j + 2];
+    const double fx = J.lam[3 * j], fy = J.lam[3 * j + 1], fz = J.lam[3 * j + 2];
+    if (J.precision == RMB_PREC_FP32_PAIRS) {
+        SrcF32 r;
+        r.x = x, r.y = y, r.z = z;
+        r.fx = (float)fx, r.fy = (float)fy, r.fz = (float)fz, r.zf = (float)z;
+        ((SrcF32 *)J.src)[j] = r;
+    } else {
+        SrcF64 r;
+        r.x = x, r.y = y, r.z = z, r.fx = fx, r.fy = fy, r.fz = fz;
+        ((SrcF64 *)J.src)[j] = r;
+    }
+}
+
+hipError_t launch_pack_table(const PackJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {
+    if (n_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_table_kernel, dim3((unsigned)n_wg), dim3(256), 0, s, jobs, n_jobs);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // pair kernels
 // ---------------------------------------------------------------------------

@@ -1,0 +1,203 @@
+"""GPU mobility solves against the CPU oracle.
+
+Bar (velocities): ||U - U_oracle|| / ||U_oracle|| <= 1e-8 for solves run to a
+residual tight enough that the forward error is below it; every solve's FP64
+residual ||b - A x|| / ||b|| is re-evaluated by the oracle on the GPU's
+(U, lambda) and must meet the requested tolerance.  lambda is checked through
+that residual (it is unique, but only determined to the solve tolerance).
+"""
+import numpy as np
+import pytest
+
+import suspensions as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env(oracle_mod):
+    import torch
+    import paper_1602_02170_amd as rmb
+    ctx = rmb.Context(0)
+    yield rmb, torch, ctx, oracle_mod
+    ctx.close()
+
+
+def _dev(torch, a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def _solve(env, sus, FT=None, slip=None, **opts):
+    rmb, torch, ctx, _ = env
+    sysd = rmb.System.from_suspension(sus)
+    FT = sus.FT if FT is None else FT
+    U, lam, info = rmb.solve_mobility(ctx, sysd, _dev(torch, FT), None if slip is None else _dev(torch, slip),
+                                      **opts)
+    torch.cuda.synchronize()
+    return U.cpu().numpy(), lam.cpu().numpy(), info
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def small_wall():
+    return S.boomerangs_wall(n_bodies=80, lateral=56.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_free_space_spheres_parity(env, prec):
+    O = env[3]
+    s = S.spheres_free_space()
+    print(f"[gpu] free-space 8 spheres {prec}", flush=True)
+    Ud, ld = O.dense_solve(s, s.FT)
+    U, lam, info = _solve(env, s, tol=1e-10, precision=prec)
+    res = O.relative_residual(s, s.FT, None, U, lam)
+    print(f"    info {info}  oracle residual {res:.2e}  U err {_rel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0
+    assert info["rel_residual"] <= 1e-10
+    assert res <= 1.05e-10
+    assert _rel(U, Ud) <= 1e-8
+    if prec == "fp32":
+        assert info["matvecs_fp32"] > 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_wall_boomerangs_parity(env, prec):
+    O = env[3]
+    s = small_wall()
+    print(f"[gpu] wall 80 boomerangs {prec}", flush=True)
+    Ud, ld = O.dense_solve(s, s.FT)
+    U, lam, info = _solve(env, s, tol=1e-8, precision=prec)
+    res = O.relative_residual(s, s.FT, None, U, lam)
+    print(f"    tol 1e-8: info {info}  oracle residual {res:.2e}  U err {_rel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0 and res <= 1.05e-8
+    U, lam, info = _solve(env, s, tol=1e-11, precision=prec)
+    res = O.relative_residual(s, s.FT, None, U, lam)
+    print(f"    tol 1e-11: info {info}  oracle residual {res:.2e}  U err {_rel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0 and res <= 1.05e-11
+    assert _rel(U, Ud) <= 1e-8
+
+
+def test_wall_slip_parity(env):
+    O = env[3]
+    s = small_wall()
+    slip = np.random.default_rng(21).standard_normal((s.n_blobs, 3)) * 0.2
+    FT = np.random.default_rng(22).standard_normal((s.n_bodies, 6))
+    Ud, ld = O.dense_solve(s, FT, slip)
+    U, lam, info = _solve(env, s, FT=FT, slip=slip, tol=1e-11)
+    res = O.relative_residual(s, FT, slip, U, lam)
+    print(f"[gpu] slip: info {info}  oracle residual {res:.2e}  U err {_rel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0 and res <= 1.05e-11
+    assert _rel(U, Ud) <= 1e-8
+
+
+def test_full_boomerang_suspension_refined_and_plain(env):
+    """1000 x 15-blob boomerangs (15,000 blobs) to 1e-8: the oracle's FP64
+    residual of the GPU result meets the tolerance for both precisions, and
+    the two agree."""
+    O = env[3]
+    s = S.boomerangs_wall()
+    out = {}
+    for prec in ("fp32", "fp64"):
+        print(f"[gpu] full boomerangs {prec}", flush=True)
+        U, lam, info = _solve(env, s, tol=1e-8, precision=prec)
+        res = O.relative_residual(s, s.FT, None, U, lam)
+        print(f"    info {info}  oracle residual {res:.2e}", flush=True)
+        assert info["status"] == 0
+        assert res <= 1.05e-8
+        out[prec] = U
+    assert _rel(out["fp32"], out["fp64"]) <= 1e-6
+
+
+def test_precond_apply_parity(env):
+    rmb, torch, ctx, O = env
+    s = small_wall()
+    rhs = np.random.default_rng(23).standard_normal((8, 3 * s.n_blobs + 6 * s.n_bodies))
+    P = O.BlockPreconditioner(s)
+    ref = np.stack([P.apply(r) for r in rhs])
+    sysd = rmb.System.from_suspension(s)
+    pc = rmb.Precond(ctx, sysd)
+    got = pc.apply(_dev(torch, rhs)).cpu().numpy()
+    err = _rel(got, ref)
+    print(f"[gpu] precond apply 8 rhs rel err {err:.2e}", flush=True)
+    assert err <= 1e-10
+    # a solve that reuses the factors gives the same result as one that builds them
+    FT = _dev(torch, s.FT)
+    U1, l1, i1 = rmb.solve_mobility(ctx, sysd, FT, precond=pc, tol=1e-9)
+    U2, l2, i2 = rmb.solve_mobility(ctx, sysd, FT, tol=1e-9)
+    assert torch.equal(U1, U2) and torch.equal(l1, l2)
+    pc.close()
+
+
+def test_batch_results_equal_alone(env):
+    rmb, torch, ctx, O = env
+    sus = [S.boomerangs_wall(n_bodies=n, lateral=np.sqrt(40 * n), seed=500 + n) for n in (7, 60, 200)]
+    sus.append(S.spheres_free_space())
+    systems = [rmb.System.from_suspension(x) for x in sus]
+    FTs = [_dev(torch, x.FT) for x in sus]
+    for prec in ("fp64", "fp32"):
+        alone = [rmb.solve_mobility(ctx, systems[i], FTs[i], tol=1e-9, precision=prec) for i in range(len(sus))]
+        mixed = rmb.solve_batch(ctx, systems, FTs, tol=1e-9, precision=prec)
+        for (Ua, la, ia), (Um, lm, im) in zip(alone, mixed):
+            assert im["status"] == 0
+            assert torch.equal(Ua, Um) and torch.equal(la, lm)
+            assert ia["iterations"] == im["iterations"]
+
+
+def test_server_results_equal_alone(env):
+    rmb, torch, ctx, O = env
+    reqs = [S.mixed_wall_request(i, n_bodies=n) for i, n in enumerate((12, 90, 33, 150, 5))]
+    systems = [rmb.System.from_suspension(x) for x in reqs]
+    FTs = [_dev(torch, x.FT) for x in reqs]
+    alone = [rmb.solve_mobility(ctx, systems[i], FTs[i], tol=1e-8, precision="fp32") for i in range(len(reqs))]
+    srv = rmb.Server(ctx, max_active=3)
+    got = {}
+    pending = list(range(len(reqs)))
+    steps = 0
+    while len(got) < len(reqs):
+        if pending and steps % 3 == 0:  # requests arrive while others run
+            i = pending.pop(0)
+            srv.submit(i, systems[i], FTs[i], tol=1e-8, precision="fp32")
+        srv.step()
+        for tag, U, lam, info in srv.poll():
+            got[tag] = (U, lam, info)
+        steps += 1
+        assert steps < 5000
+    srv.close()
+    for i, (Ua, la, ia) in enumerate(alone):
+        Um, lm, im = got[i]
+        assert im["status"] == 0
+        assert torch.equal(Ua, Um) and torch.equal(la, lm)
+        res = O.relative_residual(reqs[i], reqs[i].FT, None, Um.cpu().numpy(), lm.cpu().numpy())
+        assert res <= 1.05e-8
+
+
+def test_solve_error_paths(env):
+    rmb, torch, ctx, O = env
+    # a layer of blobs overlapping the wall: the body's block is not SPD
+    a = 0.5
+    g = np.arange(5) * 0.6
+    X, Y = np.meshgrid(g, g)
+    pos = np.stack([X.ravel(), Y.ravel(), np.full(X.size, 0.3 * a)], axis=1)
+    s = S.Suspension(pos, np.array([0, 25]), pos.mean(axis=0, keepdims=True), a, 1.0, True,
+                     np.ones((1, 6)))
+    with pytest.raises(rmb.RmbError) as e:
+        _solve(env, s)
+    assert e.value.status == rmb.RMB_ENOTSPD
+    # iteration limit: status ENOCONV, residual reported
+    s = small_wall()
+    U, lam, info = _solve(env, s, tol=1e-12, max_iters=2)
+    assert info["status"] == rmb.RMB_ENOCONV and 0 < info["rel_residual"] < 1
+    res = O.relative_residual(s, s.FT, None, U, lam)
+    assert abs(res - info["rel_residual"]) <= 1e-6 * res
+    # a blob below the wall
+    pos = s.pos.copy()
+    pos[3, 2] = -0.1
+    bad = S.Suspension(pos, s.body_off, s.q, s.a, 1.0, True, s.FT)
+    with pytest.raises(rmb.RmbError) as e:
+        _solve(env, bad)
+    assert e.value.status == rmb.RMB_EINVAL
+    # zero load: zero velocities without iterating
+    U, lam, info = _solve(env, s, FT=np.zeros_like(s.FT))
+    assert info["status"] == 0 and not U.any() and not lam.any()
