@@ -1,0 +1,264 @@
+#!/usr/bin/env python3
+"""Benchmark of the rigid-multiblob mobility solver on one MI355X.
+
+Timed step (the whole hot path, inputs resident in HBM): one mobility solve
+of 1000 x 15-blob boomerangs above a no-slip wall (15,000 blobs), right-
+preconditioned GMRES with the block-diagonal preconditioner, FP32-pair
+products inside FP64 iterative refinement to an FP64 relative residual of
+1e-8.  `value` = blob-pair interactions evaluated per second over the timed
+solves (every FP32 and FP64 mobility product counts Nb^2 pairs).
+
+Also reported (outside the timed region): the plain FP64 solve of the same
+system; the 196,608-blob monolayer mobility product in both precisions; a
+serving run of 256 wall-bounded requests (Poisson arrivals at 50/s, p50/p99
+latency, and the saturated solves/s against the same requests solved one at
+a time in plain FP64); the roofline of the dominant kernel (FP32 wall pair
+kernel) from HIP events recorded around its launches; and the CPU oracle's
+pair rate on a bounded sample.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Flop count per pair of the implemented pair kernels (FMA = 2, add/mul = 1,
+# reciprocal square root = 1, compares/selects/conversions = 0).
+FLOPS_PER_PAIR = {"pair_f32_wall": 130, "pair_f32_free": 42, "pair_f64_wall": 145, "pair_f64_free": 50}
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}  # MI355X published vector peaks
+METRIC = "blob-pair interactions/s (wall RPY matvec); solves/s + p50/p99 latency @1e-8 vs FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def solve_leg(rmb, torch, ctx, sysd, FT, precision, steps, warmup, tol=1e-8):
+    for _ in range(warmup):
+        rmb.solve_mobility(ctx, sysd, FT, tol=tol, precision=precision)
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, _, info = rmb.solve_mobility(ctx, sysd, FT, tol=tol, precision=precision)
+        infos.append(info)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kt = {k: ctx.kernel_time(k) for k in ("pair_f32_wall", "pair_f64_wall")}
+    ctx.set_timing(False)
+    return dt, infos, kt
+
+
+def matvec_leg(rmb, torch, ctx, S, reps=5):
+    sus, lam = S.icosahedra_monolayer()
+    sysd = rmb.System.from_suspension(sus)
+    lt = torch.tensor(lam, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(lt)
+    res = {"workload": f"wall RPY mobility product, {sus.n_blobs} blobs (16384 x 12-blob icosahedra monolayer)"}
+    for prec in ("fp32", "fp64"):
+        rmb.mobility_matvec(ctx, sysd, lt, prec, out)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            rmb.mobility_matvec(ctx, sysd, lt, prec, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        res[f"{prec}_ms"] = round(ms, 3)
+        res[f"{prec}_pairs_per_s"] = sus.n_blobs ** 2 / (ms * 1e-3)
+        log(f"  matvec {prec}: {ms:.2f} ms, {res[f'{prec}_pairs_per_s']:.3e} pairs/s")
+    return res
+
+
+def serving_leg(rmb, torch, ctx, S, n_req, rate):
+    t_gen = time.perf_counter()
+    reqs = [S.mixed_wall_request(i) for i in range(n_req)]
+    arrivals = S.poisson_arrivals(n_req, rate)
+    systems = [rmb.System.from_suspension(r) for r in reqs]
+    FTs = [torch.tensor(r.FT, dtype=torch.float64, device="cuda") for r in reqs]
+    torch.cuda.synchronize()
+    nb = np.array([r.n_blobs for r in reqs])
+    log(f"  serving: generated {n_req} requests ({nb.sum()} blobs, max {nb.max()}) "
+        f"in {time.perf_counter() - t_gen:.1f}s")
+    opts = dict(tol=1e-8, precision="fp32")
+    # warm-up of the server path
+    srv = rmb.Server(ctx)
+    srv.submit(0, systems[0], FTs[0], **opts)
+    while not srv.poll():
+        srv.step()
+    srv.close()
+
+    def run(arr):
+        srv = rmb.Server(ctx)
+        done = {}
+        nxt = 0
+        t0 = time.perf_counter()
+        ticks = 0
+        while len(done) < n_req:
+            now = time.perf_counter() - t0
+            while nxt < n_req and arr[nxt] <= now:
+                srv.submit(nxt, systems[nxt], FTs[nxt], **opts)
+                nxt += 1
+            a, q = srv.step()
+            ticks += 1
+            for tag, U, lam, info in srv.poll():
+                done[tag] = (time.perf_counter() - t0, info)
+            if a == 0 and q == 0 and nxt < n_req:
+                time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
+        srv.close()
+        comp = np.array([done[i][0] for i in range(n_req)])
+        infos = [done[i][1] for i in range(n_req)]
+        return comp, infos, ticks
+
+    comp, infos, ticks = run(arrivals)
+    lat = comp - arrivals
+    ok = sum(1 for i in infos if i["status"] == 0 and i["rel_residual"] <= 1e-8)
+    res = {
+        "workload": f"{n_req} wall suspensions, 10-4000 mixed icosahedra/boomerangs, Poisson {rate:g}/s, "
+                    "FP32 pairs + FP64 refinement to 1e-8",
+        "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
+        "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
+        "solves_per_s": n_req / (comp.max() - arrivals.min()),
+        "converged": ok,
+        "ticks": ticks,
+    }
+    log(f"  serving Poisson: p50 {res['p50_latency_ms']:.1f} ms p99 {res['p99_latency_ms']:.1f} ms, "
+        f"{res['solves_per_s']:.1f} solves/s, {ok}/{n_req} converged")
+    comp_sat, infos_sat, _ = run(np.zeros(n_req))
+    res["saturated_solves_per_s"] = n_req / comp_sat.max()
+    # plain FP64 GPU path, unbatched: the same requests one at a time
+    torch.cuda.synchronize()
+    service = np.zeros(n_req)
+    for i in range(n_req):
+        t = time.perf_counter()
+        rmb.solve_mobility(ctx, systems[i], FTs[i], tol=1e-8, precision="fp64")
+        torch.cuda.synchronize()
+        service[i] = time.perf_counter() - t
+    res["fp64_unbatched_solves_per_s"] = n_req / service.sum()
+    # the same Poisson stream through a FIFO of one-at-a-time FP64 solves
+    fin = np.zeros(n_req)
+    tcur = 0.0
+    for i in range(n_req):
+        tcur = max(tcur, arrivals[i]) + service[i]
+        fin[i] = tcur
+    lat64 = fin - arrivals
+    res["fp64_unbatched_p50_latency_ms"] = float(np.percentile(lat64, 50) * 1e3)
+    res["fp64_unbatched_p99_latency_ms"] = float(np.percentile(lat64, 99) * 1e3)
+    res["speedup_vs_fp64_unbatched"] = res["saturated_solves_per_s"] / res["fp64_unbatched_solves_per_s"]
+    log(f"  serving saturated: {res['saturated_solves_per_s']:.1f} solves/s; FP64 unbatched "
+        f"{res['fp64_unbatched_solves_per_s']:.1f} solves/s (x{res['speedup_vs_fp64_unbatched']:.2f})")
+    return res
+
+
+def cpu_baseline(S, sus):
+    """The CPU oracle solving the same system (plain FP64 GMRES with the
+    block-diagonal preconditioner, FP64 Kahan-summed pair products): blob-pair
+    interactions evaluated per second over the whole solve."""
+    import oracle
+    calls = [0]
+
+    def apply_A(v):
+        calls[0] += 1
+        return oracle.saddle_apply(sus, v)
+
+    t = time.perf_counter()
+    P = oracle.BlockPreconditioner(sus)
+    b = oracle.rhs(sus, sus.FT, None)
+    _, it, hist = oracle.gmres(apply_A, P.apply, b, tol=1e-8, restart=100, maxiter=1000)
+    dt = time.perf_counter() - t
+    pairs = calls[0] * sus.n_blobs ** 2
+    return {"value": pairs / dt, "unit": "blob-pair interactions/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"the oracle's full FP64 solve of the same 1000-boomerang system to 1e-8: {it} iterations, "
+                      f"{calls[0]} products of {sus.n_blobs}^2 pairs, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--rate", type=float, default=50.0)
+    ap.add_argument("--no-matvec", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only-step", action="store_true", help="timed solves only (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
+              "mobility product would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1602_02170_amd as rmb
+    import suspensions as S
+
+    ctx = rmb.Context(0)
+    sus = S.boomerangs_wall()
+    sysd = rmb.System.from_suspension(sus)
+    FT = torch.tensor(sus.FT, dtype=torch.float64, device="cuda")
+    nb = sus.n_blobs
+    log(f"workload: {sus.name}, {nb} blobs")
+
+    dt, infos, kt = solve_leg(rmb, torch, ctx, sysd, FT, "fp32", args.steps, args.warmup)
+    pairs = sum((i["matvecs_fp32"] + i["matvecs_fp64"]) * nb * nb for i in infos)
+    bad = [i for i in infos if i["status"] != 0 or i["rel_residual"] > 1e-8]
+    value = pairs / dt
+    ms_step = dt / args.steps * 1e3
+    log(f"  refined solve: {ms_step:.2f} ms/solve, {value:.3e} pairs/s, iterations "
+        f"{infos[-1]['iterations']}, fp32/fp64 products {infos[-1]['matvecs_fp32']}/{infos[-1]['matvecs_fp64']}")
+    k_ms, k_n = kt["pair_f32_wall"]
+    avg_ms = k_ms / max(k_n, 1)
+    flops = FLOPS_PER_PAIR["pair_f32_wall"] * nb * nb
+    achieved = flops / (avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "kernel": "pair_f32_kernel<wall>", "achieved": achieved,
+                "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS["fp32"],
+                "traffic": None, "flops_per_pair": FLOPS_PER_PAIR["pair_f32_wall"],
+                "pairs_per_launch": nb * nb, "avg_launch_ms": avg_ms, "launches": k_n}
+    log(f"  pair_f32 wall kernel: {avg_ms:.4f} ms avg over {k_n} launches, {achieved:.1f} TFLOP/s")
+
+    line = {"metric": METRIC, "value": value, "unit": "blob-pair interactions/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32 pairs, f64 accumulation/refinement",
+            "data": "synthetic (seeded boomerang suspension; no dataset)",
+            "config": {"workload": "wall RPY mobility solve, 1000 x 15-blob boomerangs (15,000 blobs), "
+                                   "block-diagonal preconditioned GMRES, FP32 pairs + FP64 refinement to "
+                                   "FP64 relative residual 1e-8",
+                       "n_blobs": nb, "n_bodies": sus.n_bodies, "tol": 1e-8, "parallelism": "single GPU"},
+            "roofline": roofline,
+            "solve": {"ms_per_solve": ms_step, "solves_per_s": 1e3 / ms_step,
+                      "iterations": infos[-1]["iterations"], "fp32_products": infos[-1]["matvecs_fp32"],
+                      "fp64_products": infos[-1]["matvecs_fp64"], "rel_residual": infos[-1]["rel_residual"],
+                      "failed": len(bad)}}
+    if not args.only_step:
+        dt64, infos64, kt64 = solve_leg(rmb, torch, ctx, sysd, FT, "fp64", args.steps, 1)
+        ms64 = dt64 / args.steps * 1e3
+        line["solve"]["fp64_ms_per_solve"] = ms64
+        line["solve"]["fp64_iterations"] = infos64[-1]["iterations"]
+        line["solve"]["speedup_vs_fp64"] = ms64 / ms_step
+        k64 = kt64["pair_f64_wall"]
+        line["solve"]["pair_f64_wall_avg_launch_ms"] = k64[0] / max(k64[1], 1)
+        log(f"  plain FP64 solve: {ms64:.2f} ms/solve ({infos64[-1]['iterations']} iterations)")
+        if not args.no_matvec:
+            line["matvec"] = matvec_leg(rmb, torch, ctx, S)
+        if not args.no_serving:
+            line["serving"] = serving_leg(rmb, torch, ctx, S, args.requests, args.rate)
+        if not args.no_cpu:
+            line["cpu_baseline"] = cpu_baseline(S, sus)
+            log(f"  cpu oracle: {line['cpu_baseline']['value']:.3e} pairs/s on {line['cpu_baseline']['cores']} threads")
+    ctx.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

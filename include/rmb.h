@@ -109,6 +109,21 @@ const char *rmb_last_error(rmb_ctx ctx);
 /* Library version string. */
 const char *rmb_version(void);
 
+/* Kernel timing (diagnostics).  While enabled, every launch of the pair
+ * kernels is bracketed by HIP events recorded on the stream it runs on, and
+ * the elapsed times are accumulated per kernel:
+ *   RMB_KERNEL_PAIR_F32_WALL, RMB_KERNEL_PAIR_F32_FREE,
+ *   RMB_KERNEL_PAIR_F64_WALL, RMB_KERNEL_PAIR_F64_FREE.
+ * Enabling (enable = 1) or disabling resets the totals. */
+enum { RMB_KERNEL_PAIR_F32_WALL = 0, RMB_KERNEL_PAIR_F32_FREE = 1, RMB_KERNEL_PAIR_F64_WALL = 2,
+       RMB_KERNEL_PAIR_F64_FREE = 3, RMB_KERNEL_COUNT = 4 };
+rmb_status rmb_ctx_set_timing(rmb_ctx ctx, int32_t enable);
+
+/* Total milliseconds and launch count of one kernel since timing was
+ * enabled; waits for the recorded events to complete (host arrays of one
+ * element each). */
+rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
 /* ---------------------------------------------------------------------------
  * Blob mobility product  v = M lambda   (Sec. 2.2.1; eq:RPYTensor and the
  * wall-corrected form of Sec. 2.1.1 and Sec. 5)

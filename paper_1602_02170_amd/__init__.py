@@ -30,7 +30,9 @@ PREC_FP64, PREC_FP32_PAIRS = 0, 1
 EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_mobility_matvec", "rmb_precond_factor", "rmb_precond_apply", "rmb_precond_destroy",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
-           "rmb_server_step", "rmb_server_poll", "rmb_server_destroy"]
+           "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
+           "rmb_ctx_kernel_time"]
+KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
 class RmbError(RuntimeError):
@@ -92,6 +94,8 @@ def library(path: str = LIB_PATH):
         L.rmb_server_poll.argtypes = [vp, i32, ctypes.POINTER(i64), infop, ctypes.POINTER(i32)]
         L.rmb_server_destroy.argtypes = [vp]
         L.rmb_server_destroy.restype = None
+        L.rmb_ctx_set_timing.argtypes = [vp, i32]
+        L.rmb_ctx_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         _LIB = L
     return _LIB
 
@@ -135,6 +139,16 @@ class Context:
             self.close()
         except Exception:
             pass
+
+    def set_timing(self, enable: bool):
+        """Bracket every pair-kernel launch with HIP events (resets totals)."""
+        self.check(self.lib.rmb_ctx_set_timing(self.h, 1 if enable else 0))
+
+    def kernel_time(self, kernel: str):
+        """(total ms, launches) of a pair kernel since timing was enabled."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        self.check(self.lib.rmb_ctx_kernel_time(self.h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def check(self, st):
         if st != RMB_OK:

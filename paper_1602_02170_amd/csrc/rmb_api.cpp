@@ -105,6 +105,53 @@ rmb_status check_positions(rmb_ctx ctx, const rmb_system *sys, int *flag_dev, hi
     return RMB_OK;
 }
 
+static hipEvent_t take_event(rmb_ctx ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+rmb_status pair_launch(rmb_ctx ctx, int precision, bool wall, const PairJob *jobs, int32_t n_jobs, int64_t n_tiles,
+                       hipStream_t s) {
+    const int kid = (precision == RMB_PREC_FP32_PAIRS ? 0 : 2) + (wall ? 0 : 1);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->timing) {
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a && b) RMB_HIP(ctx, hipEventRecord(a, s));
+    }
+    RMB_HIP(ctx, launch_pair_tiles(precision, wall, jobs, n_jobs, n_tiles, s));
+    if (ctx->timing && a && b) {
+        RMB_HIP(ctx, hipEventRecord(b, s));
+        ctx->pending.push_back({kid, a, b});
+    }
+    return RMB_OK;
+}
+
+void resolve_timing(rmb_ctx ctx, bool wait) {
+    size_t keep = 0;
+    for (size_t i = 0; i < ctx->pending.size(); ++i) {
+        auto &p = ctx->pending[i];
+        if (wait) (void)hipEventSynchronize(p.b);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+            ctx->kernel_ms[p.kernel] += ms;
+            ctx->kernel_launches[p.kernel] += 1;
+            ctx->event_pool.push_back(p.a);
+            ctx->event_pool.push_back(p.b);
+        } else {
+            (void)hipGetLastError();
+            ctx->pending[keep++] = p;
+        }
+    }
+    ctx->pending.resize(keep);
+}
+
 }  // namespace rmb
 
 using namespace rmb;
@@ -126,10 +173,31 @@ rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
     return RMB_OK;
 }
 
+rmb_status rmb_ctx_set_timing(rmb_ctx ctx, int32_t enable) {
+    if (!ctx) return RMB_EINVAL;
+    RMB_HIP(ctx, hipSetDevice(ctx->device));
+    resolve_timing(ctx, true);
+    ctx->timing = enable != 0;
+    for (int k = 0; k < RMB_KERNEL_COUNT; ++k) ctx->kernel_ms[k] = 0.0, ctx->kernel_launches[k] = 0;
+    return RMB_OK;
+}
+
+rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, int64_t *launches) {
+    if (!ctx || !total_ms || !launches) return RMB_EINVAL;
+    if (kernel < 0 || kernel >= RMB_KERNEL_COUNT) return fail(ctx, RMB_EINVAL, "unknown kernel id %d", kernel);
+    RMB_HIP(ctx, hipSetDevice(ctx->device));
+    resolve_timing(ctx, true);
+    *total_ms = ctx->kernel_ms[kernel];
+    *launches = ctx->kernel_launches[kernel];
+    return RMB_OK;
+}
+
 void rmb_ctx_destroy(rmb_ctx ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    resolve_timing(ctx, true);
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     delete ctx->arena;
     delete ctx;
@@ -168,8 +236,8 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     *hJ = J;
     RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(PairJob), hipMemcpyHostToDevice, s));
     RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
-    RMB_HIP(ctx, launch_pair_tiles(precision, sys->geometry == RMB_GEOM_WALL, (const PairJob *)(base + off_job), 1,
-                                   (int64_t)J.n_tblock * J.n_split, s));
+    RMB_TRY(pair_launch(ctx, precision, sys->geometry == RMB_GEOM_WALL, (const PairJob *)(base + off_job), 1,
+                        (int64_t)J.n_tblock * J.n_split, s));
     RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, nb, mobility_prefactor(sys->a, sys->eta), vel, s));
     return RMB_OK;
 }

@@ -18,6 +18,16 @@ struct rmb_ctx_s {
     size_t pinned_bytes = 0;
     hipStream_t last_stream = nullptr;
     bool any_stream = false;
+    // kernel timing (diagnostics)
+    bool timing = false;
+    struct Pending {
+        int kernel;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> event_pool;
+    double kernel_ms[RMB_KERNEL_COUNT] = {0, 0, 0, 0};
+    int64_t kernel_launches[RMB_KERNEL_COUNT] = {0, 0, 0, 0};
 };
 
 namespace rmb {
@@ -53,6 +63,13 @@ rmb_status check_system(rmb_ctx ctx, const rmb_system *sys, bool need_bodies);
 // Device-side checks of positions (finite; z > 0 above a wall).  Uses
 // `flag_dev` (one int of device memory) and synchronises `s`.
 rmb_status check_positions(rmb_ctx ctx, const rmb_system *sys, int *flag_dev, hipStream_t s);
+
+// Launches the pair kernels for one (precision, geometry) table, bracketed
+// by timing events when the context's kernel timing is on.
+rmb_status pair_launch(rmb_ctx ctx, int precision, bool wall, const PairJob *jobs, int32_t n_jobs,
+                       int64_t n_tiles, hipStream_t s);
+// Accumulates the elapsed time of completed timing events.
+void resolve_timing(rmb_ctx ctx, bool wait);
 
 inline double mobility_prefactor(double a, double eta) {
     return 1.0 / (6.0 * 3.14159265358979323846 * eta * a);

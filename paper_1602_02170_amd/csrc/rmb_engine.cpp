@@ -525,15 +525,15 @@ struct Engine {
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
                 if (!pairs[a][b].empty())
-                    RMB_HIP(ctx, launch_pair_tiles(a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0,
-                                                   (const PairJob *)D(o_pair[a][b]), (int32_t)pairs[a][b].size(),
-                                                   tiles[a][b], s));
+                    RMB_TRY(pair_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0,
+                                        (const PairJob *)D(o_pair[a][b]), (int32_t)pairs[a][b].size(), tiles[a][b], s));
         if (!sd.empty())
             RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));
         if (!orth.empty())
             RMB_HIP(ctx, launch_orthogonalise((const KrylovJob *)D(o_orth), (int32_t)orth.size(), wg_orth, s));
         RMB_HIP(ctx, hipMemcpyAsync(mbox_h, mbox_d, (size_t)max_slot * kSlot * 8, hipMemcpyDeviceToHost, s));
         RMB_HIP(ctx, hipStreamSynchronize(s));
+        if (ctx->timing) resolve_timing(ctx, false);
 
         // --- host updates -------------------------------------------------
         for (Job *J : setup) {
