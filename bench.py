@@ -79,6 +79,47 @@ def matvec_leg(rmb, torch, ctx, S, reps=5):
     return res
 
 
+def factor_leg(rmb, torch, ctx, S, reps=3):
+    """Batched per-body factorisation: 512 x 162-blob shells above the wall
+    (486 x 486 blocks, padded to 512), all blocks in one launch, then the
+    preconditioner applied to 8 right-hand sides."""
+    sus, rhs = S.shells_wall()
+    sysd = rmb.System.from_suspension(sus)
+    r = torch.tensor(rhs, dtype=torch.float64, device="cuda")
+    pc = rmb.Precond(ctx, sysd)  # first build also tunes the panel width
+    pc.close()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        pc = rmb.Precond(ctx, sysd)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+        if _ < reps - 1:
+            pc.close()
+    out = pc.apply(r)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pc.apply(r, out)
+    e1.record()
+    torch.cuda.synchronize()
+    apply_ms = e0.elapsed_time(e1) / reps
+    pc.close()
+    Mp = 512
+    flops = sus.n_bodies * (Mp ** 3 / 3 + 6 * Mp ** 2 + 36 * Mp)  # Cholesky + L^-1 K + Y^T Y
+    ms = min(ts) * 1e3
+    res = {"workload": "512 x 162-blob shells (486 x 486 wall-RPY blocks, padded to 512): assembly, Cholesky, "
+                       "L^-1 K, Schur factor; apply to 8 right-hand sides",
+           "factor_ms": ms, "factor_tflops": flops / (ms * 1e-3) / 1e12,
+           "factor_frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
+           "apply_8rhs_ms": apply_ms, "panel_width": ctx.tuned_panel(Mp)}
+    log(f"  batched factor: {ms:.2f} ms ({res['factor_tflops']:.2f} TFLOP/s), apply 8 rhs {apply_ms:.2f} ms, "
+        f"panel width {res['panel_width']}")
+    return res
+
+
 def serving_leg(rmb, torch, ctx, S, n_req, rate):
     t_gen = time.perf_counter()
     reqs = [S.mixed_wall_request(i) for i in range(n_req)]
@@ -191,6 +232,7 @@ def main():
     ap.add_argument("--rate", type=float, default=50.0)
     ap.add_argument("--no-matvec", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-factor", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="timed solves only (for profiling)")
     args = ap.parse_args()
@@ -251,6 +293,8 @@ def main():
         log(f"  plain FP64 solve: {ms64:.2f} ms/solve ({infos64[-1]['iterations']} iterations)")
         if not args.no_matvec:
             line["matvec"] = matvec_leg(rmb, torch, ctx, S)
+        if not args.no_factor:
+            line["batched_factor"] = factor_leg(rmb, torch, ctx, S)
         if not args.no_serving:
             line["serving"] = serving_leg(rmb, torch, ctx, S, args.requests, args.rate)
         if not args.no_cpu:

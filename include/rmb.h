@@ -99,7 +99,8 @@ typedef struct {
  * handle.  Errors: RMB_EINVAL (null out, bad device), RMB_EDEVICE. */
 rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out);
 
-/* Releases every device allocation the context holds.  Safe on NULL. */
+/* Releases every device allocation the context holds.  Preconditioners and
+ * servers created on the context must be destroyed first.  Safe on NULL. */
 void rmb_ctx_destroy(rmb_ctx ctx);
 
 /* Message of the last failed call on this context (never NULL; "" if none).
@@ -123,6 +124,12 @@ rmb_status rmb_ctx_set_timing(rmb_ctx ctx, int32_t enable);
  * enabled; waits for the recorded events to complete (host arrays of one
  * element each). */
 rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Panel width (16 or 32) the autotuner chose for the large-body
+ * factorisation of padded block size `padded_dim` on this context (the
+ * first factorisation of that size times both and keeps the faster), or 0
+ * if no block of that size has been factorised yet. */
+rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_width);
 
 /* ---------------------------------------------------------------------------
  * Blob mobility product  v = M lambda   (Sec. 2.2.1; eq:RPYTensor and the

@@ -31,7 +31,7 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_mobility_matvec", "rmb_precond_factor", "rmb_precond_apply", "rmb_precond_destroy",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
-           "rmb_ctx_kernel_time"]
+           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -96,6 +96,7 @@ def library(path: str = LIB_PATH):
         L.rmb_server_destroy.restype = None
         L.rmb_ctx_set_timing.argtypes = [vp, i32]
         L.rmb_ctx_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+        L.rmb_ctx_tuned_panel.argtypes = [vp, i32, ctypes.POINTER(i32)]
         _LIB = L
     return _LIB
 
@@ -128,9 +129,18 @@ class Context:
         if st != RMB_OK:
             raise RmbError(st, "rmb_ctx_create failed")
         self.h = h
+        self._children = []  # objects holding device memory of this context
+
+    def _adopt(self, obj):
+        import weakref
+        self._children.append(weakref.ref(obj))
 
     def close(self):
         if getattr(self, "h", None):
+            for ref in getattr(self, "_children", []):
+                child = ref()
+                if child is not None:
+                    child.close()
             self.lib.rmb_ctx_destroy(self.h)
             self.h = None
 
@@ -149,6 +159,12 @@ class Context:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         self.check(self.lib.rmb_ctx_kernel_time(self.h, KERNELS[kernel], ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def tuned_panel(self, padded_dim: int) -> int:
+        """Panel width the autotuner chose for this padded block size (0: none yet)."""
+        w = ctypes.c_int32()
+        self.check(self.lib.rmb_ctx_tuned_panel(self.h, int(padded_dim), ctypes.byref(w)))
+        return w.value
 
     def check(self, st):
         if st != RMB_OK:
@@ -220,6 +236,7 @@ class Precond:
         ctx.check(ctx.lib.rmb_precond_factor(ctx.h, ctypes.byref(system.c), ctypes.byref(h),
                                              _stream(stream)))
         self.h = h
+        ctx._adopt(self)
 
     def apply(self, rhs: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
         """P^-1 applied to each row of rhs (nrhs, 3 Nb + 6 N)."""
@@ -236,9 +253,9 @@ class Precond:
         return out
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx.lib.rmb_precond_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:
@@ -301,6 +318,7 @@ class Server:
         ctx.check(ctx.lib.rmb_server_create(ctx.h, max_active, _stream(stream), ctypes.byref(h)))
         self.h = h
         self.live = {}
+        ctx._adopt(self)
 
     def submit(self, tag: int, system: System, FT: torch.Tensor, slip: torch.Tensor = None, **opts):
         nb, N = system.n_blobs, system.n_bodies
@@ -330,9 +348,9 @@ class Server:
         return out
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and getattr(self.ctx, "h", None):
             self.ctx.lib.rmb_server_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         try:

@@ -22,14 +22,26 @@ struct BodyWork {
     int *flag;          // build status of the body's system (bits 4: not SPD, 8: singular)
 };
 
+// A body whose block exceeds the LDS path: padded to Mp (multiple of 32).
+struct BigBody {
+    BodyWork w;
+    int32_t Mp;
+    int32_t pad;
+};
+
+inline bool is_large_body(int64_t n_blobs) { return 3 * n_blobs > kSmallBodyMaxM; }
+inline int64_t padded_dim(int64_t n_blobs) { return (3 * n_blobs + 31) / 32 * 32; }
+
+// Factor storage of one body (doubles): L, Y (m x 6), Sc (6 x 6); large
+// bodies use the padded dimension.
 inline int64_t factor_doubles(int64_t n_blobs) {
-    const int64_t m = 3 * n_blobs;
+    const int64_t m = is_large_body(n_blobs) ? padded_dim(n_blobs) : 3 * n_blobs;
     return m * m + 6 * m + 36;
 }
 
 // P^-1 applied to `nrhs` saddle vectors of one system (vector r at in + r*ld).
 struct PrecondApplyJob {
-    const BodyWork *items;  // the system's bodies
+    const BodyWork *items;  // the system's bodies (BigBody records for the large-body kernel)
     const double *in;
     double *out;
     int64_t ld;             // stride between right-hand sides
@@ -60,6 +72,13 @@ struct SaddleJob {
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s);
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s);
+// Large bodies: assembly, MFMA left-looking Cholesky with panel width 16
+// (variant 0) or 32 (variant 1), projection; and the apply (<= 8 rhs per
+// workgroup).
+int large_panel_width(int variant);
+hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int max_Mp, int variant, hipStream_t s);
+hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
+                                      int max_Mp, int variant, hipStream_t s);
 hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_blocks, int64_t n_bodies,
                          hipStream_t s);
 

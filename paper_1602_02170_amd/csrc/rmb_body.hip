@@ -10,66 +10,10 @@
 //   t = L^-1 s,  U = S^-1 (F - Y^T t),  lambda = L^-T (t + Y U).
 #include <cmath>
 
+#include "rmb_blocks.h"
 #include "rmb_body.h"
 
 namespace rmb {
-
-// ---------------------------------------------------------------------------
-// 3x3 pair block in FP64 (assembly of per-body blocks)
-// ---------------------------------------------------------------------------
-
-// M_ij without the 1/(6 pi eta a) prefactor; row = velocity of i, column =
-// force on j.  Same formulas as the pair kernels (eq:RPYTensor plus the
-// wall image correction).
-__device__ void pair_block_f64(const double ri[3], const double rj[3], double a, bool wall,
-                               double B[9]) {
-    const double rx = ri[0] - rj[0], ry = ri[1] - rj[1], rz = ri[2] - rj[2];
-    const double d2 = rx * rx + ry * ry + rz * rz;
-    const double d = sqrt(d2);
-    double ciso, crr;  // crr multiplies r r^T (already divided by d^2)
-    if (d > 2.0 * a) {
-        const double t = a / d, t2 = t * t;
-        ciso = t * (0.75 + 0.5 * t2);
-        crr = t * (0.75 - 1.5 * t2) / d2;
-    } else {
-        ciso = 1.0 - 9.0 * d / (32.0 * a);
-        crr = d > 0.0 ? 3.0 / (32.0 * a * d) : 0.0;
-    }
-    const double r[3] = {rx, ry, rz};
-    for (int p = 0; p < 3; ++p)
-        for (int q = 0; q < 3; ++q) B[3 * p + q] = (p == q ? ciso : 0.0) + crr * r[p] * r[q];
-    if (wall) {
-        const double R[3] = {rx, ry, ri[2] + rj[2]};
-        const double L = sqrt(R[0] * R[0] + R[1] * R[1] + R[2] * R[2]);
-        const double e[3] = {R[0] / L, R[1] / L, R[2] / L};
-        const double xw = a / L, hh = rj[2] / L, ez = e[2];
-        const double xw2 = xw * xw, xw4 = xw2 * xw2, ez2 = ez * ez;
-        const double T = hh * hh - ez * hh;
-        const double c1 = 0.25 * xw * (-3.0 + 6.0 * T + xw2 * (6.0 * ez2 - 2.0) + xw4 * (2.0 - 10.0 * ez2));
-        const double c2 = 0.25 * xw * (-3.0 - 18.0 * T + xw2 * (6.0 - 30.0 * ez2) + xw4 * (70.0 * ez2 - 10.0));
-        const double c3 = xw * (1.5 * hh * (1.0 - 6.0 * ez2 + 6.0 * ez * hh) +
-                                ez * (xw2 * (15.0 * ez2 - 3.0) + xw4 * (10.0 - 35.0 * ez2)));
-        const double c4 = xw * (1.5 * hh - 5.0 * ez * xw4);
-        const double c5 = xw * (-3.0 * (hh * hh + ez2 * xw2) + xw4 * (15.0 * ez2 - 2.0));
-        for (int p = 0; p < 3; ++p)
-            for (int q = 0; q < 3; ++q)
-                B[3 * p + q] += (p == q ? c1 : 0.0) + c2 * e[p] * e[q] + (q == 2 ? c3 * e[p] : 0.0) +
-                                (p == 2 ? c4 * e[q] : 0.0) + (p == 2 && q == 2 ? c5 : 0.0);
-    }
-}
-
-// K_p row block of blob i: velocity of blob i per unit body motion U_p,
-// K[c][k] for c in 0..2 (velocity component), k in 0..5 (u then omega):
-// u_c + (omega x d)_c with d = r_i - q_p.
-__device__ __forceinline__ double K_entry(const double d[3], int c, int k) {
-    if (k < 3) return c == k ? 1.0 : 0.0;
-    // (omega x d)_c = eps_{c,l,m} omega_l d_m ; derivative w.r.t. omega_l (l = k-3)
-    const int l = k - 3;
-    if (c == l) return 0.0;
-    const int m = 3 - c - l;
-    const double sgn = ((l - c + 3) % 3 == 1) ? 1.0 : -1.0;  // eps_{c,l,m}
-    return sgn * d[m];
-}
 
 // ---------------------------------------------------------------------------
 // small-body preconditioner: build

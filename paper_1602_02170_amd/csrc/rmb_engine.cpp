@@ -28,9 +28,11 @@ using namespace rmb;
 struct rmb_precond_s {
     rmb_ctx ctx = nullptr;
     int64_t nb = 0, N = 0;
-    int max_m = 0;
+    int max_m = 0, max_Mp = 0, variant = 0;
+    int32_t n_small = 0, n_large = 0;
     char *dbuf = nullptr;
     BodyWork *items_d = nullptr;
+    BigBody *bigs_d = nullptr;
     double *factor = nullptr;
     int *flag_d = nullptr;
 };
@@ -43,15 +45,22 @@ static double now_s() {
 
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// Host-side description of a system's bodies: factor offsets and sizes.
-static void body_items(const rmb_system &sys, const int64_t *off, double *factor, int *flag,
-                       std::vector<BodyWork> &items, int *max_m) {
-    items.resize(sys.n_bodies);
+// Host-side description of a system's bodies, split into bodies handled in
+// LDS and large bodies (padded, MFMA path), with their factor offsets.
+struct BodyLists {
+    std::vector<BodyWork> small;
+    std::vector<BigBody> large;
+    int max_m = 0, max_Mp = 0;
+};
+
+static void body_items(const rmb_system &sys, const int64_t *off, double *factor, int *flag, BodyLists &out) {
+    out.small.clear();
+    out.large.clear();
+    out.max_m = out.max_Mp = 0;
     int64_t fo = 0;
-    *max_m = 0;
     const double pref = mobility_prefactor(sys.a, sys.eta);
     for (int64_t p = 0; p < sys.n_bodies; ++p) {
-        BodyWork &b = items[p];
+        BodyWork b{};
         b.pos = sys.pos;
         b.q = sys.q + 3 * p;
         b.factor = factor ? factor + fo : nullptr;
@@ -59,13 +68,26 @@ static void body_items(const rmb_system &sys, const int64_t *off, double *factor
         b.n_blobs = (int32_t)(off[p + 1] - off[p]);
         b.body = (int32_t)p;
         b.wall = sys.geometry == RMB_GEOM_WALL;
-        b.pad = 0;
         b.a = sys.a;
         b.pref = pref;
         b.flag = flag;
         fo += factor_doubles(b.n_blobs);
-        *max_m = std::max(*max_m, 3 * b.n_blobs);
+        if (is_large_body(b.n_blobs)) {
+            BigBody g{};
+            g.w = b;
+            g.Mp = (int32_t)padded_dim(b.n_blobs);
+            out.large.push_back(g);
+            out.max_Mp = std::max(out.max_Mp, g.Mp);
+        } else {
+            out.small.push_back(b);
+            out.max_m = std::max(out.max_m, 3 * b.n_blobs);
+        }
     }
+}
+
+static void set_flag(BodyLists &L, int *flag) {
+    for (auto &b : L.small) b.flag = flag;
+    for (auto &g : L.large) g.w.flag = flag;
 }
 
 static int64_t factor_total(const int64_t *off, int64_t N) {
@@ -74,11 +96,49 @@ static int64_t factor_total(const int64_t *off, int64_t N) {
     return t;
 }
 
+// Largest padded block of the large-body path: its apply keeps Mp x 8
+// doubles of right-hand sides in LDS (48 KiB at 768), beside the 8 KiB
+// diagonal block (256 blobs per body).
+constexpr int kLargeBodyMaxMp = 768;
+
 static rmb_status check_body_sizes(rmb_ctx ctx, const int64_t *off, int64_t N) {
     for (int64_t p = 0; p < N; ++p)
-        if (3 * (off[p + 1] - off[p]) > kSmallBodyMaxM)
-            return fail(ctx, RMB_EINVAL, "body %lld has %lld blobs; bodies above %d blobs are not supported yet",
-                        (long long)p, (long long)(off[p + 1] - off[p]), kSmallBodyMaxM / 3);
+        if (padded_dim(off[p + 1] - off[p]) > kLargeBodyMaxMp)
+            return fail(ctx, RMB_EINVAL, "body %lld has %lld blobs; at most %d blobs per body are supported",
+                        (long long)p, (long long)(off[p + 1] - off[p]), kLargeBodyMaxMp / 3);
+    return RMB_OK;
+}
+
+// Panel width of the large-body factorisation for padded size Mp, chosen by
+// timing both variants on the first batch of that size (cached per context).
+static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, int max_Mp, hipStream_t s,
+                              int *variant_out) {
+    auto it = ctx->tuned_panel.find(max_Mp);
+    if (it != ctx->tuned_panel.end()) {
+        *variant_out = it->second;
+        RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, it->second, s));
+        return RMB_OK;
+    }
+    float best_ms = 0.f;
+    int best = 0;
+    hipEvent_t e0, e1;
+    RMB_HIP(ctx, hipEventCreate(&e0));
+    RMB_HIP(ctx, hipEventCreate(&e1));
+    for (int v = 0; v < 2; ++v) {
+        RMB_HIP(ctx, hipEventRecord(e0, s));
+        RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, v, s));
+        RMB_HIP(ctx, hipEventRecord(e1, s));
+        RMB_HIP(ctx, hipEventSynchronize(e1));
+        float ms = 0.f;
+        RMB_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+        ctx->tune_log.push_back({max_Mp, v, ms});
+        if (v == 0 || ms < best_ms) best_ms = ms, best = v;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->tuned_panel[max_Mp] = best;
+    if (best != 1) RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, best, s));
+    *variant_out = best;
     return RMB_OK;
 }
 
@@ -111,7 +171,10 @@ struct Job {
     double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *V = nullptr;
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
     int slot = -1;
-    std::vector<BodyWork> items_h;
+    BodyLists lists;
+    BigBody *bigs_d = nullptr;
+    int32_t n_small = 0, n_large = 0;
+    int max_Mp = 0, variant = 0;
     // state
     Phase phase = SETUP;
     int k = 0, iters = 0, cycles = 0, mv64 = 0, mv32 = 0;
@@ -129,7 +192,7 @@ static size_t job_bytes(Job &J) {
     t += al((N + 1) * 8) + al(nb * 4) + al(nb * sizeof(SrcF64)) + al((size_t)J.pj.n_split * nb * 24);
     t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
     t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8);
-    if (!J.pc) t += al(factor_total(J.off.data(), N) * 8) + al(N * sizeof(BodyWork));
+    if (!J.pc) t += al(factor_total(J.off.data(), N) * 8) + al(N * sizeof(BodyWork)) + al(N * sizeof(BigBody));
     return t;
 }
 
@@ -156,9 +219,11 @@ static void job_carve(Job &J) {
     if (!J.pc) {
         J.factor = (double *)take(factor_total(J.off.data(), N) * 8);
         J.items_d = (BodyWork *)take(N * sizeof(BodyWork));
+        J.bigs_d = (BigBody *)take(N * sizeof(BigBody));
     } else {
         J.factor = J.pc->factor;
         J.items_d = J.pc->items_d;
+        J.bigs_d = J.pc->bigs_d;
     }
 }
 
@@ -293,8 +358,19 @@ struct Engine {
             J->t_admit = now_s();
             J->pj.src = J->src;
             J->pj.partial = J->partial;
-            if (!J->pc) body_items(J->sys, J->off.data(), J->factor, nullptr, J->items_h, &J->max_m);
-            else J->max_m = J->pc->max_m;
+            if (!J->pc) {
+                body_items(J->sys, J->off.data(), J->factor, nullptr, J->lists);
+                J->n_small = (int32_t)J->lists.small.size();
+                J->n_large = (int32_t)J->lists.large.size();
+                J->max_m = J->lists.max_m;
+                J->max_Mp = J->lists.max_Mp;
+            } else {
+                J->n_small = J->pc->n_small;
+                J->n_large = J->pc->n_large;
+                J->max_m = J->pc->max_m;
+                J->max_Mp = J->pc->max_Mp;
+                J->variant = J->pc->variant;
+            }
             active.push_back(J);
         }
     }
@@ -348,25 +424,20 @@ struct Engine {
         // precond build items (setup jobs without external factors)
         std::vector<BodyWork> build_items;
         int build_max_m = 0;
-        for (Job *J : setup) {
-            if (J->pc) continue;
-            for (auto &b : J->items_h) {
-                b.flag = flag_d(J);
-                build_items.push_back(b);
-            }
-            build_max_m = std::max(build_max_m, J->max_m);
-        }
-        size_t o_build = build_items.empty() ? 0 : st.put(build_items.data(), build_items.size() * sizeof(BodyWork));
         // setup items copies (persistent per job): offsets into staging
-        std::vector<size_t> o_items(setup.size(), 0), o_off(setup.size(), 0);
+        std::vector<size_t> o_items(setup.size(), 0), o_bigs(setup.size(), 0), o_off(setup.size(), 0);
         for (size_t i = 0; i < setup.size(); ++i) {
             Job *J = setup[i];
             if (!J->pc) {
-                for (auto &b : J->items_h) b.flag = flag_d(J);
-                o_items[i] = st.put(J->items_h.data(), J->items_h.size() * sizeof(BodyWork));
+                set_flag(J->lists, flag_d(J));
+                for (auto &b : J->lists.small) build_items.push_back(b);
+                build_max_m = std::max(build_max_m, J->max_m);
+                if (J->n_small) o_items[i] = st.put(J->lists.small.data(), J->n_small * sizeof(BodyWork));
+                if (J->n_large) o_bigs[i] = st.put(J->lists.large.data(), J->n_large * sizeof(BigBody));
             }
             o_off[i] = st.put(J->off.data(), J->off.size() * sizeof(int64_t));
         }
+        size_t o_build = build_items.empty() ? 0 : st.put(build_items.data(), build_items.size() * sizeof(BodyWork));
 
         // combine (finish): coefficients y
         std::vector<KrylovJob> comb;
@@ -374,22 +445,33 @@ struct Engine {
         int64_t wg_comb = 0;
         for (Job *J : finish) o_coef.push_back(st.put(J->y.data(), J->y.size() * 8));
         // precond apply: finish (z -> w) then iter (V_k -> z)
-        std::vector<PrecondApplyJob> app;
-        int64_t wg_app = 0;
-        int app_max_m = 0;
+        std::vector<PrecondApplyJob> app, appL[2];
+        int64_t wg_app = 0, wg_appL[2] = {0, 0};
+        int app_max_m = 0, appL_max_Mp[2] = {0, 0};
         auto add_app = [&](Job *J, const double *in, double *out) {
             PrecondApplyJob a{};
-            a.items = J->items_d;
             a.in = in;
             a.out = out;
             a.ld = J->n;
             a.nb3 = 3 * J->nb;
-            a.wg_begin = wg_app;
-            a.n_items = (int32_t)J->N;
             a.nrhs = 1;
-            app.push_back(a);
-            wg_app += J->N;
-            app_max_m = std::max(app_max_m, J->max_m);
+            if (J->n_small) {
+                a.items = J->items_d;
+                a.wg_begin = wg_app;
+                a.n_items = J->n_small;
+                app.push_back(a);
+                wg_app += J->n_small;
+                app_max_m = std::max(app_max_m, J->max_m);
+            }
+            if (J->n_large) {
+                const int v = J->variant;
+                a.items = (const BodyWork *)J->bigs_d;
+                a.wg_begin = wg_appL[v];
+                a.n_items = J->n_large;
+                appL[v].push_back(a);
+                wg_appL[v] += J->n_large;
+                appL_max_Mp[v] = std::max(appL_max_Mp[v], J->max_Mp);
+            }
         };
         for (Job *J : finish) add_app(J, J->z, J->w);
         for (Job *J : iter) add_app(J, J->V + (size_t)J->k * J->ldv, J->z);
@@ -480,6 +562,9 @@ struct Engine {
         }
 
         size_t o_app = app.empty() ? 0 : st.put(app.data(), app.size() * sizeof(PrecondApplyJob));
+        size_t o_appL[2];
+        for (int v = 0; v < 2; ++v)
+            o_appL[v] = appL[v].empty() ? 0 : st.put(appL[v].data(), appL[v].size() * sizeof(PrecondApplyJob));
         size_t o_pk = pk.empty() ? 0 : st.put(pk.data(), pk.size() * sizeof(PackJob));
         size_t o_pair[2][2];
         for (int a = 0; a < 2; ++a)
@@ -506,8 +591,11 @@ struct Engine {
             RMB_HIP(ctx, hipMemsetAsync(flag_d(J), 0, sizeof(int), s));
             RMB_HIP(ctx, launch_validate_positions(J->sys.pos, J->nb, J->sys.geometry == RMB_GEOM_WALL, flag_d(J), s));
             RMB_HIP(ctx, hipMemcpyAsync(J->off_d, D(o_off[i]), J->off.size() * 8, hipMemcpyDeviceToDevice, s));
-            if (!J->pc)
-                RMB_HIP(ctx, hipMemcpyAsync(J->items_d, D(o_items[i]), J->items_h.size() * sizeof(BodyWork),
+            if (!J->pc && J->n_small)
+                RMB_HIP(ctx, hipMemcpyAsync(J->items_d, D(o_items[i]), J->n_small * sizeof(BodyWork),
+                                            hipMemcpyDeviceToDevice, s));
+            if (!J->pc && J->n_large)
+                RMB_HIP(ctx, hipMemcpyAsync(J->bigs_d, D(o_bigs[i]), J->n_large * sizeof(BigBody),
                                             hipMemcpyDeviceToDevice, s));
             RMB_HIP(ctx, launch_blob_body(J->off_d, J->N, J->blob_body, s));
             RMB_HIP(ctx, launch_build_rhs(J->FT, J->slip, J->nb, J->N, J->b, s));
@@ -516,10 +604,16 @@ struct Engine {
         if (!build_items.empty())
             RMB_HIP(ctx, launch_precond_build_small((const BodyWork *)D(o_build), (int32_t)build_items.size(),
                                                     build_max_m, s));
+        for (Job *J : setup)
+            if (!J->pc && J->n_large) RMB_TRY(build_large(ctx, J->bigs_d, J->n_large, J->max_Mp, s, &J->variant));
         if (!comb.empty()) RMB_HIP(ctx, launch_combine((const KrylovJob *)D(o_comb), (int32_t)comb.size(), wg_comb, s));
         if (!app.empty())
             RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)D(o_app), (int32_t)app.size(), wg_app, 1,
                                                     app_max_m, s));
+        for (int v = 0; v < 2; ++v)
+            if (!appL[v].empty())
+                RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)D(o_appL[v]), (int32_t)appL[v].size(),
+                                                        wg_appL[v], 1, appL_max_Mp[v], v, s));
         if (!axp.empty()) RMB_HIP(ctx, launch_axpy((const KrylovJob *)D(o_axp), (int32_t)axp.size(), wg_axp, s));
         if (!pk.empty()) RMB_HIP(ctx, launch_pack_table((const PackJob *)D(o_pk), (int32_t)pk.size(), wg_pk, s));
         for (int a = 0; a < 2; ++a)
@@ -655,16 +749,22 @@ rmb_status rmb_precond_factor(rmb_ctx ctx, const rmb_system *sys, rmb_precond *o
     pc->N = sys->n_bodies;
     const size_t fbytes = al(factor_total(sys->body_off, sys->n_bodies) * 8);
     const size_t ibytes = al(sys->n_bodies * sizeof(BodyWork));
-    pc->dbuf = (char *)ctx->arena->alloc(fbytes + ibytes + 256);
+    const size_t gbytes = al(sys->n_bodies * sizeof(BigBody));
+    pc->dbuf = (char *)ctx->arena->alloc(fbytes + ibytes + gbytes + 256);
     if (!pc->dbuf) {
         delete pc;
-        return fail(ctx, RMB_ENOMEM, "preconditioner factors (%zu bytes) exceed the budget", fbytes + ibytes);
+        return fail(ctx, RMB_ENOMEM, "preconditioner factors (%zu bytes) exceed the budget", fbytes + ibytes + gbytes);
     }
     pc->factor = (double *)pc->dbuf;
     pc->items_d = (BodyWork *)(pc->dbuf + fbytes);
-    pc->flag_d = (int *)(pc->dbuf + fbytes + ibytes);
-    std::vector<BodyWork> items;
-    body_items(*sys, sys->body_off, pc->factor, pc->flag_d, items, &pc->max_m);
+    pc->bigs_d = (BigBody *)(pc->dbuf + fbytes + ibytes);
+    pc->flag_d = (int *)(pc->dbuf + fbytes + ibytes + gbytes);
+    BodyLists lists;
+    body_items(*sys, sys->body_off, pc->factor, pc->flag_d, lists);
+    pc->n_small = (int32_t)lists.small.size();
+    pc->n_large = (int32_t)lists.large.size();
+    pc->max_m = lists.max_m;
+    pc->max_Mp = lists.max_Mp;
     auto cleanup = [&](rmb_status st) {
         ctx->arena->free(pc->dbuf);
         delete pc;
@@ -672,17 +772,23 @@ rmb_status rmb_precond_factor(rmb_ctx ctx, const rmb_system *sys, rmb_precond *o
     };
     rmb_status st = check_positions(ctx, sys, pc->flag_d, s);
     if (st != RMB_OK) return cleanup(st);
-    void *h = nullptr;
-    st = pinned(ctx, items.size() * sizeof(BodyWork), &h);
+    const size_t hs = lists.small.size() * sizeof(BodyWork), hl = lists.large.size() * sizeof(BigBody);
+    char *h = nullptr;
+    st = pinned(ctx, hs + hl + 64, (void **)&h);
     if (st != RMB_OK) return cleanup(st);
-    memcpy(h, items.data(), items.size() * sizeof(BodyWork));
+    memcpy(h, lists.small.data(), hs);
+    memcpy(h + hs, lists.large.data(), hl);
     if (hipMemsetAsync(pc->flag_d, 0, sizeof(int), s) != hipSuccess ||
-        hipMemcpyAsync(pc->items_d, h, items.size() * sizeof(BodyWork), hipMemcpyHostToDevice, s) != hipSuccess ||
-        launch_precond_build_small(pc->items_d, (int32_t)items.size(), pc->max_m, s) != hipSuccess)
+        (hs && hipMemcpyAsync(pc->items_d, h, hs, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (hl && hipMemcpyAsync(pc->bigs_d, h + hs, hl, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        launch_precond_build_small(pc->items_d, pc->n_small, pc->max_m, s) != hipSuccess)
         return cleanup(fail(ctx, RMB_EDEVICE, "preconditioner build launch failed"));
-    int *hf = nullptr;
-    if (pinned(ctx, sizeof(int), (void **)&hf) != RMB_OK ||
-        hipMemcpyAsync(hf, pc->flag_d, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    if (pc->n_large) {
+        st = build_large(ctx, pc->bigs_d, pc->n_large, pc->max_Mp, s, &pc->variant);
+        if (st != RMB_OK) return cleanup(st);
+    }
+    int *hf = (int *)(h + hs + hl);
+    if (hipMemcpyAsync(hf, pc->flag_d, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return cleanup(fail(ctx, RMB_EDEVICE, "preconditioner build failed"));
     if (*hf & 4) return cleanup(fail(ctx, RMB_ENOTSPD, "a body's mobility block is not positive definite"));
@@ -700,21 +806,36 @@ rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, co
     if (nrhs < 0 || nrhs > 65535) return fail(ctx, RMB_EINVAL, "nrhs out of range");
     if (nrhs == 0) return RMB_OK;
     if (!in || !out || in == out) return fail(ctx, RMB_EINVAL, "in and out must be distinct device buffers");
-    PrecondApplyJob a{};
-    a.items = pc->items_d;
-    a.in = in;
-    a.out = out;
-    a.ld = 3 * pc->nb + 6 * pc->N;
-    a.nb3 = 3 * pc->nb;
-    a.wg_begin = 0;
-    a.n_items = (int32_t)pc->N;
-    a.nrhs = nrhs;
+    PrecondApplyJob a[2] = {};
+    for (int k = 0; k < 2; ++k) {
+        a[k].in = in;
+        a[k].out = out;
+        a[k].ld = 3 * pc->nb + 6 * pc->N;
+        a[k].nb3 = 3 * pc->nb;
+        a[k].wg_begin = 0;
+        a[k].nrhs = nrhs;
+    }
+    a[0].items = pc->items_d;
+    a[0].n_items = pc->n_small;
+    a[1].items = (const BodyWork *)pc->bigs_d;
+    a[1].n_items = pc->n_large;
     void *d = nullptr, *h = nullptr;
     RMB_TRY(scratch(ctx, sizeof a, &d));
     RMB_TRY(pinned(ctx, sizeof a, &h));
-    memcpy(h, &a, sizeof a);
+    memcpy(h, a, sizeof a);
     RMB_HIP(ctx, hipMemcpyAsync(d, h, sizeof a, hipMemcpyHostToDevice, s));
-    RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)d, 1, pc->N, nrhs, pc->max_m, s));
+    if (pc->n_small)
+        RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)d, 1, pc->n_small, nrhs, pc->max_m, s));
+    if (pc->n_large)
+        RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)d + 1, 1, pc->n_large, nrhs, pc->max_Mp,
+                                                pc->variant, s));
+    return RMB_OK;
+}
+
+rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_width) {
+    if (!ctx || !panel_width) return RMB_EINVAL;
+    auto it = ctx->tuned_panel.find(padded_dim);
+    *panel_width = it == ctx->tuned_panel.end() ? 0 : large_panel_width(it->second);
     return RMB_OK;
 }
 
