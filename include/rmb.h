@@ -125,6 +125,12 @@ rmb_status rmb_ctx_set_timing(rmb_ctx ctx, int32_t enable);
  * element each). */
 rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, int64_t *launches);
 
+/* How the mobility product of nb blobs is evaluated: *symmetric = 1 when
+ * each pair block is evaluated once and applied to both blobs (systems of at
+ * least 1024 blobs; *block = its block size), 0 for the one-sided kernel
+ * (*block = number of source splits).  A function of nb only. */
+rmb_status rmb_pair_plan(int64_t nb, int32_t *symmetric, int32_t *block);
+
 /* Panel width (16 or 32) the autotuner chose for the large-body
  * factorisation of padded block size `padded_dim` on this context (the
  * first factorisation of that size times both and keeps the faster), or 0

@@ -31,7 +31,7 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_mobility_matvec", "rmb_precond_factor", "rmb_precond_apply", "rmb_precond_destroy",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
-           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel"]
+           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_pair_plan"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -97,8 +97,18 @@ def library(path: str = LIB_PATH):
         L.rmb_ctx_set_timing.argtypes = [vp, i32]
         L.rmb_ctx_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.rmb_ctx_tuned_panel.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.rmb_pair_plan.argtypes = [i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _LIB = L
     return _LIB
+
+
+def pair_plan(nb: int):
+    """(symmetric, block) of the mobility product of nb blobs (see rmb_pair_plan)."""
+    sym, blk = ctypes.c_int32(), ctypes.c_int32()
+    st = library().rmb_pair_plan(int(nb), ctypes.byref(sym), ctypes.byref(blk))
+    if st != RMB_OK:
+        raise RmbError(st, "rmb_pair_plan failed")
+    return bool(sym.value), blk.value
 
 
 def _stream(stream=None):

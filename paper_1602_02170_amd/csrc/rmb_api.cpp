@@ -133,6 +133,23 @@ rmb_status pair_launch(rmb_ctx ctx, int precision, bool wall, const PairJob *job
     return RMB_OK;
 }
 
+rmb_status sym_launch(rmb_ctx ctx, int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs,
+                      int64_t n_tiles, hipStream_t s) {
+    const int kid = (precision == RMB_PREC_FP32_PAIRS ? 0 : 2) + (wall ? 0 : 1);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (ctx->timing) {
+        a = take_event(ctx);
+        b = take_event(ctx);
+        if (a && b) RMB_HIP(ctx, hipEventRecord(a, s));
+    }
+    RMB_HIP(ctx, launch_pair_sym(precision, wall, B, jobs, n_jobs, n_tiles, s));
+    if (ctx->timing && a && b) {
+        RMB_HIP(ctx, hipEventRecord(b, s));
+        ctx->pending.push_back({kid, a, b});
+    }
+    return RMB_OK;
+}
+
 void resolve_timing(rmb_ctx ctx, bool wait) {
     size_t keep = 0;
     for (size_t i = 0; i < ctx->pending.size(); ++i) {
@@ -170,6 +187,23 @@ rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
     c->device = device;
     c->arena = new Arena(hbm_budget_bytes ? hbm_budget_bytes : (size_t(16) << 30));
     *out = c;
+    return RMB_OK;
+}
+
+rmb_status rmb_pair_plan(int64_t nb, int32_t *symmetric, int32_t *block) {
+    if (nb < 1 || !symmetric || !block) return RMB_EINVAL;
+    if (use_sym(nb)) {
+        int32_t B, T;
+        sym_plan(nb, &B, &T);
+        *symmetric = 1;
+        *block = B;
+    } else {
+        int32_t S, Tb;
+        int64_t chunk;
+        split_plan(nb, &S, &chunk, &Tb);
+        *symmetric = 0;
+        *block = S;
+    }
     return RMB_OK;
 }
 
@@ -217,9 +251,45 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     if ((const void *)lambda == (const void *)vel) return fail(ctx, RMB_EINVAL, "vel must not alias lambda");
 
     const int64_t nb = sys->n_blobs;
+    const size_t rec = precision == RMB_PREC_FP32_PAIRS ? sizeof(SrcF32) : sizeof(SrcF64);
+    const bool wall = sys->geometry == RMB_GEOM_WALL;
+    const double pref = mobility_prefactor(sys->a, sys->eta);
+    if (use_sym(nb)) {
+        // scratch layout: [flag | job | sources | vpart, upart]
+        SymJob J{};
+        sym_plan(nb, &J.B, &J.n_blk);
+        const int64_t tiles = sym_tiles(nb);
+        size_t off_job = 256, off_src = off_job + 256;
+        size_t off_part = off_src + (nb * rec + 255) / 256 * 256;
+        size_t total = off_part + sym_partial_doubles(nb) * sizeof(double);
+        char *base = nullptr;
+        RMB_TRY(scratch(ctx, total, (void **)&base));
+        RMB_TRY(check_positions(ctx, sys, (int *)base, s));
+        J.tpos = sys->pos;
+        J.lam = lambda;
+        J.src = base + off_src;
+        J.vpart = (double *)(base + off_part);
+        J.upart = J.vpart + (size_t)tiles * J.B * 3;
+        J.vel = vel;
+        J.nb = nb;
+        J.wg_begin = 0;
+        J.red_begin = 0;
+        J.a = sys->a;
+        J.four_a2 = 4.0 * sys->a * sys->a;
+        J.k_near_iso = 9.0 / (32.0 * sys->a);
+        J.k_near_rr = 3.0 / (32.0 * sys->a);
+        J.pref = pref;
+        SymJob *hJ = nullptr;
+        RMB_TRY(pinned(ctx, sizeof(SymJob), (void **)&hJ));
+        *hJ = J;
+        RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(SymJob), hipMemcpyHostToDevice, s));
+        RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
+        RMB_TRY(sym_launch(ctx, precision, wall, J.B, (const SymJob *)(base + off_job), 1, tiles, s));
+        RMB_HIP(ctx, launch_sym_reduce((const SymJob *)(base + off_job), 1, sym_reduce_groups(nb), s));
+        return RMB_OK;
+    }
     PairJob J;
     pair_job_init(&J, sys->pos, nullptr, nullptr, nb, sys->a);
-    const size_t rec = precision == RMB_PREC_FP32_PAIRS ? sizeof(SrcF32) : sizeof(SrcF64);
     // scratch layout: [flag | job | sources | partials]
     size_t off_job = 256, off_src = off_job + 256;
     size_t off_part = off_src + (nb * rec + 255) / 256 * 256;
@@ -236,9 +306,9 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     *hJ = J;
     RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(PairJob), hipMemcpyHostToDevice, s));
     RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
-    RMB_TRY(pair_launch(ctx, precision, sys->geometry == RMB_GEOM_WALL, (const PairJob *)(base + off_job), 1,
+    RMB_TRY(pair_launch(ctx, precision, wall, (const PairJob *)(base + off_job), 1,
                         (int64_t)J.n_tblock * J.n_split, s));
-    RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, nb, mobility_prefactor(sys->a, sys->eta), vel, s));
+    RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, nb, pref, vel, s));
     return RMB_OK;
 }
 

@@ -30,10 +30,14 @@ void *Arena::alloc(size_t bytes) {
             return b.base + b.segs[k].off;
         }
     }
-    // new block
+    // new block; when the budget is reached, give completely free blocks
+    // back first (they may be too small for this request)
     size_t want = std::max(bytes, kMinBlock);
     if (reserved_ + want > budget_) want = bytes;
-    if (reserved_ + want > budget_) return nullptr;
+    if (reserved_ + want > budget_) {
+        release_free_blocks();
+        if (reserved_ + want > budget_) return nullptr;
+    }
     void *p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess || p == nullptr) {
         (void)hipGetLastError();
@@ -46,6 +50,19 @@ void *Arena::alloc(size_t bytes) {
     blocks_.push_back(std::move(b));
     in_use_ += bytes;
     return p;
+}
+
+void Arena::release_free_blocks() {
+    std::vector<Block> keep;
+    for (auto &b : blocks_) {
+        if (b.segs.size() == 1 && !b.segs[0].used) {
+            (void)hipFree(b.base);
+            reserved_ -= b.size;
+        } else {
+            keep.push_back(std::move(b));
+        }
+    }
+    blocks_ = std::move(keep);
 }
 
 void Arena::free(void *p) {

@@ -12,7 +12,8 @@ constexpr int kSmallBodyMaxM = 84;  // 28 blobs: build workspace (m^2 + 6m + 36 
 struct BodyWork {
     const double *pos;  // system's blob positions [nb][3]
     const double *q;    // this body's tracking point (3 doubles)
-    double *factor;     // L (m x m, row-major lower), Y (m x 6), Sc (6 x 6)
+    double *factor;     // LDS path: Li = L^-1 (col-major), Y (m x 6), S^-1 (6 x 6);
+                        // large path: L (padded, col-major), Y, Sc (Cholesky of S)
     int64_t blob0;      // first blob of the body
     int32_t n_blobs;
     int32_t body;       // body index within its system
@@ -86,7 +87,7 @@ hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_b
 // Krylov vector kernels
 // ---------------------------------------------------------------------------
 
-constexpr int kSeg = 2048;  // vector elements per workgroup (256 threads x 8)
+constexpr int kSeg = 512;  // vector elements per workgroup (256 threads x 2)
 
 struct KrylovJob {
     double *V;          // basis vectors, vector k at V + k*ldv
@@ -96,6 +97,8 @@ struct KrylovJob {
     double *P1, *P2;    // partial dots [(kmax+1) x n_seg]
     double *P3;         // partial squared norms [n_seg]
     double *hcol;       // output: h[0..kk-1] then the norm at hcol[kk]
+    double *hred;       // reduced coefficients: h1 [256], h2 [256], norm [1]
+    unsigned *counter;  // zero between launches; counts finished workgroups
     const double *coef; // combine coefficients (kk of them)
     double *x;          // axpy target
     const double *t;    // axpy source
@@ -112,8 +115,6 @@ hipError_t launch_orthogonalise(const KrylovJob *jobs, int32_t n_jobs, int64_t n
 hipError_t launch_combine(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
 // x += t
 hipError_t launch_axpy(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
-// ||w||^2 partials then hcol[0] = ||w|| (no normalisation)
-hipError_t launch_norm(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // misc per-system kernels

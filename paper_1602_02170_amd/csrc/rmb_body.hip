@@ -5,9 +5,11 @@
 // body's 3n x 3n mobility block fits in LDS.
 //
 // Preconditioner of body p (m = 3 n_p):
-//   M_pp = L L^T,  Y = L^-1 K_p (m x 6),  S = Y^T Y = K_p^T M_pp^-1 K_p = Sc Sc^T
+//   M_pp = L L^T,  Y = L^-1 K_p (m x 6),  S = Y^T Y = K_p^T M_pp^-1 K_p
 // and for a right-hand side (s_p, bottom_p) with F_p = -bottom_p:
 //   t = L^-1 s,  U = S^-1 (F - Y^T t),  lambda = L^-T (t + Y U).
+// Bodies on the LDS path store Li = L^-1 (column-major), Y (row-major) and
+// S^-1, so that an apply is two triangular matrix-vector products.
 #include <cmath>
 
 #include "rmb_blocks.h"
@@ -63,28 +65,36 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
         __syncthreads();
     }
 
-    // 3. Y = L^-1 K_p (forward substitution, 6 right-hand sides)
+    // 3. Li = L^-1: L goes to the factor storage, then lane c forms column c
+    //    of Li in LDS (A is overwritten; each column belongs to one lane, so
+    //    no barrier is needed inside the loop).
+    double *out = it.factor;
+    for (int e = tid; e < m * m; e += blockDim.x) out[e] = A[e];  // row-major L (lower part)
+    __syncthreads();
+    for (int c = tid; c < m; c += blockDim.x) {
+        for (int r = 0; r < c; ++r) A[c * m + r] = 0.0;
+        A[c * m + c] = 1.0 / out[c * m + c];
+        for (int r = c + 1; r < m; ++r) {
+            double acc = 0.0;
+            for (int k = c; k < r; ++k) acc += out[r * m + k] * A[c * m + k];
+            A[c * m + r] = -acc / out[r * m + r];
+        }
+    }
+    __syncthreads();
+    // 4. Y = Li K_p, S = Y^T Y
     const double *q = it.q;
     for (int e = tid; e < 6 * m; e += blockDim.x) {
         const int row = e / 6, k = e % 6;
-        const int i = row / 3, c = row % 3;
-        const double *ri = it.pos + 3 * (int64_t)(it.blob0 + i);
-        const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
-        Y[row * 6 + k] = K_entry(d, c, k);
+        double acc = 0.0;
+        for (int c = 0; c <= row; ++c) {
+            const int i = c / 3, cc = c % 3;
+            const double *ri = it.pos + 3 * (int64_t)(it.blob0 + i);
+            const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
+            acc += A[c * m + row] * K_entry(d, cc, k);
+        }
+        Y[row * 6 + k] = acc;
     }
     __syncthreads();
-    for (int l = 0; l < m; ++l) {
-        if (tid < 6) Y[l * 6 + tid] /= A[l * m + l];
-        __syncthreads();
-        const int r = m - l - 1;
-        for (int e = tid; e < 6 * r; e += blockDim.x) {
-            const int row = l + 1 + e / 6, k = e % 6;
-            Y[row * 6 + k] -= A[row * m + l] * Y[l * 6 + k];
-        }
-        __syncthreads();
-    }
-
-    // 4. S = Y^T Y, then its Cholesky factor (6 x 6)
     if (tid < 36) {
         const int r = tid / 6, c = tid % 6;
         double acc = 0.0;
@@ -92,36 +102,45 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
         S[tid] = acc;
     }
     __syncthreads();
+    // 5. S^-1 through its Cholesky factor (one lane)
     if (tid == 0) {
+        double Lc[36], Inv[36];
         for (int j = 0; j < 6; ++j) {
             double dj = S[j * 6 + j];
-            for (int k = 0; k < j; ++k) dj -= S[j * 6 + k] * S[j * 6 + k];
+            for (int k = 0; k < j; ++k) dj -= Lc[j * 6 + k] * Lc[j * 6 + k];
             if (!(dj > 0.0)) {
                 bad |= 2;
                 dj = 1.0;
             }
             const double ljj = sqrt(dj);
-            S[j * 6 + j] = ljj;
+            Lc[j * 6 + j] = ljj;
             for (int i = j + 1; i < 6; ++i) {
                 double v = S[i * 6 + j];
-                for (int k = 0; k < j; ++k) v -= S[i * 6 + k] * S[j * 6 + k];
-                S[i * 6 + j] = v / ljj;
+                for (int k = 0; k < j; ++k) v -= Lc[i * 6 + k] * Lc[j * 6 + k];
+                Lc[i * 6 + j] = v / ljj;
             }
         }
+        for (int col = 0; col < 6; ++col) {  // S^-1 e_col = Lc^-T Lc^-1 e_col
+            double u[6];
+            for (int i = 0; i < 6; ++i) {
+                double v = i == col ? 1.0 : 0.0;
+                for (int k = 0; k < i; ++k) v -= Lc[i * 6 + k] * u[k];
+                u[i] = v / Lc[i * 6 + i];
+            }
+            for (int i = 5; i >= 0; --i) {
+                double v = u[i];
+                for (int k = i + 1; k < 6; ++k) v -= Lc[k * 6 + i] * Inv[k * 6 + col];
+                Inv[i * 6 + col] = v / Lc[i * 6 + i];
+            }
+        }
+        for (int e = 0; e < 36; ++e) S[e] = Inv[e];
     }
     __syncthreads();
 
-    // 5. store L (lower, row-major m x m), Y, Sc
-    double *out = it.factor;
-    for (int e = tid; e < m * m; e += blockDim.x) {
-        const int i = e / m, k = e % m;
-        out[e] = k <= i ? A[e] : 0.0;
-    }
+    // 6. store Li (column-major), Y, S^-1
+    for (int e = tid; e < m * m; e += blockDim.x) out[e] = A[e];
     for (int e = tid; e < 6 * m; e += blockDim.x) out[m * m + e] = Y[e];
-    for (int e = tid; e < 36; e += blockDim.x) {
-        const int i = e / 6, k = e % 6;
-        out[m * m + 6 * m + e] = k <= i ? S[e] : 0.0;
-    }
+    for (int e = tid; e < 36; e += blockDim.x) out[m * m + 6 * m + e] = S[e];
     // bit 4: M_pp not positive definite; bit 8: K_p^T M_pp^-1 K_p singular
     if (tid == 0 && bad) atomicOr(it.flag, ((bad & 1) ? 4 : 0) | ((bad & 2) ? 8 : 0));
 }
@@ -131,23 +150,22 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // ---------------------------------------------------------------------------
 
 // Solves one body's [M_pp -K_p; -K_p^T 0][lambda; U] = [s; bottom] with the
-// body's L staged in LDS (lds: m*m doubles of L, then m doubles of t).
+// body's Li staged in LDS (lds: m*m doubles of Li, then 2m doubles).
 __device__ void precond_body_apply(const BodyWork &it, const double *__restrict__ s_in,
                                    const double *__restrict__ bot_in, double *__restrict__ lam_out,
                                    double *__restrict__ U_out, double *lds, double *g) {
     const int m = 3 * it.n_blobs, tid = threadIdx.x;
     const double *fac = it.factor;
-    const double *Y = fac + m * m, *Sc = fac + m * m + 6 * m;
-    double *L = lds, *t = lds + m * m;
-    for (int e = tid; e < m * m; e += blockDim.x) L[e] = fac[e];
-    for (int e = tid; e < m; e += blockDim.x) t[e] = s_in[e];
+    const double *Y = fac + m * m, *Si = fac + m * m + 6 * m;
+    double *Li = lds, *sv = lds + m * m, *t = sv + m;
+    for (int e = tid; e < m * m; e += blockDim.x) Li[e] = fac[e];
+    for (int e = tid; e < m; e += blockDim.x) sv[e] = s_in[e];
     __syncthreads();
-    // t = L^-1 s (column-oriented forward substitution)
-    for (int l = 0; l < m; ++l) {
-        const double tl = t[l] / L[l * m + l];
-        for (int r = l + 1 + tid; r < m; r += blockDim.x) t[r] -= L[r * m + l] * tl;
-        __syncthreads();
-        if (tid == 0) t[l] = tl;
+    // t = Li s
+    for (int r = tid; r < m; r += blockDim.x) {
+        double acc = 0.0;
+        for (int c = 0; c <= r; ++c) acc += Li[c * m + r] * sv[c];
+        t[r] = acc;
     }
     __syncthreads();
     // g = F - Y^T t, F = -bottom
@@ -157,43 +175,32 @@ __device__ void precond_body_apply(const BodyWork &it, const double *__restrict_
         g[tid] = -bot_in[tid] - acc;
     }
     __syncthreads();
-    // U = Sc^-T Sc^-1 g
-    if (tid == 0) {
-        double u[6];
-        for (int i = 0; i < 6; ++i) {
-            double v = g[i];
-            for (int k = 0; k < i; ++k) v -= Sc[i * 6 + k] * u[k];
-            u[i] = v / Sc[i * 6 + i];
-        }
-        for (int i = 5; i >= 0; --i) {
-            double v = u[i];
-            for (int k = i + 1; k < 6; ++k) v -= Sc[k * 6 + i] * g[k];
-            g[i] = v / Sc[i * 6 + i];
-        }
+    // U = S^-1 g
+    if (tid < 6) {
+        double u = 0.0;
+        for (int k = 0; k < 6; ++k) u += Si[tid * 6 + k] * g[k];
+        g[6 + tid] = u;
     }
     __syncthreads();
-    // w = t + Y U, then lambda = L^-T w (row-oriented backward substitution)
-    for (int e = tid; e < m; e += blockDim.x) {
-        double acc = t[e];
-        for (int k = 0; k < 6; ++k) acc += Y[e * 6 + k] * g[k];
-        t[e] = acc;
+    // w = t + Y U (into sv), then lambda = Li^T w
+    for (int r = tid; r < m; r += blockDim.x) {
+        double acc = t[r];
+        for (int k = 0; k < 6; ++k) acc += Y[r * 6 + k] * g[6 + k];
+        sv[r] = acc;
     }
     __syncthreads();
-    for (int l = m - 1; l >= 0; --l) {
-        const double tl = t[l] / L[l * m + l];
-        for (int r = tid; r < l; r += blockDim.x) t[r] -= L[l * m + r] * tl;
-        __syncthreads();
-        if (tid == 0) t[l] = tl;
+    for (int r = tid; r < m; r += blockDim.x) {
+        double acc = 0.0;
+        for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
+        lam_out[r] = acc;
     }
-    __syncthreads();
-    for (int e = tid; e < m; e += blockDim.x) lam_out[e] = t[e];
-    if (tid < 6) U_out[tid] = g[tid];
+    if (tid < 6) U_out[tid] = g[6 + tid];
 }
 
 __global__ __launch_bounds__(64) void precond_apply_small_kernel(const PrecondApplyJob *__restrict__ jobs,
                                                                  int32_t n_jobs) {
     extern __shared__ double lds[];
-    __shared__ double g[6];
+    __shared__ double g[12];
     const int64_t w = blockIdx.x;
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -293,7 +300,7 @@ hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, in
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s) {
     if (n_wg <= 0 || max_rhs <= 0) return hipSuccess;
-    size_t lds = ((size_t)max_m * max_m + max_m) * sizeof(double);
+    size_t lds = ((size_t)max_m * max_m + 2 * max_m) * sizeof(double);
     hipLaunchKernelGGL(precond_apply_small_kernel, dim3((unsigned)n_wg, max_rhs), dim3(64), lds, s, jobs,
                        n_jobs);
     return hipGetLastError();

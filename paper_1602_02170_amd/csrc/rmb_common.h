@@ -59,6 +59,40 @@ void split_plan(int64_t nb, int32_t *n_split, int64_t *chunk, int32_t *n_tblock)
 void pair_job_init(PairJob *J, const double *tpos, const void *src, double *partial, int64_t nb,
                    double a);
 
+// One system's share of a launch of the pair kernel that evaluates each pair
+// block once (pair_sym_kernel): workgroups [wg_begin, wg_begin + T(T+1)/2)
+// are the block pairs (I <= J) of its T = ceil(nb / B) blocks; reduction
+// workgroups [red_begin, red_begin + sym_reduce_groups(nb)) add the partials
+// into vel.
+struct SymJob {
+    const double *tpos;  // [nb][3] positions
+    const double *lam;   // [nb][3] operand (the target's own force for M^T lambda)
+    const void *src;     // [nb] SrcF32 or SrcF64 records
+    double *vpart;       // [tiles][B][3] target-side sums
+    double *upart;       // [tiles][B][3] source-side sums
+    double *vel;         // [nb][3] result, prefactor applied
+    int64_t nb;
+    int64_t wg_begin;
+    int64_t red_begin;
+    int32_t n_blk;
+    int32_t B;
+    double a, four_a2, k_near_iso, k_near_rr;
+    double pref;
+};
+
+// Block size and block count of the symmetric product for nb blobs (a
+// function of nb only); tiles and partial storage it needs.
+void sym_plan(int64_t nb, int32_t *B, int32_t *n_blk);
+int64_t sym_tiles(int64_t nb);
+int64_t sym_reduce_groups(int64_t nb);
+size_t sym_partial_doubles(int64_t nb);
+// Systems of at least this many blobs use the symmetric product.
+constexpr int64_t kSymMinBlobs = 1024;
+inline bool use_sym(int64_t nb) { return nb >= kSymMinBlobs; }
+hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs, int64_t n_tiles,
+                           hipStream_t s);
+hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+
 // Packing of source records for several systems in one launch.
 struct PackJob {
     const double *pos;
@@ -99,6 +133,8 @@ class Arena {
     void free(void *p);
     size_t budget() const { return budget_; }
     size_t in_use() const { return in_use_; }
+    // Returns blocks with no live allocation to HIP.
+    void release_free_blocks();
 
   private:
     struct Seg {

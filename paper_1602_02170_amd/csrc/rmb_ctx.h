@@ -76,6 +76,9 @@ rmb_status check_positions(rmb_ctx ctx, const rmb_system *sys, int *flag_dev, hi
 // by timing events when the context's kernel timing is on.
 rmb_status pair_launch(rmb_ctx ctx, int precision, bool wall, const PairJob *jobs, int32_t n_jobs,
                        int64_t n_tiles, hipStream_t s);
+// Same for the symmetric pair kernel (block size B).
+rmb_status sym_launch(rmb_ctx ctx, int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs,
+                      int64_t n_tiles, hipStream_t s);
 // Accumulates the elapsed time of completed timing events.
 void resolve_timing(rmb_ctx ctx, bool wait);
 

@@ -167,9 +167,14 @@ struct Job {
     int32_t *blob_body = nullptr;
     void *src = nullptr;
     double *partial = nullptr, *factor = nullptr;
+    double *vel = nullptr;  // reduced product of the symmetric kernel
+    bool sym = false;
+    int32_t symB = 0, symT = 0;
     BodyWork *items_d = nullptr;
     double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *V = nullptr;
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
+    double *hred = nullptr;
+    unsigned *counter = nullptr;
     int slot = -1;
     BodyLists lists;
     BigBody *bigs_d = nullptr;
@@ -189,9 +194,10 @@ struct Job {
 static size_t job_bytes(Job &J) {
     const int64_t nb = J.nb, N = J.N, n = J.n;
     size_t t = 0;
-    t += al((N + 1) * 8) + al(nb * 4) + al(nb * sizeof(SrcF64)) + al((size_t)J.pj.n_split * nb * 24);
+    const size_t part = J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24;
+    t += al((N + 1) * 8) + al(nb * 4) + al(nb * sizeof(SrcF64)) + al(part) + al(nb * 24);
     t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
-    t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8);
+    t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8) + al(768 * 8) + al(8);
     if (!J.pc) t += al(factor_total(J.off.data(), N) * 8) + al(N * sizeof(BodyWork)) + al(N * sizeof(BigBody));
     return t;
 }
@@ -207,7 +213,8 @@ static void job_carve(Job &J) {
     J.off_d = (int64_t *)take((N + 1) * 8);
     J.blob_body = (int32_t *)take(nb * 4);
     J.src = take(nb * sizeof(SrcF64));
-    J.partial = (double *)take((size_t)J.pj.n_split * nb * 24);
+    J.partial = (double *)take(J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24);
+    J.vel = (double *)take(nb * 24);
     J.x = (double *)take(n * 8);
     J.b = (double *)take(n * 8);
     J.w = (double *)take(n * 8);
@@ -216,6 +223,8 @@ static void job_carve(Job &J) {
     J.P1 = (double *)take((size_t)(J.m + 1) * J.nseg * 8);
     J.P2 = (double *)take((size_t)(J.m + 1) * J.nseg * 8);
     J.P3 = (double *)take(J.nseg * 8);
+    J.hred = (double *)take(768 * 8);
+    J.counter = (unsigned *)take(8);
     if (!J.pc) {
         J.factor = (double *)take(factor_total(J.off.data(), N) * 8);
         J.items_d = (BodyWork *)take(N * sizeof(BodyWork));
@@ -323,6 +332,8 @@ struct Engine {
         J->ldv = (J->n + 31) / 32 * 32;
         J->nseg = (J->n + kSeg - 1) / kSeg;
         pair_job_init(&J->pj, sys->pos, nullptr, nullptr, J->nb, sys->a);
+        J->sym = use_sym(J->nb);
+        if (J->sym) sym_plan(J->nb, &J->symB, &J->symT);
         J->bytes = job_bytes(*J);
         if (J->bytes > ctx->arena->budget())
             return fail(ctx, RMB_ENOMEM, "request needs %zu bytes of device memory, budget is %zu", J->bytes,
@@ -483,6 +494,12 @@ struct Engine {
         int64_t wg_pk = 0;
         std::vector<PairJob> pairs[2][2];  // [fp32][wall]
         int64_t tiles[2][2] = {{0, 0}, {0, 0}};
+        // symmetric product: [fp32][wall][block size 64/128/256/512]
+        std::vector<SymJob> syms[2][2][4];
+        int64_t stiles[2][2][4] = {};
+        std::vector<SymJob> sred;  // reduction table (all symmetric jobs)
+        int64_t wg_sred = 0;
+        auto bidx = [](int B) { return B == 64 ? 0 : B == 128 ? 1 : B == 256 ? 2 : 3; };
         std::vector<SaddleJob> sd;
         int64_t wg_sd_blob = 0, wg_sd_body = 0;
         for (Job *J : mv) {
@@ -499,24 +516,49 @@ struct Engine {
             pk.push_back(p);
             wg_pk += (J->nb + 255) / 256;
             const int wl = J->sys.geometry == RMB_GEOM_WALL;
-            PairJob pj = J->pj;
-            pj.tile_begin = tiles[f32][wl];
-            pairs[f32][wl].push_back(pj);
-            tiles[f32][wl] += (int64_t)pj.n_tblock * pj.n_split;
+            if (J->sym) {
+                SymJob y{};
+                y.tpos = J->sys.pos;
+                y.lam = xin;
+                y.src = J->src;
+                y.vpart = J->partial;
+                y.upart = J->partial + (size_t)sym_tiles(J->nb) * J->symB * 3;
+                y.vel = J->vel;
+                y.nb = J->nb;
+                y.n_blk = J->symT;
+                y.B = J->symB;
+                y.a = J->sys.a;
+                y.four_a2 = 4.0 * J->sys.a * J->sys.a;
+                y.k_near_iso = 9.0 / (32.0 * J->sys.a);
+                y.k_near_rr = 3.0 / (32.0 * J->sys.a);
+                y.pref = mobility_prefactor(J->sys.a, J->sys.eta);
+                const int bi = bidx(J->symB);
+                y.wg_begin = stiles[f32][wl][bi];
+                y.red_begin = wg_sred;
+                stiles[f32][wl][bi] += sym_tiles(J->nb);
+                wg_sred += sym_reduce_groups(J->nb);
+                syms[f32][wl][bi].push_back(y);
+                sred.push_back(y);
+            } else {
+                PairJob pj = J->pj;
+                pj.tile_begin = tiles[f32][wl];
+                pairs[f32][wl].push_back(pj);
+                tiles[f32][wl] += (int64_t)pj.n_tblock * pj.n_split;
+            }
             SaddleJob sj{};
             sj.pos = J->sys.pos;
             sj.q = J->sys.q;
             sj.body_off = J->off_d;
             sj.blob_body = J->blob_body;
-            sj.partial = J->partial;
+            sj.partial = J->sym ? J->vel : J->partial;
             sj.x = xin;
             sj.b = is_iter ? nullptr : J->b;
             sj.y = J->w;
             sj.nb = J->nb;
             sj.blk_begin = wg_sd_blob;
             sj.body_begin = wg_sd_body;
-            sj.n_split = J->pj.n_split;
-            sj.pref = mobility_prefactor(J->sys.a, J->sys.eta);
+            sj.n_split = J->sym ? 1 : J->pj.n_split;
+            sj.pref = J->sym ? 1.0 : mobility_prefactor(J->sys.a, J->sys.eta);
             sd.push_back(sj);
             wg_sd_blob += (J->nb + 255) / 256;
             wg_sd_body += J->N;
@@ -537,6 +579,8 @@ struct Engine {
             K.P2 = J->P2;
             K.P3 = J->P3;
             K.hcol = hcol_d(J);
+            K.hred = J->hred;
+            K.counter = J->counter;
             K.n = J->n;
             K.wg_begin = wg;
             K.n_seg = (int32_t)J->nseg;
@@ -570,6 +614,13 @@ struct Engine {
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
                 o_pair[a][b] = pairs[a][b].empty() ? 0 : st.put(pairs[a][b].data(), pairs[a][b].size() * sizeof(PairJob));
+        size_t o_sym[2][2][4] = {};
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int c = 0; c < 4; ++c)
+                    if (!syms[a][b][c].empty())
+                        o_sym[a][b][c] = st.put(syms[a][b][c].data(), syms[a][b][c].size() * sizeof(SymJob));
+        size_t o_sred = sred.empty() ? 0 : st.put(sred.data(), sred.size() * sizeof(SymJob));
         size_t o_sd = sd.empty() ? 0 : st.put(sd.data(), sd.size() * sizeof(SaddleJob));
         size_t o_orth = orth.empty() ? 0 : st.put(orth.data(), orth.size() * sizeof(KrylovJob));
         size_t o_axp = axp.empty() ? 0 : st.put(axp.data(), axp.size() * sizeof(KrylovJob));
@@ -600,6 +651,7 @@ struct Engine {
             RMB_HIP(ctx, launch_blob_body(J->off_d, J->N, J->blob_body, s));
             RMB_HIP(ctx, launch_build_rhs(J->FT, J->slip, J->nb, J->N, J->b, s));
             RMB_HIP(ctx, hipMemsetAsync(J->x, 0, J->n * 8, s));
+            RMB_HIP(ctx, hipMemsetAsync(J->counter, 0, sizeof(unsigned), s));
         }
         if (!build_items.empty())
             RMB_HIP(ctx, launch_precond_build_small((const BodyWork *)D(o_build), (int32_t)build_items.size(),
@@ -621,6 +673,17 @@ struct Engine {
                 if (!pairs[a][b].empty())
                     RMB_TRY(pair_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0,
                                         (const PairJob *)D(o_pair[a][b]), (int32_t)pairs[a][b].size(), tiles[a][b], s));
+        {
+            const int Bs[4] = {64, 128, 256, 512};
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int c = 0; c < 4; ++c)
+                        if (!syms[a][b][c].empty())
+                            RMB_TRY(sym_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0, Bs[c],
+                                               (const SymJob *)D(o_sym[a][b][c]), (int32_t)syms[a][b][c].size(),
+                                               stiles[a][b][c], s));
+            if (!sred.empty()) RMB_HIP(ctx, launch_sym_reduce((const SymJob *)D(o_sred), (int32_t)sred.size(), wg_sred, s));
+        }
         if (!sd.empty())
             RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));
         if (!orth.empty())

@@ -1,0 +1,389 @@
+// Blob mobility product evaluating each pair block once (Sec. 2.2.1).
+//
+// The blob mobility is symmetric, M_ji = M_ij^T: the free-space RPY block is
+// a symmetric function of r_i - r_j, and the wall-corrected tensor is
+// reciprocal (the Faxen-corrected Blake Green's function, Sec. 2.1.1).  So
+// one evaluation of the pair's coefficients serves both
+//   v_i += M_ij lambda_j   and   v_j += M_ij^T lambda_i.
+//
+// Blobs are split into blocks of B (64..512, chosen from Nb alone).  One
+// workgroup is one wave and owns one block pair (I <= J).  It walks the
+// targets of block I in groups of 64 (one per lane) against the sources of
+// block J in groups of 64:
+//   * every lane holds one target and one source of the group; in 64 steps
+//     the sources, together with their running sums of M_ij^T lambda_i, are
+//     passed one lane along the wave (DPP wave rotation), so each lane meets
+//     every source once and each source meets every target once;
+//   * target side: each lane sums M_ij lambda_j in FP32 over the 64 sources
+//     of a group and flushes to FP64;
+//   * source side: after a full turn each source is back in its own lane,
+//     and its FP32 sum over the 64 targets is added to an FP64 accumulator.
+// Diagonal tiles (I == J) use the one-sided form over all ordered pairs,
+// with the sources as wave-uniform records from the scalar cache.
+// Every tile writes its target-side sums for block I and its source-side
+// sums for block J to its own slots; a second kernel adds, for each blob, its
+// tiles' contributions in a fixed order (bitwise reproducible, independent of
+// what shares the launch).
+#include <cmath>
+
+#include "rmb_common.h"
+
+namespace rmb {
+
+template <typename T>
+using gptr = const __attribute__((address_space(1))) T *;
+
+// Tile t of a T x T upper triangle (row-major over I, then J >= I).
+__device__ __forceinline__ void tile_ij(int64_t t, int32_t T, int32_t *I, int32_t *J) {
+    // I = largest i with start(i) = i*T - i*(i-1)/2 <= t
+    const double b = 2.0 * T + 1.0;
+    int32_t i = (int32_t)floor((b - sqrt(b * b - 8.0 * (double)t)) * 0.5);
+    if (i < 0) i = 0;
+    if (i > T - 1) i = T - 1;
+    auto start = [&](int64_t r) { return r * T - r * (r - 1) / 2; };
+    while (i > 0 && start(i) > t) --i;
+    while (i + 1 < T && start(i + 1) <= t) ++i;
+    *I = i;
+    *J = i + (int32_t)(t - start(i));
+}
+
+// One DPP step: x + x(shifted by `CTRL`), rows outside ROW_MASK and lanes
+// shifted in from outside the row read 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float x) {
+    const int s = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, true);
+    return x + __int_as_float(s);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_add(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffff), CTRL, ROW_MASK, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROW_MASK, 0xf, true);
+    return x + __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// Sum over the 64 lanes of a wave; the total lands in lane 63:
+// row_shr 1, 2, 4, 8 leave each row's sum in its lane 15, then row_bcast:15
+// and row_bcast:31 carry the row sums up to lane 63.
+template <typename R>
+__device__ __forceinline__ R wave_sum_to_63(R v) {
+    v = dpp_add<0x111, 0xf>(v);
+    v = dpp_add<0x112, 0xf>(v);
+    v = dpp_add<0x114, 0xf>(v);
+    v = dpp_add<0x118, 0xf>(v);
+    v = dpp_add<0x142, 0xa>(v);
+    v = dpp_add<0x143, 0xc>(v);
+    return v;
+}
+
+// Moves a value one lane up the wave (lane l receives lane l-1, lane 0
+// receives lane 63).  Every lane is written, so no prior value is needed.
+__device__ __forceinline__ float rot1(float x) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), 0x13c, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double rot1(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffff), 0x13c, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x13c, 0xf, 0xf, false);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+template <typename R>
+__device__ __forceinline__ R read_lane63(R v);
+template <>
+__device__ __forceinline__ float read_lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+template <>
+__device__ __forceinline__ double read_lane63(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), 63);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+__device__ __forceinline__ double rsqrt64(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsqrt_r(double x) { return rsqrt64(x); }
+
+// Coefficients of one pair block, shared by both contractions:
+//   M_ij f   = A f + Bv (r . f) r + W f,   W f = c1 f + (c2 (e.f) + c3 f_z) e + (c4 (e.f) + c5 f_z) z
+//   M_ij^T f = A f + Bv (r . f) r + c1 f + (c2 (e.f) + c4 f_z) e + (c3 (e.f) + c5 f_z) z
+template <typename R, bool WALL>
+struct PairCoef {
+    R ciso, crr;                 // RPY: ciso I + crr r r^T
+    R c1, c2, c3, c4, c5, invL;  // wall image (R = (rx, ry, Rz), e = R invL)
+    R Rz;
+
+    __device__ __forceinline__ void eval(R rx, R ry, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
+        const R rxy2 = rx * rx + ry * ry;
+        const R d2 = rz * rz + rxy2;
+        const R inv_d = rsqrt_r(d2 + tiny);
+        const R d = d2 * inv_d;
+        const R t = a * inv_d;
+        const R t2 = t * t;
+        const R iso_far = t * ((R)0.5 * t2 + (R)0.75);
+        const R rr_far = t * ((R)-1.5 * t2 + (R)0.75) * (inv_d * inv_d);
+        const R iso_near = (R)1 - kiso * d;
+        const R rr_near = krr * inv_d;
+        const bool near = d2 <= four_a2;
+        ciso = near ? iso_near : iso_far;
+        crr = near ? rr_near : rr_far;
+        if (WALL) {
+            Rz = rz + (R)2 * zj;
+            const R L2 = Rz * Rz + rxy2;
+            invL = rsqrt_r(L2);
+            const R xw = a * invL, hh = zj * invL, ez = Rz * invL;
+            const R xw2 = xw * xw, xw4 = xw2 * xw2, ez2 = ez * ez;
+            const R hh2 = hh * hh, ezh = ez * hh;
+            const R T = hh2 - ezh;
+            const R xq = (R)0.25 * xw;
+            c1 = xq * (xw4 * ((R)-10 * ez2 + (R)2) + (xw2 * ((R)6 * ez2 - (R)2) + ((R)6 * T - (R)3)));
+            c2 = xq * (xw4 * ((R)70 * ez2 - (R)10) + (xw2 * ((R)-30 * ez2 + (R)6) + ((R)-18 * T - (R)3)));
+            const R hh15 = (R)1.5 * hh;
+            const R m3 = hh15 * ((R)-6 * ez2 + ((R)6 * ezh + (R)1));
+            const R e3 = xw2 * ((R)15 * ez2 - (R)3) + xw4 * ((R)-35 * ez2 + (R)10);
+            c3 = xw * (ez * e3 + m3);
+            c4 = xw * ((R)-5 * ez * xw4 + hh15);
+            c5 = xw * (xw4 * ((R)15 * ez2 - (R)2) + (R)-3 * (ez2 * xw2 + hh2));
+        }
+    }
+    // out += M_ij f  (transpose = false) or M_ij^T f (transpose = true)
+    template <bool TRANSPOSE>
+    __device__ __forceinline__ void apply(R rx, R ry, R rz, R fx, R fy, R fz, R &ox, R &oy, R &oz) const {
+        const R pxy = rx * fx + ry * fy;
+        const R sr = crr * (rz * fz + pxy);
+        if (!WALL) {
+            ox += ciso * fx + sr * rx;
+            oy += ciso * fy + sr * ry;
+            oz += ciso * fz + sr * rz;
+        } else {
+            const R ef = (Rz * fz + pxy) * invL;
+            const R ce = TRANSPOSE ? c4 : c3, cz = TRANSPOSE ? c3 : c4;
+            const R g = (c2 * ef + ce * fz) * invL;
+            const R kz = cz * ef + c5 * fz;
+            const R iso = ciso + c1;
+            const R gr = sr + g;
+            ox += iso * fx + gr * rx;
+            oy += iso * fy + gr * ry;
+            oz += iso * fz + sr * rz + g * Rz + kz;
+        }
+    }
+};
+
+template <typename SRC>
+struct SrcView;
+template <>
+struct SrcView<SrcF32> {
+    using R = float;
+};
+template <>
+struct SrcView<SrcF64> {
+    using R = double;
+};
+
+__device__ __forceinline__ float src_z(const gptr<SrcF32> s, int64_t j) { return s[j].zf; }
+__device__ __forceinline__ double src_z(const gptr<SrcF64> s, int64_t j) { return s[j].z; }
+
+// One tile per wave.  B: block size (multiple of 64).
+template <typename SRC, int B, bool WALL>
+__global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs) {
+    using R = typename SrcView<SRC>::R;
+    constexpr int G = B / 64;
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].wg_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const SymJob &J = jobs[lo];
+    const int64_t t = w - J.wg_begin;
+    int32_t I, Jb;
+    tile_ij(t, J.n_blk, &I, &Jb);
+    const int64_t nb = J.nb;
+    const int lane = threadIdx.x;
+    gptr<SRC> __restrict__ src = (gptr<SRC>)J.src;
+    const bool diag = I == Jb;
+    const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
+    const R a = (R)J.a, four_a2 = (R)J.four_a2, kiso = (R)J.k_near_iso, krr = (R)J.k_near_rr;
+    const R tiny = sizeof(R) == 4 ? (R)1e-30f : (R)1e-280;
+    double *vout = J.vpart + t * (int64_t)B * 3;
+    double *uout = J.upart + t * (int64_t)B * 3;
+
+    double u64[G][3];
+#pragma unroll
+    for (int g = 0; g < G; ++g) u64[g][0] = u64[g][1] = u64[g][2] = 0.0;
+
+    for (int sub = 0; sub < G; ++sub) {
+        const int64_t i = (int64_t)I * B + sub * 64 + lane;
+        if ((int64_t)I * B + sub * 64 >= nb) break;  // wave-uniform
+        const bool active = i < nb;
+        const int64_t ii = active ? i : (int64_t)I * B + sub * 64;
+        const double xi = J.tpos[3 * ii], yi = J.tpos[3 * ii + 1], zi = J.tpos[3 * ii + 2];
+        // the target's own force enters the transposed contraction
+        const R fix = active ? (R)J.lam[3 * ii] : (R)0, fiy = active ? (R)J.lam[3 * ii + 1] : (R)0,
+                fiz = active ? (R)J.lam[3 * ii + 2] : (R)0;
+        double vx = 0.0, vy = 0.0, vz = 0.0;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t jb = s0 + 64 * g;
+            if (jb >= s1) break;  // wave-uniform
+            R ax = 0, ay = 0, az = 0;
+            if (diag) {
+                const int je = (int)min((int64_t)64, s1 - jb);
+                for (int jj = 0; jj < je; ++jj) {
+                    const int64_t j = jb + jj;
+                    const R rx = (R)(xi - src[j].x), ry = (R)(yi - src[j].y), rz = (R)(zi - src[j].z);
+                    PairCoef<R, WALL> pc;
+                    pc.eval(rx, ry, rz, src_z(src, j), a, four_a2, kiso, krr, tiny);
+                    pc.template apply<false>(rx, ry, rz, (R)src[j].fx, (R)src[j].fy, (R)src[j].fz, ax, ay, az);
+                }
+            } else {
+                // this lane's source of the group (idle lanes carry a valid
+                // position with zero force)
+                const int64_t jl = jb + lane;
+                const bool jvalid = jl < s1;
+                const int64_t jr = jvalid ? jl : jb;
+                const SRC *rec = (const SRC *)J.src + jr;
+                double sx = rec->x, sy = rec->y, sz = rec->z;
+                R sfx = jvalid ? (R)rec->fx : (R)0, sfy = jvalid ? (R)rec->fy : (R)0,
+                  sfz = jvalid ? (R)rec->fz : (R)0;
+                R szj = (R)sz;
+                R ux = 0, uy = 0, uz = 0;
+                for (int step = 0; step < 64; ++step) {
+                    const R rx = (R)(xi - sx), ry = (R)(yi - sy), rz = (R)(zi - sz);
+                    PairCoef<R, WALL> pc;
+                    pc.eval(rx, ry, rz, szj, a, four_a2, kiso, krr, tiny);
+                    pc.template apply<false>(rx, ry, rz, sfx, sfy, sfz, ax, ay, az);
+                    pc.template apply<true>(rx, ry, rz, fix, fiy, fiz, ux, uy, uz);
+                    sx = rot1(sx), sy = rot1(sy), sz = rot1(sz);
+                    sfx = rot1(sfx), sfy = rot1(sfy), sfz = rot1(sfz);
+                    szj = rot1(szj);
+                    ux = rot1(ux), uy = rot1(uy), uz = rot1(uz);
+                }
+                u64[g][0] += (double)ux;
+                u64[g][1] += (double)uy;
+                u64[g][2] += (double)uz;
+            }
+            vx += (double)ax;
+            vy += (double)ay;
+            vz += (double)az;
+        }
+        if (active) {
+            double *o = vout + (sub * 64 + lane) * 3;
+            o[0] = vx;
+            o[1] = vy;
+            o[2] = vz;
+        }
+    }
+    if (!diag) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t j = s0 + 64 * g + lane;
+            if (j < s1) {
+                double *o = uout + (64 * g + lane) * 3;
+                o[0] = u64[g][0];
+                o[1] = u64[g][1];
+                o[2] = u64[g][2];
+            }
+        }
+    }
+}
+
+// v[k] = pref * (sum_{J >= K} vpart[tile(K,J)][kk] + sum_{I < K} upart[tile(I,K)][kk]).
+// A workgroup covers 16 blobs with 16 threads each: thread (q, b) sums the
+// contributions q, q+16, q+32, ... of blob b (in the order listed above), and
+// the 16 partial sums are added in the order q = 0..15.
+constexpr int kRedBlobs = 16, kRedParts = 16;
+
+__global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs) {
+    __shared__ double part[kRedParts][kRedBlobs][3];
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].red_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const SymJob &J = jobs[lo];
+    const int b = threadIdx.x % kRedBlobs, q = threadIdx.x / kRedBlobs;
+    const int64_t k = (w - J.red_begin) * kRedBlobs + b;
+    double s[3] = {0.0, 0.0, 0.0};
+    if (k < J.nb) {
+        const int32_t B = J.B, T = J.n_blk;
+        const int32_t K = (int32_t)(k / B);
+        const int64_t kk = k % B;
+        auto tile = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i); };
+        const int32_t nv = T - K;  // vpart contributions, then K upart ones
+        for (int32_t c = q; c < T; c += kRedParts) {
+            const double *p = c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
+                                     : J.upart + (tile(c - nv, K) * B + kk) * 3;
+            s[0] += p[0], s[1] += p[1], s[2] += p[2];
+        }
+    }
+    part[q][b][0] = s[0], part[q][b][1] = s[1], part[q][b][2] = s[2];
+    __syncthreads();
+    if (q == 0 && k < J.nb) {
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int r = 0; r < kRedParts; ++r) t[0] += part[r][b][0], t[1] += part[r][b][1], t[2] += part[r][b][2];
+        double *o = J.vel + 3 * k;
+        o[0] = J.pref * t[0];
+        o[1] = J.pref * t[1];
+        o[2] = J.pref * t[2];
+    }
+}
+
+int64_t sym_reduce_groups(int64_t nb) { return (nb + kRedBlobs - 1) / kRedBlobs; }
+
+void sym_plan(int64_t nb, int32_t *B, int32_t *n_blk) {
+    int32_t b = nb <= 16384 ? 64 : nb <= 65536 ? 128 : nb <= 262144 ? 256 : 512;
+    *B = b;
+    *n_blk = (int32_t)((nb + b - 1) / b);
+}
+
+int64_t sym_tiles(int64_t nb) {
+    int32_t B, T;
+    sym_plan(nb, &B, &T);
+    return (int64_t)T * (T + 1) / 2;
+}
+
+size_t sym_partial_doubles(int64_t nb) {
+    int32_t B, T;
+    sym_plan(nb, &B, &T);
+    return (size_t)sym_tiles(nb) * B * 3 * 2;  // vpart + upart
+}
+
+template <typename SRC, bool WALL>
+static void launch_sym_b(int B, const SymJob *jobs, int32_t n_jobs, int64_t n_tiles, hipStream_t s) {
+    dim3 g((unsigned)n_tiles), b(64);
+    switch (B) {
+        case 64: hipLaunchKernelGGL((pair_sym_kernel<SRC, 64, WALL>), g, b, 0, s, jobs, n_jobs); break;
+        case 128: hipLaunchKernelGGL((pair_sym_kernel<SRC, 128, WALL>), g, b, 0, s, jobs, n_jobs); break;
+        case 256: hipLaunchKernelGGL((pair_sym_kernel<SRC, 256, WALL>), g, b, 0, s, jobs, n_jobs); break;
+        default: hipLaunchKernelGGL((pair_sym_kernel<SRC, 512, WALL>), g, b, 0, s, jobs, n_jobs); break;
+    }
+}
+
+hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs, int64_t n_tiles,
+                           hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (precision == RMB_PREC_FP32_PAIRS) {
+        if (wall) launch_sym_b<SrcF32, true>(B, jobs, n_jobs, n_tiles, s);
+        else launch_sym_b<SrcF32, false>(B, jobs, n_jobs, n_tiles, s);
+    } else {
+        if (wall) launch_sym_b<SrcF64, true>(B, jobs, n_jobs, n_tiles, s);
+        else launch_sym_b<SrcF64, false>(B, jobs, n_jobs, n_tiles, s);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {
+    if (n_wg <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)n_wg), dim3(256), 0, s, jobs, n_jobs);
+    return hipGetLastError();
+}
+
+}  // namespace rmb

@@ -1,0 +1,91 @@
+"""Continuous batching: admission by device-memory footprint, requests that
+arrive while others run, and results equal to solving each request alone."""
+import numpy as np
+import pytest
+
+import suspensions as S
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_1602_02170_amd as rmb
+    return rmb, torch
+
+
+def _reqs(rmb, torch, sizes):
+    reqs = [S.mixed_wall_request(100 + i, n_bodies=n) for i, n in enumerate(sizes)]
+    systems = [rmb.System.from_suspension(r) for r in reqs]
+    FTs = [torch.tensor(r.FT, dtype=torch.float64, device="cuda") for r in reqs]
+    return reqs, systems, FTs
+
+
+def test_admission_under_a_small_budget(env, oracle_mod):
+    rmb, torch = env
+    sizes = (40, 25, 60, 10, 35, 50, 20)
+    reqs, systems, FTs = _reqs(rmb, torch, sizes)
+    big = rmb.Context(0)
+    alone = [rmb.solve_mobility(big, systems[i], FTs[i], tol=1e-8, precision="fp32") for i in range(len(sizes))]
+    torch.cuda.synchronize()
+    # a budget that holds the server's buffers and only a few requests at a time
+    ctx = rmb.Context(0, hbm_budget=12 << 20)
+    srv = rmb.Server(ctx, max_active=64)
+    for i in range(len(sizes)):
+        srv.submit(i, systems[i], FTs[i], tol=1e-8, precision="fp32")
+    got, peak, steps = {}, 0, 0
+    while len(got) < len(sizes):
+        a, q = srv.step()
+        peak = max(peak, a)
+        for tag, U, lam, info in srv.poll():
+            got[tag] = (U, lam, info)
+        steps += 1
+        assert steps < 10000
+    print(f"[gpu] peak active {peak} of {len(sizes)}", flush=True)
+    assert 1 <= peak < len(sizes)  # memory, not the slot limit, bounded admission
+    for i, (Ua, la, ia) in enumerate(alone):
+        Um, lm, im = got[i]
+        assert im["status"] == 0
+        assert torch.equal(Ua, Um) and torch.equal(la, lm)
+    srv.close()
+    ctx.close()
+    big.close()
+
+
+def test_request_larger_than_budget_is_refused(env):
+    rmb, torch = env
+    reqs, systems, FTs = _reqs(rmb, torch, (400,))
+    ctx = rmb.Context(0, hbm_budget=4 << 20)
+    srv = rmb.Server(ctx, max_active=4)
+    with pytest.raises(rmb.RmbError) as e:
+        srv.submit(0, systems[0], FTs[0], tol=1e-8)
+    assert e.value.status == rmb.RMB_ENOMEM
+    srv.close()
+    ctx.close()
+
+
+def test_mixed_precisions_and_geometries_in_one_batch(env, oracle_mod):
+    rmb, torch = env
+    ctx = rmb.Context(0)
+    free = S.spheres_free_space()
+    wall = S.boomerangs_wall(n_bodies=70, lateral=53.0, seed=77)
+    sus = [free, wall, S.mixed_wall_request(7, n_bodies=120)]
+    systems = [rmb.System.from_suspension(x) for x in sus]
+    FTs = [torch.tensor(x.FT, dtype=torch.float64, device="cuda") for x in sus]
+    srv = rmb.Server(ctx)
+    precs = ["fp64", "fp32", "fp64"]
+    for i in range(3):
+        srv.submit(i, systems[i], FTs[i], tol=1e-9, precision=precs[i])
+    got = {}
+    while len(got) < 3:
+        srv.step()
+        for tag, U, lam, info in srv.poll():
+            got[tag] = (U.cpu().numpy(), lam.cpu().numpy(), info)
+    for i in range(3):
+        U, lam, info = got[i]
+        assert info["status"] == 0
+        res = oracle_mod.relative_residual(sus[i], sus[i].FT, None, U, lam)
+        assert res <= 1.05e-9
+    srv.close()
+    ctx.close()
