@@ -123,10 +123,15 @@ rmb_status pair_launch(rmb_ctx ctx, int precision, bool wall, const PairJob *job
     if (ctx->timing) {
         a = take_event(ctx);
         b = take_event(ctx);
-        if (a && b) RMB_HIP(ctx, hipEventRecord(a, s));
+        if (!a || !b) {
+            if (a) ctx->event_pool.push_back(a);
+            if (b) ctx->event_pool.push_back(b);
+            a = b = nullptr;
+        }
+        if (a) RMB_HIP(ctx, hipEventRecord(a, s));
     }
     RMB_HIP(ctx, launch_pair_tiles(precision, wall, jobs, n_jobs, n_tiles, s));
-    if (ctx->timing && a && b) {
+    if (a) {
         RMB_HIP(ctx, hipEventRecord(b, s));
         ctx->pending.push_back({kid, a, b});
     }
@@ -140,10 +145,15 @@ rmb_status sym_launch(rmb_ctx ctx, int precision, bool wall, int B, const SymJob
     if (ctx->timing) {
         a = take_event(ctx);
         b = take_event(ctx);
-        if (a && b) RMB_HIP(ctx, hipEventRecord(a, s));
+        if (!a || !b) {
+            if (a) ctx->event_pool.push_back(a);
+            if (b) ctx->event_pool.push_back(b);
+            a = b = nullptr;
+        }
+        if (a) RMB_HIP(ctx, hipEventRecord(a, s));
     }
     RMB_HIP(ctx, launch_pair_sym(precision, wall, B, jobs, n_jobs, n_tiles, s));
-    if (ctx->timing && a && b) {
+    if (a) {
         RMB_HIP(ctx, hipEventRecord(b, s));
         ctx->pending.push_back({kid, a, b});
     }

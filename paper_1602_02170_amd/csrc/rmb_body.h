@@ -87,7 +87,16 @@ hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_b
 // Krylov vector kernels
 // ---------------------------------------------------------------------------
 
-constexpr int kSeg = 512;  // vector elements per workgroup (256 threads x 2)
+constexpr int kSeg = 512;     // vector elements per chunk (256 threads x 2)
+constexpr int kMaxSeg = 256;  // most workgroups per system in a Krylov launch
+
+// Workgroups and chunks per workgroup covering an n-vector (n_seg <= kMaxSeg).
+inline void krylov_segments(int64_t n, int32_t *n_seg, int32_t *n_chunk) {
+    const int64_t chunks = (n + kSeg - 1) / kSeg;
+    const int64_t per = (chunks + kMaxSeg - 1) / kMaxSeg;
+    *n_chunk = (int32_t)(per > 0 ? per : 1);
+    *n_seg = (int32_t)((n + (int64_t)*n_chunk * kSeg - 1) / ((int64_t)*n_chunk * kSeg));
+}
 
 struct KrylovJob {
     double *V;          // basis vectors, vector k at V + k*ldv
@@ -97,14 +106,14 @@ struct KrylovJob {
     double *P1, *P2;    // partial dots [(kmax+1) x n_seg]
     double *P3;         // partial squared norms [n_seg]
     double *hcol;       // output: h[0..kk-1] then the norm at hcol[kk]
-    double *hred;       // reduced coefficients: h1 [256], h2 [256], norm [1]
-    unsigned *counter;  // zero between launches; counts finished workgroups
+    double *hred;       // h1 [256], kept between the second and third pass
     const double *coef; // combine coefficients (kk of them)
     double *x;          // axpy target
     const double *t;    // axpy source
     int64_t n;
     int64_t wg_begin;
-    int32_t n_seg;
+    int32_t n_seg;      // workgroups of this system
+    int32_t n_chunk;    // 512-element chunks per workgroup
     int32_t kk;
 };
 

@@ -150,19 +150,36 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // ---------------------------------------------------------------------------
 
 // Solves one body's [M_pp -K_p; -K_p^T 0][lambda; U] = [s; bottom] with the
-// body's Li staged in LDS (lds: m*m doubles of Li, then 2m doubles).
+// body's factor staged in LDS (lds: m*m + 6m + 36 doubles of the factor,
+// then 2m doubles).
+constexpr int kApplyThreads = 64;
+
 __device__ void precond_body_apply(const BodyWork &it, const double *__restrict__ s_in,
                                    const double *__restrict__ bot_in, double *__restrict__ lam_out,
                                    double *__restrict__ U_out, double *lds, double *g) {
     const int m = 3 * it.n_blobs, tid = threadIdx.x;
-    const double *fac = it.factor;
-    const double *Y = fac + m * m, *Si = fac + m * m + 6 * m;
-    double *Li = lds, *sv = lds + m * m, *t = sv + m;
-    for (int e = tid; e < m * m; e += blockDim.x) Li[e] = fac[e];
-    for (int e = tid; e < m; e += blockDim.x) sv[e] = s_in[e];
+    // the whole factor [Li | Y | S^-1] is staged in LDS, eight loads in
+    // flight per thread, followed by the right-hand side
+    const int nf = m * m + 6 * m + 36;
+    double *F = lds, *sv = lds + nf, *t = sv + m;
+    const double *Li = F, *Y = F + m * m, *Si = F + m * m + 6 * m;
+    for (int e0 = tid; e0 < nf; e0 += 8 * kApplyThreads) {
+        double v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + i * kApplyThreads;
+            v[i] = e < nf ? it.factor[e] : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int e = e0 + i * kApplyThreads;
+            if (e < nf) F[e] = v[i];
+        }
+    }
+    for (int e = tid; e < m; e += kApplyThreads) sv[e] = s_in[e];
     __syncthreads();
     // t = Li s
-    for (int r = tid; r < m; r += blockDim.x) {
+    for (int r = tid; r < m; r += kApplyThreads) {
         double acc = 0.0;
         for (int c = 0; c <= r; ++c) acc += Li[c * m + r] * sv[c];
         t[r] = acc;
@@ -183,13 +200,13 @@ __device__ void precond_body_apply(const BodyWork &it, const double *__restrict_
     }
     __syncthreads();
     // w = t + Y U (into sv), then lambda = Li^T w
-    for (int r = tid; r < m; r += blockDim.x) {
+    for (int r = tid; r < m; r += kApplyThreads) {
         double acc = t[r];
         for (int k = 0; k < 6; ++k) acc += Y[r * 6 + k] * g[6 + k];
         sv[r] = acc;
     }
     __syncthreads();
-    for (int r = tid; r < m; r += blockDim.x) {
+    for (int r = tid; r < m; r += kApplyThreads) {
         double acc = 0.0;
         for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
         lam_out[r] = acc;
@@ -197,7 +214,7 @@ __device__ void precond_body_apply(const BodyWork &it, const double *__restrict_
     if (tid < 6) U_out[tid] = g[6 + tid];
 }
 
-__global__ __launch_bounds__(64) void precond_apply_small_kernel(const PrecondApplyJob *__restrict__ jobs,
+__global__ __launch_bounds__(kApplyThreads) void precond_apply_small_kernel(const PrecondApplyJob *__restrict__ jobs,
                                                                  int32_t n_jobs) {
     extern __shared__ double lds[];
     __shared__ double g[12];
@@ -300,8 +317,8 @@ hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, in
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s) {
     if (n_wg <= 0 || max_rhs <= 0) return hipSuccess;
-    size_t lds = ((size_t)max_m * max_m + 2 * max_m) * sizeof(double);
-    hipLaunchKernelGGL(precond_apply_small_kernel, dim3((unsigned)n_wg, max_rhs), dim3(64), lds, s, jobs,
+    size_t lds = ((size_t)max_m * max_m + 8 * max_m + 36) * sizeof(double);
+    hipLaunchKernelGGL(precond_apply_small_kernel, dim3((unsigned)n_wg, max_rhs), dim3(kApplyThreads), lds, s, jobs,
                        n_jobs);
     return hipGetLastError();
 }

@@ -158,6 +158,7 @@ struct Job {
     rmb_precond pc = nullptr;  // external factors (not owned) or null
     // sizes
     int64_t nb = 0, N = 0, n = 0, ldv = 0, nseg = 0;
+    int32_t nchunk = 1;
     PairJob pj{};
     int max_m = 0;
     size_t bytes = 0;
@@ -174,7 +175,6 @@ struct Job {
     double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *V = nullptr;
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
     double *hred = nullptr;
-    unsigned *counter = nullptr;
     int slot = -1;
     BodyLists lists;
     BigBody *bigs_d = nullptr;
@@ -197,7 +197,7 @@ static size_t job_bytes(Job &J) {
     const size_t part = J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24;
     t += al((N + 1) * 8) + al(nb * 4) + al(nb * sizeof(SrcF64)) + al(part) + al(nb * 24);
     t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
-    t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8) + al(768 * 8) + al(8);
+    t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8) + al(256 * 8);
     if (!J.pc) t += al(factor_total(J.off.data(), N) * 8) + al(N * sizeof(BodyWork)) + al(N * sizeof(BigBody));
     return t;
 }
@@ -223,8 +223,7 @@ static void job_carve(Job &J) {
     J.P1 = (double *)take((size_t)(J.m + 1) * J.nseg * 8);
     J.P2 = (double *)take((size_t)(J.m + 1) * J.nseg * 8);
     J.P3 = (double *)take(J.nseg * 8);
-    J.hred = (double *)take(768 * 8);
-    J.counter = (unsigned *)take(8);
+    J.hred = (double *)take(256 * 8);
     if (!J.pc) {
         J.factor = (double *)take(factor_total(J.off.data(), N) * 8);
         J.items_d = (BodyWork *)take(N * sizeof(BodyWork));
@@ -330,7 +329,11 @@ struct Engine {
         J->nb = sys->n_blobs, J->N = sys->n_bodies;
         J->n = 3 * J->nb + 6 * J->N;
         J->ldv = (J->n + 31) / 32 * 32;
-        J->nseg = (J->n + kSeg - 1) / kSeg;
+        {
+            int32_t ns = 0;
+            krylov_segments(J->n, &ns, &J->nchunk);
+            J->nseg = ns;
+        }
         pair_job_init(&J->pj, sys->pos, nullptr, nullptr, J->nb, sys->a);
         J->sym = use_sym(J->nb);
         if (J->sym) sym_plan(J->nb, &J->symB, &J->symT);
@@ -580,10 +583,10 @@ struct Engine {
             K.P3 = J->P3;
             K.hcol = hcol_d(J);
             K.hred = J->hred;
-            K.counter = J->counter;
             K.n = J->n;
             K.wg_begin = wg;
             K.n_seg = (int32_t)J->nseg;
+            K.n_chunk = J->nchunk;
             K.kk = kk;
             wg += J->nseg;
             return K;
@@ -651,7 +654,6 @@ struct Engine {
             RMB_HIP(ctx, launch_blob_body(J->off_d, J->N, J->blob_body, s));
             RMB_HIP(ctx, launch_build_rhs(J->FT, J->slip, J->nb, J->N, J->b, s));
             RMB_HIP(ctx, hipMemsetAsync(J->x, 0, J->n * 8, s));
-            RMB_HIP(ctx, hipMemsetAsync(J->counter, 0, sizeof(unsigned), s));
         }
         if (!build_items.empty())
             RMB_HIP(ctx, launch_precond_build_small((const BodyWork *)D(o_build), (int32_t)build_items.size(),

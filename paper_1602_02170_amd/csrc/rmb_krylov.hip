@@ -3,17 +3,19 @@
 //
 // Every launch may cover several independent systems.  A system owns the
 // workgroups [wg_begin, wg_begin + n_seg) of the launch; workgroup s of a
-// system covers elements [s*512, (s+1)*512) of its vectors.  Dot products
-// are reduced in two stages: per-workgroup partials, then a fixed-order sum
-// done by whichever workgroup of the system finishes last.  The order depends
-// only on the system's own sizes, so results are bitwise reproducible and
-// independent of what else shares the launch.
+// system covers elements [s*L, (s+1)*L) of its vectors, L = n_chunk * 512
+// (n_chunk keeps n_seg <= kMaxSeg).  Dot products are reduced in two
+// stages: each workgroup writes its partials, and every workgroup of the
+// next launch sums all of a system's partials itself, in one fixed order.
+// All workgroups therefore hold bitwise the same coefficients, independent
+// of scheduling and of what else shares the launch, and no workgroup ever
+// waits on another inside a launch (no device-wide fences or atomics).
 #include "rmb_body.h"
 
 namespace rmb {
 
 constexpr int kThreads = 256;
-constexpr int kPer = kSeg / kThreads;  // elements per thread
+constexpr int kPer = kSeg / kThreads;  // elements per thread and chunk
 constexpr int kMaxKK = 256;            // largest basis handled (restart <= 255)
 
 __device__ __forceinline__ int find_wg_job(const KrylovJob *__restrict__ jobs, int32_t n_jobs, int64_t w) {
@@ -23,6 +25,16 @@ __device__ __forceinline__ int find_wg_job(const KrylovJob *__restrict__ jobs, i
         if (jobs[mid].wg_begin <= w) lo = mid; else hi = mid - 1;
     }
     return lo;
+}
+
+// This workgroup's element range [b0, b1) of its system.
+struct Range {
+    int64_t b0, b1;
+};
+__device__ __forceinline__ Range seg_range(const KrylovJob &J, int sg) {
+    const int64_t len = (int64_t)J.n_chunk * kSeg;
+    const int64_t b0 = (int64_t)sg * len;
+    return Range{b0, min(J.n, b0 + len)};
 }
 
 // One DPP step on a double: x + (x moved by CTRL); lanes outside ROW_MASK or
@@ -51,64 +63,38 @@ __device__ __forceinline__ double wave_total(double v) {
 }
 
 // Block-wide sums of per-thread values: each wave totals its lanes and lane
-// 0 stores red[k][wave]; the caller syncs and adds the 4 wave results in
-// order.
+// 0 stores red[k][wave]; after a sync, block_sum(red, k) adds the 4 wave
+// results in order.
 __device__ __forceinline__ void stash_wave_sum(double v, int k, double *red) {
     v = wave_total(v);
     if ((threadIdx.x & 63) == 0) red[k * 4 + (threadIdx.x >> 6)] = v;
 }
-
-// Partial dot products <V_k, w> of this workgroup's elements for k < kk,
-// four basis vectors at a time so that their reductions interleave.
-__device__ __forceinline__ void block_dots(const KrylovJob &J, const double *wv, int64_t e0, int kk, double *red) {
-    int k = 0;
-    for (; k + 4 <= kk; k += 4) {
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const double *Vk = J.V + (k + c) * J.ldv;
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int64_t e = e0 + u * 256;
-                if (e < J.n) acc[c] += Vk[e] * wv[u];
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) stash_wave_sum(acc[c], k + c, red);
-    }
-    for (; k < kk; ++k) {
-        const double *Vk = J.V + k * J.ldv;
-        double acc = 0.0;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int64_t e = e0 + u * 256;
-            if (e < J.n) acc += Vk[e] * wv[u];
-        }
-        stash_wave_sum(acc, k, red);
-    }
+__device__ __forceinline__ double block_sum(const double *red, int k) {
+    return ((red[4 * k] + red[4 * k + 1]) + red[4 * k + 2]) + red[4 * k + 3];
 }
 
-// Writes this workgroup's partials, then lets the last workgroup of the
-// system to finish (atomic ticket) reduce them: out[k] = sum_s P[k][s] for
-// k < kk, in a fixed order (strided partial sums per thread, then a fixed
-// tree), so the result does not depend on which workgroup finishes last.
-// Returns true in the reducing workgroup.
-__device__ bool last_block_reduce(const KrylovJob &J, const double *P, int kk, double *out, double *red) {
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) last = atomicAdd(J.counter, 1u) == (unsigned)(J.n_seg - 1);
-    __syncthreads();
-    if (!last) return false;
-    __threadfence();
+// out[k] = sum_{s < n_seg} P[k*n_seg + s] for k < kk, in a fixed order:
+// Q threads per k take strided partial sums (s = q, q+Q, ..., eight loads in
+// flight), then a fixed tree over q.  Ends with a sync.
+__device__ void reduce_partials(const double *__restrict__ P, int kk, int n_seg, double *out, double *red) {
     int Q = kThreads;
     while (Q > 1 && Q * kk > kThreads) Q >>= 1;
     const int t = threadIdx.x;
     for (int k0 = 0; k0 < kk; k0 += kThreads / Q) {
         const int k = k0 + t / Q, q = t % Q;
         double acc = 0.0;
-        if (k < kk)
-            for (int sg = q; sg < J.n_seg; sg += Q) acc += __builtin_nontemporal_load(&P[(int64_t)k * J.n_seg + sg]);
+        if (k < kk) {
+            const double *Pk = P + (int64_t)k * n_seg;
+            int sg = q;
+            for (; sg + 7 * Q < n_seg; sg += 8 * Q) {
+                double v[8];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) v[i] = Pk[sg + i * Q];
+#pragma unroll
+                for (int i = 0; i < 8; ++i) acc += v[i];
+            }
+            for (; sg < n_seg; sg += Q) acc += Pk[sg];
+        }
         red[t] = acc;
         __syncthreads();
         for (int w = Q / 2; w >= 1; w >>= 1) {
@@ -118,11 +104,90 @@ __device__ bool last_block_reduce(const KrylovJob &J, const double *P, int kk, d
         if (q == 0 && k < kk) out[k] = red[t];
         __syncthreads();
     }
-    if (threadIdx.x == 0) *J.counter = 0u;
-    return true;
 }
 
-// pass 1: partial <V_k, w>; the last workgroup forms h1
+// Partial dot products <V_k, w> over [r.b0, r.b1) for k < kk into red (see
+// stash_wave_sum), eight basis vectors at a time so that their loads are in
+// flight together and their wave reductions interleave.
+__device__ void block_dots(const KrylovJob &J, Range r, int kk, double *red) {
+    constexpr int C = 8;
+    int k = 0;
+    for (; k < kk; k += C) {
+        const int nc = min(C, kk - k);
+        double acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0.0;
+        for (int64_t e0 = r.b0 + threadIdx.x; e0 < r.b1; e0 += kSeg) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int64_t e = e0 + u * kThreads;
+                if (e >= r.b1) continue;
+                const double we = J.w[e];
+                if (nc == C) {
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] += J.V[(k + c) * J.ldv + e] * we;
+                } else {
+                    for (int c = 0; c < nc; ++c) acc[c] += J.V[(k + c) * J.ldv + e] * we;
+                }
+            }
+        }
+        if (nc == C) {
+#pragma unroll
+            for (int c = 0; c < C; ++c) stash_wave_sum(acc[c], k + c, red);
+        } else {
+            for (int c = 0; c < nc; ++c) stash_wave_sum(acc[c], k + c, red);
+        }
+    }
+}
+
+// w -= sum_k h[k] V_k over [r.b0, r.b1), subtracting in the order k = 0, 1,
+// ...  (eight basis vectors loaded at a time), and returns this thread's part
+// of ||w||^2 after the update.
+__device__ double block_subtract(const KrylovJob &J, Range r, const double *h, int kk) {
+    constexpr int C = 8;
+    double sq = 0.0;
+    for (int64_t e0 = r.b0 + threadIdx.x; e0 < r.b1; e0 += kSeg) {
+        double wv[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t e = e0 + u * kThreads;
+            wv[u] = e < r.b1 ? J.w[e] : 0.0;
+        }
+        int k = 0;
+        for (; k + C <= kk; k += C) {
+            double v[C][kPer];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) {
+                    const int64_t e = e0 + u * kThreads;
+                    v[c][u] = e < r.b1 ? J.V[(k + c) * J.ldv + e] : 0.0;
+                }
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int u = 0; u < kPer; ++u) wv[u] -= h[k + c] * v[c][u];
+        }
+        for (; k < kk; ++k) {
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                const int64_t e = e0 + u * kThreads;
+                if (e < r.b1) wv[u] -= h[k] * J.V[k * J.ldv + e];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t e = e0 + u * kThreads;
+            if (e < r.b1) {
+                if (kk > 0) J.w[e] = wv[u];
+                sq += wv[u] * wv[u];
+            }
+        }
+    }
+    return sq;
+}
+
+// pass 1: partials P1 of <V_k, w>
 __global__ __launch_bounds__(kThreads) void orth_dots_kernel(const KrylovJob *__restrict__ jobs, int32_t n_jobs) {
     __shared__ double red[kMaxKK * 4];
     const int64_t wgi = blockIdx.x;
@@ -130,22 +195,13 @@ __global__ __launch_bounds__(kThreads) void orth_dots_kernel(const KrylovJob *__
     const int sg = (int)(wgi - J.wg_begin);
     const int kk = J.kk;
     if (kk == 0) return;
-    const int64_t e0 = (int64_t)sg * kSeg + threadIdx.x;
-    double wv[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        wv[u] = e < J.n ? J.w[e] : 0.0;
-    }
-    block_dots(J, wv, e0, kk, red);
+    block_dots(J, seg_range(J, sg), kk, red);
     __syncthreads();
-    for (int k = threadIdx.x; k < kk; k += kThreads)
-        J.P1[(int64_t)k * J.n_seg + sg] = ((red[4 * k] + red[4 * k + 1]) + red[4 * k + 2]) + red[4 * k + 3];
-    last_block_reduce(J, J.P1, kk, J.hred, red);
+    for (int k = threadIdx.x; k < kk; k += kThreads) J.P1[(int64_t)k * J.n_seg + sg] = block_sum(red, k);
 }
 
-// pass 2: w -= V h1, partial <V_k, w>; the last workgroup forms h2 and
-// hcol[k] = h1 + h2
+// pass 2: h1 = sum of P1; w -= V h1; partials P2 of <V_k, w>.  Workgroup 0
+// keeps h1 in hred.
 __global__ __launch_bounds__(kThreads) void orth_update_dots_kernel(const KrylovJob *__restrict__ jobs,
                                                                     int32_t n_jobs) {
     __shared__ double red[kMaxKK * 4];
@@ -155,39 +211,18 @@ __global__ __launch_bounds__(kThreads) void orth_update_dots_kernel(const Krylov
     const int sg = (int)(wgi - J.wg_begin);
     const int kk = J.kk;
     if (kk == 0) return;
-    for (int k = threadIdx.x; k < kk; k += kThreads) h[k] = J.hred[k];
+    reduce_partials(J.P1, kk, J.n_seg, h, red);
+    if (sg == 0)
+        for (int k = threadIdx.x; k < kk; k += kThreads) J.hred[k] = h[k];
+    const Range r = seg_range(J, sg);
+    (void)block_subtract(J, r, h, kk);
+    block_dots(J, r, kk, red);
     __syncthreads();
-    const int64_t e0 = (int64_t)sg * kSeg + threadIdx.x;
-    double wv[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        wv[u] = e < J.n ? J.w[e] : 0.0;
-    }
-    for (int k = 0; k < kk; ++k) {
-        const double *Vk = J.V + k * J.ldv;
-        const double hk = h[k];
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int64_t e = e0 + u * kThreads;
-            if (e < J.n) wv[u] -= hk * Vk[e];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        if (e < J.n) J.w[e] = wv[u];
-    }
-    block_dots(J, wv, e0, kk, red);
-    __syncthreads();
-    for (int k = threadIdx.x; k < kk; k += kThreads)
-        J.P2[(int64_t)k * J.n_seg + sg] = ((red[4 * k] + red[4 * k + 1]) + red[4 * k + 2]) + red[4 * k + 3];
-    if (last_block_reduce(J, J.P2, kk, J.hred + kMaxKK, red)) {
-        for (int k = threadIdx.x; k < kk; k += kThreads) J.hcol[k] = h[k] + J.hred[kMaxKK + k];
-    }
+    for (int k = threadIdx.x; k < kk; k += kThreads) J.P2[(int64_t)k * J.n_seg + sg] = block_sum(red, k);
 }
 
-// pass 3: w -= V h2, partial ||w||^2; the last workgroup forms the norm
+// pass 3: h2 = sum of P2; w -= V h2; partials P3 of ||w||^2.  Workgroup 0
+// writes hcol[k] = h1 + h2.
 __global__ __launch_bounds__(kThreads) void orth_update_norm_kernel(const KrylovJob *__restrict__ jobs,
                                                                     int32_t n_jobs) {
     __shared__ double red[kThreads];
@@ -196,61 +231,32 @@ __global__ __launch_bounds__(kThreads) void orth_update_norm_kernel(const Krylov
     const KrylovJob &J = jobs[find_wg_job(jobs, n_jobs, wgi)];
     const int sg = (int)(wgi - J.wg_begin);
     const int kk = J.kk;
-    const int64_t e0 = (int64_t)sg * kSeg + threadIdx.x;
-    double wv[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        wv[u] = e < J.n ? J.w[e] : 0.0;
-    }
     if (kk > 0) {
-        for (int k = threadIdx.x; k < kk; k += kThreads) h[k] = J.hred[kMaxKK + k];
-        __syncthreads();
-        for (int k = 0; k < kk; ++k) {
-            const double *Vk = J.V + k * J.ldv;
-            const double hk = h[k];
-#pragma unroll
-            for (int u = 0; u < kPer; ++u) {
-                const int64_t e = e0 + u * kThreads;
-                if (e < J.n) wv[u] -= hk * Vk[e];
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int64_t e = e0 + u * kThreads;
-            if (e < J.n) J.w[e] = wv[u];
-        }
+        reduce_partials(J.P2, kk, J.n_seg, h, red);
+        if (sg == 0)
+            for (int k = threadIdx.x; k < kk; k += kThreads) J.hcol[k] = J.hred[k] + h[k];
     }
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) acc += wv[u] * wv[u];
-    stash_wave_sum(acc, 0, red);
+    const double sq = block_subtract(J, seg_range(J, sg), h, kk);
+    stash_wave_sum(sq, 0, red);
     __syncthreads();
-    if (threadIdx.x == 0) J.P3[sg] = ((red[0] + red[1]) + red[2]) + red[3];
-    __syncthreads();
-    if (last_block_reduce(J, J.P3, 1, J.hred + 2 * kMaxKK, red)) {
-        if (threadIdx.x == 0) {
-            const double beta = sqrt(J.hred[2 * kMaxKK]);
-            J.hred[2 * kMaxKK] = beta;
-            J.hcol[kk] = beta;
-        }
-    }
+    if (threadIdx.x == 0) J.P3[sg] = block_sum(red, 0);
 }
 
-// pass 4: vnext = w / beta
+// pass 4: beta = sqrt(sum of P3); vnext = w / beta.  Workgroup 0 writes
+// hcol[kk] = beta.
 __global__ __launch_bounds__(kThreads) void orth_normalise_kernel(const KrylovJob *__restrict__ jobs,
                                                                   int32_t n_jobs) {
+    __shared__ double red[kThreads];
+    __shared__ double nrm[1];
     const int64_t wgi = blockIdx.x;
     const KrylovJob &J = jobs[find_wg_job(jobs, n_jobs, wgi)];
     const int sg = (int)(wgi - J.wg_begin);
-    const double beta = J.hred[2 * kMaxKK];
+    reduce_partials(J.P3, 1, J.n_seg, nrm, red);
+    const double beta = sqrt(nrm[0]);
+    if (sg == 0 && threadIdx.x == 0) J.hcol[J.kk] = beta;
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
-    const int64_t e0 = (int64_t)sg * kSeg + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        if (e < J.n) J.vnext[e] = J.w[e] * inv;
-    }
+    const Range r = seg_range(J, sg);
+    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) J.vnext[e] = J.w[e] * inv;
 }
 
 hipError_t launch_orthogonalise(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {
@@ -267,24 +273,11 @@ hipError_t launch_orthogonalise(const KrylovJob *jobs, int32_t n_jobs, int64_t n
 __global__ __launch_bounds__(kThreads) void combine_kernel(const KrylovJob *__restrict__ jobs, int32_t n_jobs) {
     const int64_t wgi = blockIdx.x;
     const KrylovJob &J = jobs[find_wg_job(jobs, n_jobs, wgi)];
-    const int sg = (int)(wgi - J.wg_begin);
-    const int64_t e0 = (int64_t)sg * kSeg + threadIdx.x;
-    double acc[kPer];
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) acc[u] = 0.0;
-    for (int k = 0; k < J.kk; ++k) {
-        const double c = J.coef[k];
-        const double *Vk = J.V + k * J.ldv;
-#pragma unroll
-        for (int u = 0; u < kPer; ++u) {
-            const int64_t e = e0 + u * kThreads;
-            if (e < J.n) acc[u] += c * Vk[e];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        if (e < J.n) J.w[e] = acc[u];
+    const Range r = seg_range(J, (int)(wgi - J.wg_begin));
+    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) {
+        double acc = 0.0;
+        for (int k = 0; k < J.kk; ++k) acc += J.coef[k] * J.V[k * J.ldv + e];
+        J.w[e] = acc;
     }
 }
 
@@ -294,16 +287,12 @@ hipError_t launch_combine(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, h
     return hipGetLastError();
 }
 
+// x += t
 __global__ __launch_bounds__(kThreads) void axpy_kernel(const KrylovJob *__restrict__ jobs, int32_t n_jobs) {
     const int64_t wgi = blockIdx.x;
     const KrylovJob &J = jobs[find_wg_job(jobs, n_jobs, wgi)];
-    const int sg = (int)(wgi - J.wg_begin);
-    const int64_t e0 = (int64_t)sg * kSeg + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < kPer; ++u) {
-        const int64_t e = e0 + u * kThreads;
-        if (e < J.n) J.x[e] += J.t[e];
-    }
+    const Range r = seg_range(J, (int)(wgi - J.wg_begin));
+    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) J.x[e] += J.t[e];
 }
 
 hipError_t launch_axpy(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {

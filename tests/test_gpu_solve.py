@@ -110,6 +110,22 @@ def test_full_boomerang_suspension_refined_and_plain(env):
     assert _rel(out["fp32"], out["fp64"]) <= 1e-6
 
 
+def test_large_system_multi_chunk_krylov(env):
+    """3000 x 15-blob boomerangs (45,000 blobs, 153,000 unknowns): more
+    unknowns than 256 Krylov workgroups of 512 elements cover, so each
+    workgroup takes several chunks.  The oracle's FP64 residual of the GPU
+    result meets the tolerance."""
+    O = env[3]
+    s = S.boomerangs_wall(n_bodies=3000, lateral=200.0 * np.sqrt(3.0))
+    assert 3 * s.n_blobs + 6 * 3000 > 256 * 512
+    print(f"[gpu] 3000 boomerangs fp32 ({s.n_blobs} blobs)", flush=True)
+    U, lam, info = _solve(env, s, tol=1e-8, precision="fp32")
+    res = O.relative_residual(s, s.FT, None, U, lam)
+    print(f"    info {info}  oracle residual {res:.2e}", flush=True)
+    assert info["status"] == 0
+    assert res <= 1.05e-8
+
+
 def test_precond_apply_parity(env):
     rmb, torch, ctx, O = env
     s = small_wall()
