@@ -189,11 +189,61 @@ struct SrcView<SrcF64> {
 __device__ __forceinline__ float src_z(const gptr<SrcF32> s, int64_t j) { return s[j].zf; }
 __device__ __forceinline__ double src_z(const gptr<SrcF64> s, int64_t j) { return s[j].z; }
 
+// A group of 64 sources staged in LDS twice over (entries l and l + 64 hold
+// source l), so that lane l reads the source it pairs with at step s at
+// entry l - s + 64 without wrapping.
+template <typename R>
+struct SymStage;
+template <>
+struct SymStage<float> {
+    double x[128], y[128], z[128];
+    float2 fxy[128], fzz[128];  // (fx, fy), (fz, z rounded to float)
+    __device__ __forceinline__ void put(int l, double px, double py, double pz, float fx, float fy, float fz) {
+        x[l] = x[l + 64] = px;
+        y[l] = y[l + 64] = py;
+        z[l] = z[l + 64] = pz;
+        fxy[l] = fxy[l + 64] = make_float2(fx, fy);
+        fzz[l] = fzz[l + 64] = make_float2(fz, (float)pz);
+    }
+    __device__ __forceinline__ void get(int e, double &px, double &py, double &pz, float &fx, float &fy, float &fz,
+                                        float &zj) const {
+        px = x[e], py = y[e], pz = z[e];
+        const float2 a = fxy[e], b = fzz[e];
+        fx = a.x, fy = a.y, fz = b.x, zj = b.y;
+    }
+};
+template <>
+struct SymStage<double> {
+    double x[128], y[128], z[128], fx[128], fy[128], fz[128];
+    __device__ __forceinline__ void put(int l, double px, double py, double pz, double gx, double gy, double gz) {
+        x[l] = x[l + 64] = px;
+        y[l] = y[l + 64] = py;
+        z[l] = z[l + 64] = pz;
+        fx[l] = fx[l + 64] = gx;
+        fy[l] = fy[l + 64] = gy;
+        fz[l] = fz[l + 64] = gz;
+    }
+    __device__ __forceinline__ void get(int e, double &px, double &py, double &pz, double &gx, double &gy,
+                                        double &gz, double &zj) const {
+        px = x[e], py = y[e], pz = z[e];
+        gx = fx[e], gy = fy[e], gz = fz[e];
+        zj = pz;
+    }
+};
+
 // One tile per wave.  B: block size (multiple of 64).
+//
+// Diagonal tiles (I == J) run the one-sided product over the block with the
+// source read through the scalar cache.  Off-diagonal tiles form each
+// unordered pair once: lane l of a 64-target sub-block meets source
+// (l - s) mod 64 of a 64-source group at step s (read from LDS) and adds
+// M_ij f_j to its target and M_ij^T f_i to an accumulator that travels with
+// the source (rotated one lane per step).
 template <typename SRC, int B, bool WALL>
 __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs) {
     using R = typename SrcView<SRC>::R;
     constexpr int G = B / 64;
+    __shared__ SymStage<R> st;
     const int64_t w = blockIdx.x;
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -243,28 +293,30 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                     pc.template apply<false>(rx, ry, rz, (R)src[j].fx, (R)src[j].fy, (R)src[j].fz, ax, ay, az);
                 }
             } else {
-                // this lane's source of the group (idle lanes carry a valid
-                // position with zero force)
+                // stage the group (idle lanes carry a valid position with
+                // zero force)
                 const int64_t jl = jb + lane;
                 const bool jvalid = jl < s1;
-                const int64_t jr = jvalid ? jl : jb;
-                const SRC *rec = (const SRC *)J.src + jr;
-                double sx = rec->x, sy = rec->y, sz = rec->z;
-                R sfx = jvalid ? (R)rec->fx : (R)0, sfy = jvalid ? (R)rec->fy : (R)0,
-                  sfz = jvalid ? (R)rec->fz : (R)0;
-                R szj = (R)sz;
+                const SRC *rec = (const SRC *)J.src + (jvalid ? jl : jb);
+                const double px = rec->x, py = rec->y, pz = rec->z;
+                const R gx = jvalid ? (R)rec->fx : (R)0, gy = jvalid ? (R)rec->fy : (R)0,
+                        gz = jvalid ? (R)rec->fz : (R)0;
+                __syncthreads();  // the previous group's reads are done
+                st.put(lane, px, py, pz, gx, gy, gz);
+                __syncthreads();
                 R ux = 0, uy = 0, uz = 0;
                 for (int step = 0; step < 64; ++step) {
+                    double sx, sy, sz;
+                    R sfx, sfy, sfz, szj;
+                    st.get(lane - step + 64, sx, sy, sz, sfx, sfy, sfz, szj);
                     const R rx = (R)(xi - sx), ry = (R)(yi - sy), rz = (R)(zi - sz);
                     PairCoef<R, WALL> pc;
                     pc.eval(rx, ry, rz, szj, a, four_a2, kiso, krr, tiny);
                     pc.template apply<false>(rx, ry, rz, sfx, sfy, sfz, ax, ay, az);
                     pc.template apply<true>(rx, ry, rz, fix, fiy, fiz, ux, uy, uz);
-                    sx = rot1(sx), sy = rot1(sy), sz = rot1(sz);
-                    sfx = rot1(sfx), sfy = rot1(sfy), sfz = rot1(sfz);
-                    szj = rot1(szj);
                     ux = rot1(ux), uy = rot1(uy), uz = rot1(uz);
                 }
+                // after 64 rotations each accumulator is back on its source's lane
                 u64[g][0] += (double)ux;
                 u64[g][1] += (double)uy;
                 u64[g][2] += (double)uz;
