@@ -19,6 +19,7 @@ pair rate on a bounded sample.
 Prints one JSON line on stdout; progress goes to stderr.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -57,6 +58,46 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE
+# runs scaled by the same counters on a plain copy of known size.  It is
+# reported only while the kernel source still hashes to what was profiled.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "pair_sym_f32_wall_boomerangs15000_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1602_02170_amd", "csrc", f)
+                  for f in ("rmb_pair_sym.hip", "rmb_common.h")]
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None, None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None, "kernel changed since the counters were taken"
+    return t["hbm_bytes_per_launch"], t
+
+
+def copy_calibration(torch, mib):
+    """A plain device copy of `mib` MiB, three times (reference for the
+    FETCH_SIZE / WRITE_SIZE counters: each dispatch reads and writes exactly
+    mib MiB)."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"  copy calibration: 3 x {mib} MiB device-to-device copies")
+
+
 def solve_leg(rmb, torch, ctx, sysd, FT, precision, steps, warmup, tol=1e-8):
     for _ in range(warmup):
         rmb.solve_mobility(ctx, sysd, FT, tol=tol, precision=precision)
@@ -74,27 +115,39 @@ def solve_leg(rmb, torch, ctx, sysd, FT, precision, steps, warmup, tol=1e-8):
     return dt, infos, kt
 
 
-def matvec_leg(rmb, torch, ctx, S, reps=5):
-    sus, lam = S.icosahedra_monolayer()
-    sysd = rmb.System.from_suspension(sus)
-    lt = torch.tensor(lam, dtype=torch.float64, device="cuda")
-    out = torch.empty_like(lt)
-    res = {"workload": f"wall RPY mobility product, {sus.n_blobs} blobs (16384 x 12-blob icosahedra monolayer)"}
-    for prec in ("fp32", "fp64"):
-        rmb.mobility_matvec(ctx, sysd, lt, prec, out)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
+def matvec_leg(rmb, torch, ctx, S, reps=20):
+    """Wall mobility products of prefixes of the 128 x 128 icosahedron
+    monolayer (1024 ... 16384 bodies, 12,288 ... 196,608 blobs): median of
+    `reps` launches after a warm-up, each launch timed with its own events."""
+    res = {"workload": "wall RPY mobility product, 16384 x 12-blob icosahedra monolayer (196,608 blobs) and "
+                       "prefixes of it", "sweep": []}
+    for n_bodies in (1024, 2048, 4096, 8192, 16384):
+        sus, lam = S.icosahedra_monolayer(n_bodies=n_bodies)
+        sysd = rmb.System.from_suspension(sus)
+        lt = torch.tensor(lam, dtype=torch.float64, device="cuda")
+        out = torch.empty_like(lt)
+        row = {"n_blobs": sus.n_blobs}
+        for prec in ("fp32", "fp64"):
             rmb.mobility_matvec(ctx, sysd, lt, prec, out)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        res[f"{prec}_ms"] = round(ms, 3)
-        res[f"{prec}_pairs_per_s"] = sus.n_blobs ** 2 / (ms * 1e-3)
-        k = "pair_f32_wall" if prec == "fp32" else "pair_f64_wall"
-        res[f"{prec}_tflops"] = product_flops(rmb, k, sus.n_blobs) / (ms * 1e-3) / 1e12
-        log(f"  matvec {prec}: {ms:.2f} ms, {res[f'{prec}_pairs_per_s']:.3e} pairs/s")
+            torch.cuda.synchronize()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+            for e0, e1 in ev:
+                e0.record()
+                rmb.mobility_matvec(ctx, sysd, lt, prec, out)
+                e1.record()
+            torch.cuda.synchronize()
+            ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+            k = "pair_f32_wall" if prec == "fp32" else "pair_f64_wall"
+            row[f"{prec}_ms"] = round(ms, 4)
+            row[f"{prec}_pairs_per_s"] = sus.n_blobs ** 2 / (ms * 1e-3)
+            row[f"{prec}_tflops"] = product_flops(rmb, k, sus.n_blobs) / (ms * 1e-3) / 1e12
+            log(f"  matvec {sus.n_blobs} blobs {prec}: {ms:.3f} ms, {row[f'{prec}_pairs_per_s']:.3e} pairs/s, "
+                f"{row[f'{prec}_tflops']:.1f} TFLOP/s")
+        res["sweep"].append(row)
+        del lt, out
+    full = res["sweep"][-1]
+    for k in ("fp32_ms", "fp32_pairs_per_s", "fp32_tflops", "fp64_ms", "fp64_pairs_per_s", "fp64_tflops"):
+        res[k] = full[k]
     return res
 
 
@@ -254,6 +307,8 @@ def main():
     ap.add_argument("--no-factor", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="timed solves only (for profiling)")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
@@ -290,6 +345,15 @@ def main():
                 "launches": k_n}
     log(f"  pair f32 wall kernel ({'symmetric B=%d' % blk if sym else 'one-sided'}): {avg_ms:.4f} ms avg "
         f"over {k_n} launches, {achieved:.1f} TFLOP/s")
+    traffic, detail = measured_traffic()
+    roofline["traffic"] = traffic
+    if isinstance(detail, dict):
+        roofline["traffic_detail"] = {k: detail[k] for k in ("fetch_bytes_per_launch", "write_bytes_per_launch",
+                                                              "copy_factor_fetch", "copy_factor_write", "profile")}
+    elif detail:
+        roofline["traffic_detail"] = detail
+    if args.calib_copy:
+        copy_calibration(torch, args.calib_copy)
 
     line = {"metric": METRIC, "value": value, "unit": "blob-pair interactions/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,

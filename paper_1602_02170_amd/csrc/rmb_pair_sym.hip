@@ -107,70 +107,128 @@ __device__ __forceinline__ double rsqrt64(double x) {
     double e = fma(-x * y, y, 1.0);
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
-__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
+// The result of a transcendental instruction needs one wait state before a
+// VALU instruction reads it.  The compiler inserts it for its own consumers
+// but not for the inline-asm consumers below, so the wait is part of the
+// instruction's own asm.
+__device__ __forceinline__ float rsqrt_r(float x) {
+    float y;
+    asm("v_rsq_f32_e32 %0, %1\n\ts_nop 0" : "=v"(y) : "v"(x));
+    return y;
+}
 __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt64(x); }
+
+// Arithmetic between two or three register operands.  On gfx950 the
+// two-VGPR-source VOP2 encodings of v_mul/v_add/v_sub/v_fmac_f32 issue at
+// about 21 lanes per clock per SIMD, while the same operations in VOP3
+// encoding issue at 27-30, so the FP32 forms are written as VOP3 explicitly
+// (the compiler would shrink them to VOP2).  Operations with a constant
+// operand stay plain C: the compiler gives them literal or inline-constant
+// forms, which also issue at about 30.  FP64 arithmetic is VOP3 only.
+template <typename R>
+struct VOp;
+template <>
+struct VOp<float> {
+    static __device__ __forceinline__ float mul(float a, float b) {
+        float d;
+        asm("v_mul_f32_e64 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+        return d;
+    }
+    static __device__ __forceinline__ float add(float a, float b) {
+        float d;
+        asm("v_add_f32_e64 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+        return d;
+    }
+    static __device__ __forceinline__ float sub(float a, float b) {
+        float d;
+        asm("v_sub_f32_e64 %0, %1, %2" : "=v"(d) : "v"(a), "v"(b));
+        return d;
+    }
+    static __device__ __forceinline__ float fma(float a, float b, float c) {
+        float d;
+        asm("v_fma_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
+        return d;
+    }
+    // 1 - a b
+    static __device__ __forceinline__ float one_minus(float a, float b) {
+        float d;
+        asm("v_fma_f32 %0, -%1, %2, 1.0" : "=v"(d) : "v"(a), "v"(b));
+        return d;
+    }
+};
+template <>
+struct VOp<double> {
+    static __device__ __forceinline__ double mul(double a, double b) { return a * b; }
+    static __device__ __forceinline__ double add(double a, double b) { return a + b; }
+    static __device__ __forceinline__ double sub(double a, double b) { return a - b; }
+    static __device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
+    static __device__ __forceinline__ double one_minus(double a, double b) { return ::fma(-a, b, 1.0); }
+};
 
 // Coefficients of one pair block, shared by both contractions:
 //   M_ij f   = A f + Bv (r . f) r + W f,   W f = c1 f + (c2 (e.f) + c3 f_z) e + (c4 (e.f) + c5 f_z) z
 //   M_ij^T f = A f + Bv (r . f) r + c1 f + (c2 (e.f) + c4 f_z) e + (c3 (e.f) + c5 f_z) z
 template <typename R, bool WALL>
 struct PairCoef {
-    R ciso, crr;                 // RPY: ciso I + crr r r^T
-    R c1, c2, c3, c4, c5, invL;  // wall image (R = (rx, ry, Rz), e = R invL)
+    using P = VOp<R>;
+    R iso, crr;                  // ciso + c1 (ciso alone in free space), and crr: ciso I + crr r r^T
+    R c2, c3, c4, c5, invL;      // wall image (R = (rx, ry, Rz), e = R invL)
     R Rz;
 
     __device__ __forceinline__ void eval(R rx, R ry, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
-        const R rxy2 = rx * rx + ry * ry;
-        const R d2 = rz * rz + rxy2;
+        const R rxy2 = P::fma(ry, ry, P::mul(rx, rx));
+        const R d2 = P::fma(rz, rz, rxy2);
         const R inv_d = rsqrt_r(d2 + tiny);
-        const R d = d2 * inv_d;
-        const R t = a * inv_d;
-        const R t2 = t * t;
-        const R iso_far = t * ((R)0.5 * t2 + (R)0.75);
-        const R rr_far = t * ((R)-1.5 * t2 + (R)0.75) * (inv_d * inv_d);
-        const R iso_near = (R)1 - kiso * d;
-        const R rr_near = krr * inv_d;
+        const R d = P::mul(d2, inv_d);
+        const R t = P::mul(a, inv_d);
+        const R t2 = P::mul(t, t);
+        const R iso_far = P::mul(t, (R)0.5 * t2 + (R)0.75);
+        const R rr_far = P::mul(P::mul(t, (R)-1.5 * t2 + (R)0.75), P::mul(inv_d, inv_d));
+        const R iso_near = P::one_minus(kiso, d);
+        const R rr_near = P::mul(krr, inv_d);
         const bool near = d2 <= four_a2;
-        ciso = near ? iso_near : iso_far;
+        const R ciso = near ? iso_near : iso_far;
         crr = near ? rr_near : rr_far;
         if (WALL) {
-            Rz = rz + (R)2 * zj;
-            const R L2 = Rz * Rz + rxy2;
+            Rz = (R)2 * zj + rz;
+            const R L2 = P::fma(Rz, Rz, rxy2);
             invL = rsqrt_r(L2);
-            const R xw = a * invL, hh = zj * invL, ez = Rz * invL;
-            const R xw2 = xw * xw, xw4 = xw2 * xw2, ez2 = ez * ez;
-            const R hh2 = hh * hh, ezh = ez * hh;
-            const R T = hh2 - ezh;
+            const R xw = P::mul(a, invL), hh = P::mul(zj, invL), ez = P::mul(Rz, invL);
+            const R xw2 = P::mul(xw, xw), xw4 = P::mul(xw2, xw2), ez2 = P::mul(ez, ez);
+            const R hh2 = P::mul(hh, hh), ezh = P::mul(ez, hh);
+            const R T = P::sub(hh2, ezh);
             const R xq = (R)0.25 * xw;
-            c1 = xq * (xw4 * ((R)-10 * ez2 + (R)2) + (xw2 * ((R)6 * ez2 - (R)2) + ((R)6 * T - (R)3)));
-            c2 = xq * (xw4 * ((R)70 * ez2 - (R)10) + (xw2 * ((R)-30 * ez2 + (R)6) + ((R)-18 * T - (R)3)));
+            const R c1 = P::mul(xq, P::fma(xw4, (R)-10 * ez2 + (R)2, P::fma(xw2, (R)6 * ez2 - (R)2, (R)6 * T - (R)3)));
+            c2 = P::mul(xq, P::fma(xw4, (R)70 * ez2 - (R)10, P::fma(xw2, (R)-30 * ez2 + (R)6, (R)-18 * T - (R)3)));
             const R hh15 = (R)1.5 * hh;
-            const R m3 = hh15 * ((R)-6 * ez2 + ((R)6 * ezh + (R)1));
-            const R e3 = xw2 * ((R)15 * ez2 - (R)3) + xw4 * ((R)-35 * ez2 + (R)10);
-            c3 = xw * (ez * e3 + m3);
-            c4 = xw * ((R)-5 * ez * xw4 + hh15);
-            c5 = xw * (xw4 * ((R)15 * ez2 - (R)2) + (R)-3 * (ez2 * xw2 + hh2));
+            const R m3 = P::mul(hh15, (R)-6 * ez2 + ((R)6 * ezh + (R)1));
+            const R e3 = P::fma(xw4, (R)-35 * ez2 + (R)10, P::mul(xw2, (R)15 * ez2 - (R)3));
+            c3 = P::mul(xw, P::fma(ez, e3, m3));
+            c4 = P::mul(xw, P::fma((R)-5 * ez, xw4, hh15));
+            c5 = P::mul(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)));
+            iso = P::add(ciso, c1);
+        } else {
+            iso = ciso;
         }
     }
     // out += M_ij f  (transpose = false) or M_ij^T f (transpose = true)
     template <bool TRANSPOSE>
     __device__ __forceinline__ void apply(R rx, R ry, R rz, R fx, R fy, R fz, R &ox, R &oy, R &oz) const {
-        const R pxy = rx * fx + ry * fy;
-        const R sr = crr * (rz * fz + pxy);
+        const R pxy = P::fma(ry, fy, P::mul(rx, fx));
+        const R sr = P::mul(crr, P::fma(rz, fz, pxy));
         if (!WALL) {
-            ox += ciso * fx + sr * rx;
-            oy += ciso * fy + sr * ry;
-            oz += ciso * fz + sr * rz;
+            ox = P::fma(iso, fx, P::fma(sr, rx, ox));
+            oy = P::fma(iso, fy, P::fma(sr, ry, oy));
+            oz = P::fma(iso, fz, P::fma(sr, rz, oz));
         } else {
-            const R ef = (Rz * fz + pxy) * invL;
+            const R ef = P::mul(P::fma(Rz, fz, pxy), invL);
             const R ce = TRANSPOSE ? c4 : c3, cz = TRANSPOSE ? c3 : c4;
-            const R g = (c2 * ef + ce * fz) * invL;
-            const R kz = cz * ef + c5 * fz;
-            const R iso = ciso + c1;
-            const R gr = sr + g;
-            ox += iso * fx + gr * rx;
-            oy += iso * fy + gr * ry;
-            oz += iso * fz + sr * rz + g * Rz + kz;
+            const R g = P::mul(P::fma(c2, ef, P::mul(ce, fz)), invL);
+            const R kz = P::fma(cz, ef, P::mul(c5, fz));
+            const R gr = P::add(sr, g);
+            ox = P::fma(iso, fx, P::fma(gr, rx, ox));
+            oy = P::fma(iso, fy, P::fma(gr, ry, oy));
+            oz = P::fma(iso, fz, P::fma(sr, rz, P::fma(g, Rz, P::add(oz, kz))));
         }
     }
 };
