@@ -2,21 +2,29 @@
 // too large for LDS (Sec. 2.2.2: the per-body factorisation of M_pp behind
 // eq:saddle_M_precon), e.g. 162-blob shells (486 x 486).
 //
-// Storage per body, leading dimension Mp = m rounded up to the panel width
-// NB (padding rows/columns hold the identity, so the padded factor is
-// blockdiag(L, I)):
-//   L  : Mp x Mp, column-major, lower triangle
-//   Y  : Mp x 6, row-major  (L^-1 K_p, zero in the padding)
-//   Sc : 6 x 6 lower        (Cholesky factor of Y^T Y)
+// Storage per body (doubles), Mp = 3n rounded up to 32; rows and columns
+// past 3n hold the identity, so the padded factor is blockdiag(L, I):
+//   L    : Mp x Mp, column-major, lower triangle (the upper triangle is zero)
+//   Y    : Mp x 6, row-major (L^-1 K_p, zero in the padding)
+//   Dinv : the inverses of L's NB x NB diagonal blocks, block j/NB at
+//          offset j*NB, each column-major (room for NB = 32: Mp x 32)
+//   Sc   : 6 x 6 lower (Cholesky factor of S = Y^T Y)
 //
-// Factorisation: one workgroup (4 waves) per body, all bodies in one launch,
-// left-looking by panels of NB columns.  Panel update
+// Build, each launch covering all bodies: assembly of the lower triangle,
+// Cholesky (with the diagonal-block inverses), projection (Y, S, Sc).
+//
+// Cholesky: one workgroup (4 waves) per body, left-looking by panels of NB
+// columns.  Panel update
 //   A[j:, j:j+NB] -= L[j:, 0:j] L[j:j+NB, 0:j]^T
-// runs on FP64 matrix cores (v_mfma_f64_16x16x4: D[16x16] += A[16x4] B[4x16])
-// with operands read straight from global memory, so each column block of L
-// is read once per later panel and the trailing matrix is never rewritten.
-// The panel's NB x NB diagonal block is then factorised in LDS and the rows
-// below it are solved against it (one row per lane, registers).
+// runs on FP64 matrix cores (v_mfma_f64_16x16x4: D[16x16] += A[16x4] B[4x16]);
+// the operands of the next 16 columns of L are loaded while the current ones
+// are multiplied.  The panel's NB x NB diagonal block is then factorised in
+// LDS (one barrier per column) and inverted, and the rows below it become
+// x = a L11^-T, a product with the inverse, also on matrix cores.
+//
+// Substitutions (projection and apply) go by panels, right-looking: the
+// panel's unknowns are x_j = Dinv_j b_j, then every later (earlier, for
+// L^T) row is updated at once, with all of its loads in flight.
 #include <cmath>
 
 #include "rmb_blocks.h"
@@ -34,36 +42,73 @@ __device__ __forceinline__ dbl4 mfma16x16x4(double a, double b, dbl4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+constexpr int kDinvCols = 32;  // room reserved per row for the diagonal-block inverses
+
+__device__ __forceinline__ double *big_Y(const BigBody &it) { return it.w.factor + (int64_t)it.Mp * it.Mp; }
+__device__ __forceinline__ double *big_Dinv(const BigBody &it) { return big_Y(it) + 6 * (int64_t)it.Mp; }
+__device__ __forceinline__ double *big_Sc(const BigBody &it) { return big_Dinv(it) + (int64_t)kDinvCols * it.Mp; }
 
 // ---------------------------------------------------------------------------
-// assembly of the padded block (column-major), grid = (body, chunk)
+// assembly of the lower triangle of the padded block (column-major)
 // ---------------------------------------------------------------------------
 
+constexpr int kAsmBlobs = 16;      // blobs per tile side (48 x 48 entries)
+constexpr int kAsmPadGroups = 8;   // workgroups per body writing the padding
+
+int asm_tiles(int max_Mp) {
+    const int T = (max_Mp / 3 + kAsmBlobs - 1) / kAsmBlobs;
+    return T * (T + 1) / 2 + kAsmPadGroups;
+}
+
+// grid = (body, tile): tile y < T(T+1)/2 is the blob-block pair (I, J),
+// I >= J, y = I(I+1)/2 + J; each thread forms one 3x3 pair block into an
+// LDS tile, which is then written out column by column.  The next
+// kAsmPadGroups tiles write the identity padding.
 __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__restrict__ items) {
+    constexpr int E = 3 * kAsmBlobs;
+    __shared__ double tile[E][E + 1];  // [column][row]
     const BigBody it = items[blockIdx.x];
     const int n = it.w.n_blobs, m = 3 * n, Mp = it.Mp;
     double *A = it.w.factor;
-    const int64_t npairs = (int64_t)n * n;
-    for (int64_t pq = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; pq < npairs;
-         pq += (int64_t)gridDim.y * blockDim.x) {
-        const int i = (int)(pq / n), j = (int)(pq % n);
-        const double *ri = it.w.pos + 3 * (it.w.blob0 + i);
-        const double *rj = it.w.pos + 3 * (it.w.blob0 + j);
-        const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
-        double B[9];
-        pair_block_f64(a_i, a_j, it.w.a, it.w.wall != 0, B);
-        for (int p = 0; p < 3; ++p)
-            for (int q = 0; q < 3; ++q) A[(int64_t)(3 * j + q) * Mp + 3 * i + p] = it.w.pref * B[3 * p + q];
+    const int T = (n + kAsmBlobs - 1) / kAsmBlobs;
+    const int ntile = T * (T + 1) / 2;
+    const int y = blockIdx.y, tid = threadIdx.x;
+    if (y < ntile) {
+        int I = (int)((sqrt(8.0 * y + 1.0) - 1.0) * 0.5);
+        while ((I + 1) * (I + 2) / 2 <= y) ++I;
+        while (I * (I + 1) / 2 > y) --I;
+        const int J = y - I * (I + 1) / 2;
+        const int il = tid % kAsmBlobs, jl = tid / kAsmBlobs;
+        const int i = I * kAsmBlobs + il, j = J * kAsmBlobs + jl;
+        if (i < n && j < n) {
+            const double *ri = it.w.pos + 3 * (it.w.blob0 + i);
+            const double *rj = it.w.pos + 3 * (it.w.blob0 + j);
+            const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
+            double B[9];
+            pair_block_f64(a_i, a_j, it.w.a, it.w.wall != 0, B);
+            for (int p = 0; p < 3; ++p)
+                for (int q = 0; q < 3; ++q) tile[3 * jl + q][3 * il + p] = it.w.pref * B[3 * p + q];
+        }
+        __syncthreads();
+        const int r0 = E * I, c0 = E * J;
+        for (int e = tid; e < E * E; e += 256) {
+            const int c = e / E, r = e % E;
+            if (r0 + r < m && c0 + c < m) A[(int64_t)(c0 + c) * Mp + r0 + r] = tile[c][r];
+        }
+        return;
     }
-    // identity padding
-    const int64_t pad = (int64_t)Mp * Mp - (int64_t)m * Mp;  // columns m..Mp-1 entirely
-    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < pad; e += (int64_t)gridDim.y * blockDim.x) {
+    const int g = y - ntile;
+    if (g >= kAsmPadGroups) return;
+    const int64_t stride = (int64_t)kAsmPadGroups * 256;
+    // columns m..Mp-1: identity
+    const int64_t pad = (int64_t)(Mp - m) * Mp;
+    for (int64_t e = (int64_t)g * 256 + tid; e < pad; e += stride) {
         const int64_t col = m + e / Mp, row = e % Mp;
         A[col * Mp + row] = row == col ? 1.0 : 0.0;
     }
-    // rows m..Mp-1 of columns 0..m-1
+    // rows m..Mp-1 of columns 0..m-1: zero
     const int64_t padr = (int64_t)(Mp - m) * m;
-    for (int64_t e = (int64_t)blockIdx.y * blockDim.x + threadIdx.x; e < padr; e += (int64_t)gridDim.y * blockDim.x) {
+    for (int64_t e = (int64_t)g * 256 + tid; e < padr; e += stride) {
         const int64_t col = e / (Mp - m), row = m + e % (Mp - m);
         A[col * Mp + row] = 0.0;
     }
@@ -76,12 +121,17 @@ __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__re
 template <int NB>
 __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restrict__ items) {
     constexpr int CT = NB / 16;  // column tiles per panel
-    constexpr int G = 4;         // row tiles per wave per pass
-    __shared__ double D[NB * NB];
+    constexpr int G = 2;         // row tiles per wave per pass (keeps VGPRs <= 256: two bodies per CU)
+    constexpr int U = 4;         // steps of 4 columns per prefetched chunk
+    __shared__ double D[NB * NB];   // diagonal block being factorised (column-major)
+    __shared__ double Lc[NB * NB];  // its Cholesky factor
+    __shared__ double W[NB * NB];   // the factor's inverse
+    __shared__ double Li[NB];       // reciprocals of the factor's diagonal
     __shared__ int bad;
     const BigBody it = items[blockIdx.x];
     const int Mp = it.Mp;
     double *L = it.w.factor;
+    double *Dinv = big_Dinv(it);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     if (tid == 0) bad = 0;
@@ -103,17 +153,36 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
                         acc[g][c][r] = row0[g] >= 0 ? L[(int64_t)(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] : 0.0;
                 }
             }
-            for (int k0 = 0; k0 < j; k0 += 4) {
-                const int64_t kcol = (int64_t)(k0 + l4) * Mp;
-                double b[CT];
+            if (j > 0) {
+                // j is a multiple of 16: whole chunks of 4 * U columns
+                double a0[U][G], b0[U][CT], a1[U][G], b1[U][CT];
+                auto load = [&](int k0, double (&a)[U][G], double (&b)[U][CT]) {
 #pragma unroll
-                for (int c = 0; c < CT; ++c) b[c] = L[kcol + j + 16 * c + l16];
+                    for (int u = 0; u < U; ++u) {
+                        const int kc = (k0 + 4 * u + l4) * Mp;  // Mp^2 < 2^31
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    if (row0[g] < 0) continue;
-                    const double a = -L[kcol + row0[g] + l16];
+                        for (int c = 0; c < CT; ++c) b[u][c] = L[kc + j + 16 * c + l16];
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) acc[g][c] = mfma16x16x4(a, b[c], acc[g][c]);
+                        for (int g = 0; g < G; ++g) a[u][g] = row0[g] >= 0 ? -L[kc + row0[g] + l16] : 0.0;
+                    }
+                };
+                auto mma = [&](const double (&a)[U][G], const double (&b)[U][CT]) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u)
+#pragma unroll
+                        for (int g = 0; g < G; ++g) {
+                            if (row0[g] < 0) continue;  // wave-uniform
+#pragma unroll
+                            for (int c = 0; c < CT; ++c) acc[g][c] = mfma16x16x4(a[u][g], b[u][c], acc[g][c]);
+                        }
+                };
+                load(0, a0, b0);
+                for (int k0 = 0; k0 < j; k0 += 8 * U) {
+                    if (k0 + 4 * U < j) load(k0 + 4 * U, a1, b1);
+                    mma(a0, b0);
+                    if (k0 + 4 * U >= j) break;
+                    if (k0 + 8 * U < j) load(k0 + 8 * U, a0, b0);
+                    mma(a1, b1);
                 }
             }
 #pragma unroll
@@ -127,49 +196,81 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
             }
         }
         __syncthreads();
-        // 2. factorise the diagonal block in LDS
+        // 2. factorise the diagonal block in LDS: step c reads column c of D
+        //    and writes only columns > c of D and column c of Lc
         for (int e = tid; e < NB * NB; e += 256) {
             const int r = e % NB, c = e / NB;
-            D[c * NB + r] = L[(int64_t)(j + c) * Mp + j + r];
+            D[e] = r >= c ? L[(int64_t)(j + c) * Mp + j + r] : 0.0;
         }
         __syncthreads();
         for (int c = 0; c < NB; ++c) {
-            if (tid == 0) {
-                const double d = D[c * NB + c];
-                if (!(d > 0.0)) bad = 1;
-                D[c * NB + c] = sqrt(d > 0.0 ? d : 1.0);
-            }
-            __syncthreads();
-            const double dc = D[c * NB + c];
-            for (int r = c + 1 + tid; r < NB; r += 256) D[c * NB + r] /= dc;
-            __syncthreads();
+            const double dcc = D[c * NB + c];
+            if (tid == 0 && !(dcc > 0.0)) bad = 1;
+            const double s = sqrt(dcc > 0.0 ? dcc : 1.0), inv = 1.0 / s, inv2 = inv * inv;
+            if (tid < NB) Lc[c * NB + tid] = tid > c ? D[c * NB + tid] * inv : (tid == c ? s : 0.0);
+            if (tid == 0) Li[c] = inv;
             const int rem = NB - c - 1;
             for (int e = tid; e < rem * rem; e += 256) {
                 const int r = c + 1 + e % rem, cc = c + 1 + e / rem;
-                if (r >= cc) D[cc * NB + r] -= D[c * NB + r] * D[c * NB + cc];
+                if (r >= cc) D[cc * NB + r] -= D[c * NB + r] * D[c * NB + cc] * inv2;
             }
             __syncthreads();
         }
+        // 3. W = L11^-1, column k by thread k, built in place in LDS
+        if (tid < NB) {
+            const int k = tid;
+            for (int i = 0; i < k; ++i) W[k * NB + i] = 0.0;
+            W[k * NB + k] = Li[k];
+            for (int i = k + 1; i < NB; ++i) {
+                double v = 0.0;
+                for (int mm = k; mm < i; ++mm) v -= Lc[mm * NB + i] * W[k * NB + mm];
+                W[k * NB + i] = v * Li[i];
+            }
+        }
+        __syncthreads();
         for (int e = tid; e < NB * NB; e += 256) {
             const int r = e % NB, c = e / NB;
-            L[(int64_t)(j + c) * Mp + j + r] = r >= c ? D[c * NB + r] : 0.0;
+            L[(int64_t)(j + c) * Mp + j + r] = Lc[e];
+            Dinv[(int64_t)j * NB + e] = W[e];
         }
-        // 3. rows below: x L11^T = a  (one row per lane)
-        for (int r = j + NB + tid; r < Mp; r += 256) {
-            double x[NB];
+        // 4. rows below the diagonal block: x L11^T = a, i.e. X = A W^T, on
+        //    matrix cores (A operand from the panel, B operand W^T from LDS)
+        {
+            const int RT4 = (Mp - j - NB) / 16;
+            for (int pass = 0; pass * 4 * G < RT4; ++pass) {
+                dbl4 acc[G][CT];
+                int row0[G];
 #pragma unroll
-            for (int c = 0; c < NB; ++c) x[c] = L[(int64_t)(j + c) * Mp + r];
+                for (int g = 0; g < G; ++g) {
+                    const int t = pass * 4 * G + g * 4 + wave;
+                    row0[g] = t < RT4 ? j + NB + 16 * t : -1;
 #pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                double v = x[c];
+                    for (int c = 0; c < CT; ++c) acc[g][c] = dbl4{0.0, 0.0, 0.0, 0.0};
+                }
 #pragma unroll
-                for (int l = 0; l < c; ++l) v -= x[l] * D[l * NB + c];
-                x[c] = v / D[c * NB + c];
+                for (int k0 = 0; k0 < NB; k0 += 4) {
+                    double b[CT];
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) b[c] = W[(k0 + l4) * NB + 16 * c + l16];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        if (row0[g] < 0) continue;  // wave-uniform
+                        const double a = L[(j + k0 + l4) * Mp + row0[g] + l16];
+#pragma unroll
+                        for (int c = 0; c < CT; ++c) acc[g][c] = mfma16x16x4(a, b[c], acc[g][c]);
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if (row0[g] < 0) continue;
+#pragma unroll
+                    for (int c = 0; c < CT; ++c)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) L[(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] = acc[g][c][r];
+                }
             }
-#pragma unroll
-            for (int c = 0; c < NB; ++c) L[(int64_t)(j + c) * Mp + r] = x[c];
         }
-        // zero the strict upper triangle of the panel's columns above the diagonal block
+        // 5. zero the panel's columns above the diagonal block
         for (int e = tid; e < j * NB; e += 256) {
             const int r = e % j, c = e / j;
             L[(int64_t)(j + c) * Mp + r] = 0.0;
@@ -180,34 +281,41 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
 }
 
 // ---------------------------------------------------------------------------
-// blocked triangular solves with R right-hand sides held in LDS (row-major
-// Mp x R), panels of NB
+// blocked substitutions with R right-hand sides held in LDS (row-major
+// Mp x R).  Dj: NB x NB staging, T: NB x R.
 // ---------------------------------------------------------------------------
 
 // X <- L^-1 X
 template <int NB, int R>
-__device__ void forward_blocked(const double *__restrict__ L, int Mp, double *X, double *D) {
+__device__ void forward_rl(const double *__restrict__ L, const double *__restrict__ Dinv, int Mp, double *X,
+                           double *Dj, double *T) {
     const int tid = threadIdx.x;
     for (int j = 0; j < Mp; j += NB) {
-        // X[j:j+NB] -= L[j:j+NB, 0:j] X[0:j]
+        for (int e = tid; e < NB * NB; e += 256) Dj[e] = Dinv[(int64_t)j * NB + e];
+        __syncthreads();
+        // x_j = Dinv_j b_j
         for (int o = tid; o < NB * R; o += 256) {
             const int r = o / R, c = o % R;
             double acc = 0.0;
-            for (int k = 0; k < j; ++k) acc += L[(int64_t)k * Mp + j + r] * X[k * R + c];
-            X[(j + r) * R + c] -= acc;
-        }
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int r = e % NB, c = e / NB;
-            D[c * NB + r] = L[(int64_t)(j + c) * Mp + j + r];
+            for (int l = 0; l <= r; ++l) acc += Dj[l * NB + r] * X[(j + l) * R + c];
+            T[o] = acc;
         }
         __syncthreads();
-        // forward substitution with the diagonal block, one thread per rhs
-        if (tid < R) {
-            for (int r = 0; r < NB; ++r) {
-                double v = X[(j + r) * R + tid];
-                for (int l = 0; l < r; ++l) v -= D[l * NB + r] * X[(j + l) * R + tid];
-                X[(j + r) * R + tid] = v / D[r * NB + r];
+        for (int o = tid; o < NB * R; o += 256) X[j * R + o] = T[o];
+        __syncthreads();
+        // later rows: b[r] -= L[r, j:j+NB] x_j
+        for (int r = j + NB + tid; r < Mp; r += 256) {
+            double acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = 0.0;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const double lv = L[(int64_t)(j + l) * Mp + r];
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += lv * X[(j + l) * R + c];
             }
+#pragma unroll
+            for (int c = 0; c < R; ++c) X[r * R + c] -= acc[c];
         }
         __syncthreads();
     }
@@ -215,28 +323,36 @@ __device__ void forward_blocked(const double *__restrict__ L, int Mp, double *X,
 
 // X <- L^-T X
 template <int NB, int R>
-__device__ void backward_blocked(const double *__restrict__ L, int Mp, double *X, double *D) {
+__device__ void backward_rl(const double *__restrict__ L, const double *__restrict__ Dinv, int Mp, double *X,
+                            double *Dj, double *T) {
     const int tid = threadIdx.x;
     for (int j = Mp - NB; j >= 0; j -= NB) {
-        // X[j:j+NB] -= L[j+NB:Mp, j:j+NB]^T X[j+NB:Mp]
+        for (int e = tid; e < NB * NB; e += 256) Dj[e] = Dinv[(int64_t)j * NB + e];
+        __syncthreads();
+        // x_j = Dinv_j^T b_j: x[r] = sum_{l >= r} Dinv_j[l][r] b[l]
         for (int o = tid; o < NB * R; o += 256) {
-            const int cc = o / R, c = o % R;
+            const int r = o / R, c = o % R;
             double acc = 0.0;
-            const double *col = L + (int64_t)(j + cc) * Mp;
-            for (int k = j + NB; k < Mp; ++k) acc += col[k] * X[k * R + c];
-            X[(j + cc) * R + c] -= acc;
-        }
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int r = e % NB, c = e / NB;
-            D[c * NB + r] = L[(int64_t)(j + c) * Mp + j + r];
+            for (int l = r; l < NB; ++l) acc += Dj[r * NB + l] * X[(j + l) * R + c];
+            T[o] = acc;
         }
         __syncthreads();
-        if (tid < R) {
-            for (int r = NB - 1; r >= 0; --r) {
-                double v = X[(j + r) * R + tid];
-                for (int l = r + 1; l < NB; ++l) v -= D[r * NB + l] * X[(j + l) * R + tid];
-                X[(j + r) * R + tid] = v / D[r * NB + r];
+        for (int o = tid; o < NB * R; o += 256) X[j * R + o] = T[o];
+        __syncthreads();
+        // earlier rows: b[k] -= sum_l L[j+l][k] x[j+l]
+        for (int k = tid; k < j; k += 256) {
+            double acc[R];
+#pragma unroll
+            for (int c = 0; c < R; ++c) acc[c] = 0.0;
+            const double *col = L + (int64_t)k * Mp + j;
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                const double lv = col[l];
+#pragma unroll
+                for (int c = 0; c < R; ++c) acc[c] += lv * X[(j + l) * R + c];
             }
+#pragma unroll
+            for (int c = 0; c < R; ++c) X[k * R + c] -= acc[c];
         }
         __syncthreads();
     }
@@ -246,7 +362,8 @@ __device__ void backward_blocked(const double *__restrict__ L, int Mp, double *X
 template <int NB>
 __global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__restrict__ items) {
     extern __shared__ double lds[];
-    __shared__ double D[NB * NB];
+    __shared__ double Dj[NB * NB];
+    __shared__ double T[NB * 6];
     __shared__ double S[36];
     __shared__ int bad;
     const BigBody it = items[blockIdx.x];
@@ -267,7 +384,7 @@ __global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__res
         Y[e] = v;
     }
     __syncthreads();
-    forward_blocked<NB, 6>(L, Mp, Y, D);
+    forward_rl<NB, 6>(L, big_Dinv(it), Mp, Y, Dj, T);
     if (tid < 36) {
         const int r = tid / 6, c = tid % 6;
         double acc = 0.0;
@@ -293,9 +410,9 @@ __global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__res
         }
     }
     __syncthreads();
-    double *Yg = it.w.factor + (int64_t)Mp * Mp;
+    double *Yg = big_Y(it);
     for (int e = tid; e < 6 * Mp; e += 256) Yg[e] = Y[e];
-    double *Sc = Yg + 6 * Mp;
+    double *Sc = big_Sc(it);
     if (tid < 36) Sc[tid] = ((tid % 6) <= (tid / 6)) ? S[tid] : 0.0;
     if (tid == 0 && bad) atomicOr(it.w.flag, 8);
 }
@@ -304,9 +421,11 @@ __global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__res
 // (grid.y = groups of 8 rhs).  lds: X (Mp x 8).
 template <int NB>
 __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob *__restrict__ jobs, int32_t n_jobs) {
+    constexpr int R = 8, QP = 16;  // rhs per workgroup; partial sums per (rhs, k) of Y^T t
     extern __shared__ double lds[];
-    __shared__ double D[NB * NB];
-    __shared__ double g[8][6];
+    __shared__ double Dj[NB * NB > QP * R * 6 ? NB * NB : QP * R * 6];
+    __shared__ double T[NB * R];
+    __shared__ double g[R][6];
     const int64_t w = blockIdx.x;
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
@@ -316,30 +435,43 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     const PrecondApplyJob &J = jobs[lo];
     const BigBody it = ((const BigBody *)J.items)[w - J.wg_begin];
     const int Mp = it.Mp, m = 3 * it.w.n_blobs, tid = threadIdx.x;
-    const int r0 = 8 * blockIdx.y;
-    const int R = min(8, J.nrhs - r0);
-    if (R <= 0) return;
+    const int r0 = R * blockIdx.y;
+    const int nr = min(R, J.nrhs - r0);
+    if (nr <= 0) return;
     const double *L = it.w.factor;
-    const double *Y = L + (int64_t)Mp * Mp, *Sc = Y + 6 * Mp;
+    const double *Y = big_Y(it), *Dinv = big_Dinv(it), *Sc = big_Sc(it);
     double *X = lds;  // Mp x 8
     const int64_t b3 = 3 * it.w.blob0, u6 = J.nb3 + 6 * (int64_t)it.w.body;
-    for (int e = tid; e < Mp * 8; e += 256) {
-        const int row = e / 8, c = e % 8;
-        X[e] = (row < m && c < R) ? J.in[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
+    for (int e = tid; e < Mp * R; e += 256) {
+        const int row = e / R, c = e % R;
+        X[e] = (row < m && c < nr) ? J.in[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
     }
     __syncthreads();
-    forward_blocked<NB, 8>(L, Mp, X, D);
-    // g = F - Y^T t, F = -bottom
-    if (tid < 48) {
-        const int c = tid / 6, k = tid % 6;
-        if (c < R) {
-            double acc = 0.0;
-            for (int l = 0; l < Mp; ++l) acc += Y[l * 6 + k] * X[l * 8 + c];
-            g[c][k] = -J.in[(int64_t)(r0 + c) * J.ld + u6 + k] - acc;
+    forward_rl<NB, R>(L, Dinv, Mp, X, Dj, T);
+    // g = F - Y^T t, F = -bottom: thread (c, qp) sums rows l = qp (mod QP)
+    // for k = 0..5, then the QP partials are added in order
+    double *part = Dj;  // [QP][R][6]
+    if (tid < QP * R) {
+        const int c = tid % R, qp = tid / R;
+        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+        for (int l = qp; l < Mp; l += QP) {
+            const double x = X[l * R + c];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc[k] += Y[l * 6 + k] * x;
         }
+#pragma unroll
+        for (int k = 0; k < 6; ++k) part[(qp * R + c) * 6 + k] = acc[k];
     }
     __syncthreads();
-    if (tid < R) {
+    if (tid < R * 6) {
+        const int c = tid / 6, k = tid % 6;
+        double acc = 0.0;
+        for (int qp = 0; qp < QP; ++qp) acc += part[(qp * R + c) * 6 + k];
+        g[c][k] = c < nr ? -J.in[(int64_t)(r0 + c) * J.ld + u6 + k] - acc : 0.0;
+    }
+    __syncthreads();
+    if (tid < nr) {
         double u[6];
         double *gg = g[tid];
         for (int i = 0; i < 6; ++i) {
@@ -354,23 +486,27 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         }
     }
     __syncthreads();
-    for (int e = tid; e < Mp * 8; e += 256) {
-        const int row = e / 8, c = e % 8;
-        if (c < R) {
-            double acc = X[e];
-            for (int k = 0; k < 6; ++k) acc += Y[row * 6 + k] * g[c][k];
-            X[e] = acc;
+    for (int row = tid; row < Mp; row += 256) {
+        double yk[6];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) yk[k] = Y[row * 6 + k];
+#pragma unroll
+        for (int c = 0; c < R; ++c) {
+            double acc = X[row * R + c];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) acc += yk[k] * g[c][k];
+            X[row * R + c] = acc;
         }
     }
     __syncthreads();
-    backward_blocked<NB, 8>(L, Mp, X, D);
-    for (int e = tid; e < m * 8; e += 256) {
-        const int row = e / 8, c = e % 8;
-        if (c < R) J.out[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];
+    backward_rl<NB, R>(L, Dinv, Mp, X, Dj, T);
+    for (int e = tid; e < m * R; e += 256) {
+        const int row = e / R, c = e % R;
+        if (c < nr) J.out[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];
     }
-    if (tid < 48) {
+    if (tid < R * 6) {
         const int c = tid / 6, k = tid % 6;
-        if (c < R) J.out[(int64_t)(r0 + c) * J.ld + u6 + k] = g[c][k];
+        if (c < nr) J.out[(int64_t)(r0 + c) * J.ld + u6 + k] = g[c][k];
     }
 }
 
@@ -380,7 +516,7 @@ int large_panel_width(int variant) { return variant == 1 ? 32 : 16; }
 
 hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int max_Mp, int variant, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_large_kernel, dim3(n_items, 16), dim3(256), 0, s, items);
+    hipLaunchKernelGGL(assemble_large_kernel, dim3(n_items, asm_tiles(max_Mp)), dim3(256), 0, s, items);
     const size_t lds = (size_t)max_Mp * 6 * sizeof(double);
     if (variant == 1) {
         hipLaunchKernelGGL(chol_large_kernel<32>, dim3(n_items), dim3(256), 0, s, items);

@@ -13,7 +13,8 @@ struct BodyWork {
     const double *pos;  // system's blob positions [nb][3]
     const double *q;    // this body's tracking point (3 doubles)
     double *factor;     // LDS path: Li = L^-1 (col-major), Y (m x 6), S^-1 (6 x 6);
-                        // large path: L (padded, col-major), Y, Sc (Cholesky of S)
+                        // large path: L (padded, col-major), Y, diagonal-block
+                        // inverses of L, Sc (Cholesky of S)
     int64_t blob0;      // first blob of the body
     int32_t n_blobs;
     int32_t body;       // body index within its system
@@ -33,11 +34,16 @@ struct BigBody {
 inline bool is_large_body(int64_t n_blobs) { return 3 * n_blobs > kSmallBodyMaxM; }
 inline int64_t padded_dim(int64_t n_blobs) { return (3 * n_blobs + 31) / 32 * 32; }
 
-// Factor storage of one body (doubles): L, Y (m x 6), Sc (6 x 6); large
-// bodies use the padded dimension.
+// Factor storage of one body (doubles).  Small bodies: L^-1 (m x m), Y
+// (m x 6), S^-1 (6 x 6).  Large bodies, padded dimension Mp: L (Mp x Mp),
+// Y (Mp x 6), inverses of L's diagonal blocks (Mp x 32), Sc (6 x 6).
 inline int64_t factor_doubles(int64_t n_blobs) {
-    const int64_t m = is_large_body(n_blobs) ? padded_dim(n_blobs) : 3 * n_blobs;
-    return m * m + 6 * m + 36;
+    if (!is_large_body(n_blobs)) {
+        const int64_t m = 3 * n_blobs;
+        return m * m + 6 * m + 36;
+    }
+    const int64_t Mp = padded_dim(n_blobs);
+    return Mp * Mp + 6 * Mp + 32 * Mp + 36;
 }
 
 // P^-1 applied to `nrhs` saddle vectors of one system (vector r at in + r*ld).
