@@ -186,9 +186,13 @@ def factor_leg(rmb, torch, ctx, S, reps=3):
                        "L^-1 K, Schur factor; apply to 8 right-hand sides",
            "factor_ms": ms, "factor_tflops": flops / (ms * 1e-3) / 1e12,
            "factor_frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"],
-           "apply_8rhs_ms": apply_ms, "panel_width": ctx.tuned_panel(Mp)}
+           "apply_8rhs_ms": apply_ms, "panel_width": ctx.tuned_panel(Mp),
+           "autotune": [t for t in ctx.tune_log() if t["padded_dim"] == Mp]}
     log(f"  batched factor: {ms:.2f} ms ({res['factor_tflops']:.2f} TFLOP/s), apply 8 rhs {apply_ms:.2f} ms, "
         f"panel width {res['panel_width']}")
+    for t in res["autotune"]:
+        log(f"    shape panel {t['panel']} row tiles {t['row_tiles']} chunk {t['chunk']}: {t['ms']:.2f} ms"
+            f"{'  (chosen)' if t['chosen'] else ''}")
     return res
 
 

@@ -131,11 +131,29 @@ rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, in
  * (*block = number of source splits).  A function of nb only. */
 rmb_status rmb_pair_plan(int64_t nb, int32_t *symmetric, int32_t *block);
 
-/* Panel width (16 or 32) the autotuner chose for the large-body
- * factorisation of padded block size `padded_dim` on this context (the
- * first factorisation of that size times both and keeps the faster), or 0
- * if no block of that size has been factorised yet. */
+/* Panel width (16 or 32) of the tile shape the autotuner chose for the
+ * large-body factorisation of padded block size `padded_dim` on this context
+ * (the first factorisation of that size times every candidate shape and
+ * keeps the fastest), or 0 if no block of that size has been factorised yet. */
 rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_width);
+
+/* One timing of the large-body factorisation autotuner. */
+typedef struct rmb_tune_record {
+    int32_t padded_dim; /* Mp: block size rounded up to 32 */
+    int32_t panel;      /* columns per Cholesky panel */
+    int32_t row_tiles;  /* 16-row tiles per wave per pass of the panel update */
+    int32_t chunk;      /* columns of L whose matrix-core operands are loaded ahead */
+    double ms;          /* time of the whole batched build with this shape */
+    int32_t chosen;     /* 1 for the shape kept for this padded size */
+    int32_t reserved;
+} rmb_tune_record;
+
+/* Copies up to `capacity` autotuner timings of this context, in the order
+ * they were taken, into `records` (host memory, caller-owned); *count
+ * receives the total number held (which may exceed capacity).
+ * RMB_EINVAL for a null count, a negative capacity, or a null records array
+ * with capacity > 0. */
+rmb_status rmb_ctx_tune_log(rmb_ctx ctx, int32_t capacity, rmb_tune_record *records, int32_t *count);
 
 /* ---------------------------------------------------------------------------
  * Blob mobility product  v = M lambda   (Sec. 2.2.1; eq:RPYTensor and the

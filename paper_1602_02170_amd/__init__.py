@@ -31,7 +31,7 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_mobility_matvec", "rmb_precond_factor", "rmb_precond_apply", "rmb_precond_destroy",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
-           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_pair_plan"]
+           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -50,6 +50,12 @@ class rmb_system(ctypes.Structure):
 class rmb_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("precision", ctypes.c_int32), ("restart", ctypes.c_int32),
                 ("max_iters", ctypes.c_int32), ("pad", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+
+
+class rmb_tune_record(ctypes.Structure):
+    _fields_ = [("padded_dim", ctypes.c_int32), ("panel", ctypes.c_int32), ("row_tiles", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("ms", ctypes.c_double), ("chosen", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class rmb_solve_info(ctypes.Structure):
@@ -97,6 +103,7 @@ def library(path: str = LIB_PATH):
         L.rmb_ctx_set_timing.argtypes = [vp, i32]
         L.rmb_ctx_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.rmb_ctx_tuned_panel.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.rmb_ctx_tune_log.argtypes = [vp, i32, ctypes.POINTER(rmb_tune_record), ctypes.POINTER(i32)]
         L.rmb_pair_plan.argtypes = [i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _LIB = L
     return _LIB
@@ -175,6 +182,16 @@ class Context:
         w = ctypes.c_int32()
         self.check(self.lib.rmb_ctx_tuned_panel(self.h, int(padded_dim), ctypes.byref(w)))
         return w.value
+
+    def tune_log(self) -> list:
+        """Every timing the large-body autotuner took on this context:
+        dicts with padded_dim, panel, row_tiles, chunk, ms, chosen."""
+        n = ctypes.c_int32()
+        self.check(self.lib.rmb_ctx_tune_log(self.h, 0, None, ctypes.byref(n)))
+        recs = (rmb_tune_record * max(n.value, 1))()
+        self.check(self.lib.rmb_ctx_tune_log(self.h, n.value, recs, ctypes.byref(n)))
+        return [{"padded_dim": r.padded_dim, "panel": r.panel, "row_tiles": r.row_tiles, "chunk": r.chunk,
+                 "ms": r.ms, "chosen": bool(r.chosen)} for r in recs[:n.value]]
 
     def check(self, st):
         if st != RMB_OK:

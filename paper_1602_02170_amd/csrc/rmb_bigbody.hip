@@ -118,11 +118,11 @@ __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__re
 // left-looking blocked Cholesky with MFMA panel updates
 // ---------------------------------------------------------------------------
 
-template <int NB>
+// NB: panel width; G: 16-row tiles per wave per pass; U: steps of 4 columns
+// per prefetched chunk (the autotuner picks among a few shapes).
+template <int NB, int G, int U>
 __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restrict__ items) {
     constexpr int CT = NB / 16;  // column tiles per panel
-    constexpr int G = 2;         // row tiles per wave per pass (keeps VGPRs <= 256: two bodies per CU)
-    constexpr int U = 4;         // steps of 4 columns per prefetched chunk
     __shared__ double D[NB * NB];   // diagonal block being factorised (column-major)
     __shared__ double Lc[NB * NB];  // its Cholesky factor
     __shared__ double W[NB * NB];   // the factor's inverse
@@ -512,28 +512,57 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
 
 // ---------------------------------------------------------------------------
 
-int large_panel_width(int variant) { return variant == 1 ? 32 : 16; }
+// Tile shapes the autotuner times: {panel width, row tiles per wave, steps
+// per prefetched chunk}.  Shapes with G * U <= 8 stay within 256 VGPRs
+// (two bodies per CU); the others trade occupancy for operand reuse.
+struct LargeShape {
+    int nb, g, u;
+};
+static constexpr LargeShape kLargeShapes[] = {{16, 2, 4}, {32, 2, 4}, {32, 2, 8}, {32, 4, 2}, {32, 1, 8}, {16, 4, 4}};
+constexpr int kLargeVariants = (int)(sizeof(kLargeShapes) / sizeof(kLargeShapes[0]));
+
+int large_variant_count() { return kLargeVariants; }
+int large_panel_width(int variant) { return kLargeShapes[variant].nb; }
+void large_variant_shape(int variant, int *nb, int *row_tiles, int *chunk) {
+    *nb = kLargeShapes[variant].nb;
+    *row_tiles = kLargeShapes[variant].g;
+    *chunk = 4 * kLargeShapes[variant].u;
+}
+
+template <int V>
+static void launch_chol(const BigBody *items, int32_t n_items, hipStream_t s) {
+    constexpr LargeShape sh = kLargeShapes[V];
+    hipLaunchKernelGGL((chol_large_kernel<sh.nb, sh.g, sh.u>), dim3(n_items), dim3(256), 0, s, items);
+}
 
 hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int max_Mp, int variant, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
+    if (variant < 0 || variant >= kLargeVariants) return hipErrorInvalidValue;
     hipLaunchKernelGGL(assemble_large_kernel, dim3(n_items, asm_tiles(max_Mp)), dim3(256), 0, s, items);
-    const size_t lds = (size_t)max_Mp * 6 * sizeof(double);
-    if (variant == 1) {
-        hipLaunchKernelGGL(chol_large_kernel<32>, dim3(n_items), dim3(256), 0, s, items);
-        hipLaunchKernelGGL(project_large_kernel<32>, dim3(n_items), dim3(256), lds, s, items);
-    } else {
-        hipLaunchKernelGGL(chol_large_kernel<16>, dim3(n_items), dim3(256), 0, s, items);
-        hipLaunchKernelGGL(project_large_kernel<16>, dim3(n_items), dim3(256), lds, s, items);
+    switch (variant) {
+        case 0: launch_chol<0>(items, n_items, s); break;
+        case 1: launch_chol<1>(items, n_items, s); break;
+        case 2: launch_chol<2>(items, n_items, s); break;
+        case 3: launch_chol<3>(items, n_items, s); break;
+        case 4: launch_chol<4>(items, n_items, s); break;
+        default: launch_chol<5>(items, n_items, s); break;
     }
+    static_assert(kLargeVariants == 6, "launch switch covers every shape");
+    const size_t lds = (size_t)max_Mp * 6 * sizeof(double);
+    if (large_panel_width(variant) == 32)
+        hipLaunchKernelGGL(project_large_kernel<32>, dim3(n_items), dim3(256), lds, s, items);
+    else
+        hipLaunchKernelGGL(project_large_kernel<16>, dim3(n_items), dim3(256), lds, s, items);
     return hipGetLastError();
 }
 
 hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
-                                      int max_Mp, int variant, hipStream_t s) {
+                                      int max_Mp, int panel, hipStream_t s) {
     if (n_wg <= 0 || max_rhs <= 0) return hipSuccess;
     const size_t lds = (size_t)max_Mp * 8 * sizeof(double);
     dim3 g((unsigned)n_wg, (max_rhs + 7) / 8);
-    if (variant == 1)
+    if (panel != 16 && panel != 32) return hipErrorInvalidValue;
+    if (panel == 32)
         hipLaunchKernelGGL(apply_large_kernel<32>, g, dim3(256), lds, s, jobs, n_jobs);
     else
         hipLaunchKernelGGL(apply_large_kernel<16>, g, dim3(256), lds, s, jobs, n_jobs);

@@ -79,13 +79,17 @@ struct SaddleJob {
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s);
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s);
-// Large bodies: assembly, MFMA left-looking Cholesky with panel width 16
-// (variant 0) or 32 (variant 1), projection; and the apply (<= 8 rhs per
-// workgroup).
+// Large bodies: assembly, MFMA left-looking Cholesky, projection; and the
+// apply (<= 8 rhs per workgroup).  `variant` selects one of
+// large_variant_count() tile shapes (panel width, row tiles per wave,
+// prefetched columns); the apply takes only the panel width.
+int large_variant_count();
 int large_panel_width(int variant);
+void large_variant_shape(int variant, int *panel, int *row_tiles, int *chunk);
 hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int max_Mp, int variant, hipStream_t s);
+// `panel`: the panel width (16 or 32) the bodies' factors were built with.
 hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
-                                      int max_Mp, int variant, hipStream_t s);
+                                      int max_Mp, int panel, hipStream_t s);
 hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_blocks, int64_t n_bodies,
                          hipStream_t s);
 

@@ -29,7 +29,7 @@ struct rmb_ctx_s {
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[RMB_KERNEL_COUNT] = {0, 0, 0, 0};
     int64_t kernel_launches[RMB_KERNEL_COUNT] = {0, 0, 0, 0};
-    // autotuned panel width variant of the large-body factorisation, by padded size
+    // autotuned tile-shape variant of the large-body factorisation, by padded size
     std::map<int, int> tuned_panel;
     struct TuneRecord {
         int Mp, variant;

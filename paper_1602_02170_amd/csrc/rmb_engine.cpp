@@ -109,8 +109,9 @@ static rmb_status check_body_sizes(rmb_ctx ctx, const int64_t *off, int64_t N) {
     return RMB_OK;
 }
 
-// Panel width of the large-body factorisation for padded size Mp, chosen by
-// timing both variants on the first batch of that size (cached per context).
+// Tile shape of the large-body factorisation for padded size Mp, chosen by
+// timing every candidate shape on the first batch of that size (cached per
+// context; the timings are kept in the context's tune log).
 static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, int max_Mp, hipStream_t s,
                               int *variant_out) {
     auto it = ctx->tuned_panel.find(max_Mp);
@@ -119,12 +120,13 @@ static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, in
         RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, it->second, s));
         return RMB_OK;
     }
+    const int nv = large_variant_count();
     float best_ms = 0.f;
     int best = 0;
     hipEvent_t e0, e1;
     RMB_HIP(ctx, hipEventCreate(&e0));
     RMB_HIP(ctx, hipEventCreate(&e1));
-    for (int v = 0; v < 2; ++v) {
+    for (int v = 0; v < nv; ++v) {
         RMB_HIP(ctx, hipEventRecord(e0, s));
         RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, v, s));
         RMB_HIP(ctx, hipEventRecord(e1, s));
@@ -137,7 +139,7 @@ static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, in
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->tuned_panel[max_Mp] = best;
-    if (best != 1) RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, best, s));
+    if (best != nv - 1) RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, best, s));
     *variant_out = best;
     return RMB_OK;
 }
@@ -459,7 +461,7 @@ struct Engine {
         int64_t wg_comb = 0;
         for (Job *J : finish) o_coef.push_back(st.put(J->y.data(), J->y.size() * 8));
         // precond apply: finish (z -> w) then iter (V_k -> z)
-        std::vector<PrecondApplyJob> app, appL[2];
+        std::vector<PrecondApplyJob> app, appL[2];  // large bodies: [panel width 16, 32]
         int64_t wg_app = 0, wg_appL[2] = {0, 0};
         int app_max_m = 0, appL_max_Mp[2] = {0, 0};
         auto add_app = [&](Job *J, const double *in, double *out) {
@@ -478,7 +480,7 @@ struct Engine {
                 app_max_m = std::max(app_max_m, J->max_m);
             }
             if (J->n_large) {
-                const int v = J->variant;
+                const int v = large_panel_width(J->variant) == 32 ? 1 : 0;  // apply tables by panel width
                 a.items = (const BodyWork *)J->bigs_d;
                 a.wg_begin = wg_appL[v];
                 a.n_items = J->n_large;
@@ -667,7 +669,7 @@ struct Engine {
         for (int v = 0; v < 2; ++v)
             if (!appL[v].empty())
                 RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)D(o_appL[v]), (int32_t)appL[v].size(),
-                                                        wg_appL[v], 1, appL_max_Mp[v], v, s));
+                                                        wg_appL[v], 1, appL_max_Mp[v], v ? 32 : 16, s));
         if (!axp.empty()) RMB_HIP(ctx, launch_axpy((const KrylovJob *)D(o_axp), (int32_t)axp.size(), wg_axp, s));
         if (!pk.empty()) RMB_HIP(ctx, launch_pack_table((const PackJob *)D(o_pk), (int32_t)pk.size(), wg_pk, s));
         for (int a = 0; a < 2; ++a)
@@ -893,7 +895,7 @@ rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, co
         RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)d, 1, pc->n_small, nrhs, pc->max_m, s));
     if (pc->n_large)
         RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)d + 1, 1, pc->n_large, nrhs, pc->max_Mp,
-                                                pc->variant, s));
+                                                large_panel_width(pc->variant), s));
     return RMB_OK;
 }
 
@@ -901,6 +903,24 @@ rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_w
     if (!ctx || !panel_width) return RMB_EINVAL;
     auto it = ctx->tuned_panel.find(padded_dim);
     *panel_width = it == ctx->tuned_panel.end() ? 0 : large_panel_width(it->second);
+    return RMB_OK;
+}
+
+rmb_status rmb_ctx_tune_log(rmb_ctx ctx, int32_t capacity, rmb_tune_record *records, int32_t *count) {
+    if (!ctx || !count || capacity < 0 || (capacity > 0 && !records))
+        return ctx ? fail(ctx, RMB_EINVAL, "rmb_ctx_tune_log: bad arguments") : RMB_EINVAL;
+    const int32_t total = (int32_t)ctx->tune_log.size();
+    for (int32_t i = 0; i < total && i < capacity; ++i) {
+        const auto &t = ctx->tune_log[i];
+        rmb_tune_record r{};
+        r.padded_dim = t.Mp;
+        large_variant_shape(t.variant, &r.panel, &r.row_tiles, &r.chunk);
+        r.ms = t.ms;
+        auto it = ctx->tuned_panel.find(t.Mp);
+        r.chosen = it != ctx->tuned_panel.end() && it->second == t.variant;
+        records[i] = r;
+    }
+    *count = total;
     return RMB_OK;
 }
 
