@@ -130,69 +130,73 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
     __shared__ int bad;
     const BigBody it = items[blockIdx.x];
     const int Mp = it.Mp;
-    double *L = it.w.factor;
-    double *Dinv = big_Dinv(it);
+    const gmem<double> L = as_global(it.w.factor);
+    const gmem<double> Dinv = as_global(big_Dinv(it));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int l16 = lane & 15, l4 = lane >> 4;
     if (tid == 0) bad = 0;
 
     for (int j = 0; j < Mp; j += NB) {
-        // 1. panel update: rows [j, Mp), columns [j, j+NB)
+        // 1. panel update: rows [j, Mp), columns [j, j+NB).  A wave's row
+        //    tiles past the panel are clamped to its last tile, so every load
+        //    is unconditional (no branch between a prefetch and its use);
+        //    only their stores are skipped.
         const int RT = (Mp - j) / 16;  // row tiles in the panel
         for (int pass = 0; pass * 4 * G < RT; ++pass) {
             dbl4 acc[G][CT];
             int row0[G];
+            bool live[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 const int t = pass * 4 * G + g * 4 + wave;
-                row0[g] = t < RT ? j + 16 * t : -1;
+                live[g] = t < RT;
+                row0[g] = j + 16 * (t < RT ? t : RT - 1);
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        acc[g][c][r] = row0[g] >= 0 ? L[(int64_t)(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] : 0.0;
+                        acc[g][c][r] = L[(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r];
                 }
             }
             if (j > 0) {
-                // j is a multiple of 16: whole chunks of 4 * U columns
+                // j is a multiple of 16 (and of 4 * U): nch whole chunks
+                const int nch = j / (4 * U);
                 double a0[U][G], b0[U][CT], a1[U][G], b1[U][CT];
-                auto load = [&](int k0, double (&a)[U][G], double (&b)[U][CT]) {
+                auto load = [&](int ch, double (&a)[U][G], double (&b)[U][CT]) {
 #pragma unroll
                     for (int u = 0; u < U; ++u) {
-                        const int kc = (k0 + 4 * u + l4) * Mp;  // Mp^2 < 2^31
+                        const int kc = (4 * U * ch + 4 * u + l4) * Mp;  // Mp^2 < 2^31
 #pragma unroll
                         for (int c = 0; c < CT; ++c) b[u][c] = L[kc + j + 16 * c + l16];
 #pragma unroll
-                        for (int g = 0; g < G; ++g) a[u][g] = row0[g] >= 0 ? -L[kc + row0[g] + l16] : 0.0;
+                        for (int g = 0; g < G; ++g) a[u][g] = -L[kc + row0[g] + l16];
                     }
                 };
                 auto mma = [&](const double (&a)[U][G], const double (&b)[U][CT]) {
 #pragma unroll
                     for (int u = 0; u < U; ++u)
 #pragma unroll
-                        for (int g = 0; g < G; ++g) {
-                            if (row0[g] < 0) continue;  // wave-uniform
+                        for (int g = 0; g < G; ++g)
 #pragma unroll
                             for (int c = 0; c < CT; ++c) acc[g][c] = mfma16x16x4(a[u][g], b[u][c], acc[g][c]);
-                        }
                 };
                 load(0, a0, b0);
-                for (int k0 = 0; k0 < j; k0 += 8 * U) {
-                    if (k0 + 4 * U < j) load(k0 + 4 * U, a1, b1);
+                for (int ch = 0; ch < nch; ch += 2) {
+                    load(min(ch + 1, nch - 1), a1, b1);
                     mma(a0, b0);
-                    if (k0 + 4 * U >= j) break;
-                    if (k0 + 8 * U < j) load(k0 + 8 * U, a0, b0);
+                    if (ch + 1 >= nch) break;
+                    load(min(ch + 2, nch - 1), a0, b0);
                     mma(a1, b1);
                 }
             }
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                if (row0[g] < 0) continue;
+                if (!live[g]) continue;
 #pragma unroll
                 for (int c = 0; c < CT; ++c)
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
-                        L[(int64_t)(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] = acc[g][c][r];
+                        L[(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] = acc[g][c][r];
             }
         }
         __syncthreads();

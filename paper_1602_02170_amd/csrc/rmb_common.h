@@ -12,6 +12,18 @@
 
 namespace rmb {
 
+// Device pointers read from job tables are generic to the compiler, so their
+// loads become flat loads, which count against both the vector-memory and the
+// LDS counters and force full waits.  A global-address-space view gives
+// global loads that the compiler can wait on one at a time.
+template <typename T>
+using gmem = __attribute__((address_space(1))) T *;
+template <typename T>
+__device__ __forceinline__ gmem<T> as_global(T *p) {
+    return (gmem<T>)p;
+}
+
+
 // ---------------------------------------------------------------------------
 // pair-product work description
 // ---------------------------------------------------------------------------
