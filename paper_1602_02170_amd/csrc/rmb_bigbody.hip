@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__re
     __shared__ double tile[E][E + 1];  // [column][row]
     const BigBody it = items[blockIdx.x];
     const int n = it.w.n_blobs, m = 3 * n, Mp = it.Mp;
-    double *A = it.w.factor;
+    gmem<double> A = as_global(it.w.factor);
     const int T = (n + kAsmBlobs - 1) / kAsmBlobs;
     const int ntile = T * (T + 1) / 2;
     const int y = blockIdx.y, tid = threadIdx.x;
@@ -81,8 +81,8 @@ __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__re
         const int il = tid % kAsmBlobs, jl = tid / kAsmBlobs;
         const int i = I * kAsmBlobs + il, j = J * kAsmBlobs + jl;
         if (i < n && j < n) {
-            const double *ri = it.w.pos + 3 * (it.w.blob0 + i);
-            const double *rj = it.w.pos + 3 * (it.w.blob0 + j);
+            const gmem<const double> ri = as_global(it.w.pos + 3 * (it.w.blob0 + i));
+            const gmem<const double> rj = as_global(it.w.pos + 3 * (it.w.blob0 + j));
             const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
             double B[9];
             pair_block_f64(a_i, a_j, it.w.a, it.w.wall != 0, B);
@@ -291,7 +291,7 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
 
 // X <- L^-1 X
 template <int NB, int R>
-__device__ void forward_rl(const double *__restrict__ L, const double *__restrict__ Dinv, int Mp, double *X,
+__device__ void forward_rl(const gmem<const double> L, const gmem<const double> Dinv, int Mp, double *X,
                            double *Dj, double *T) {
     const int tid = threadIdx.x;
     for (int j = 0; j < Mp; j += NB) {
@@ -327,7 +327,7 @@ __device__ void forward_rl(const double *__restrict__ L, const double *__restric
 
 // X <- L^-T X
 template <int NB, int R>
-__device__ void backward_rl(const double *__restrict__ L, const double *__restrict__ Dinv, int Mp, double *X,
+__device__ void backward_rl(const gmem<const double> L, const gmem<const double> Dinv, int Mp, double *X,
                             double *Dj, double *T) {
     const int tid = threadIdx.x;
     for (int j = Mp - NB; j >= 0; j -= NB) {
@@ -348,7 +348,7 @@ __device__ void backward_rl(const double *__restrict__ L, const double *__restri
             double acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0.0;
-            const double *col = L + (int64_t)k * Mp + j;
+            const gmem<const double> col = L + (int64_t)k * Mp + j;
 #pragma unroll
             for (int l = 0; l < NB; ++l) {
                 const double lv = col[l];
@@ -372,23 +372,23 @@ __global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__res
     __shared__ int bad;
     const BigBody it = items[blockIdx.x];
     const int Mp = it.Mp, m = 3 * it.w.n_blobs, tid = threadIdx.x;
-    const double *L = it.w.factor;
+    const gmem<const double> L = as_global(it.w.factor);
     double *Y = lds;  // Mp x 6
     if (tid == 0) bad = 0;
-    const double *q = it.w.q;
+    const gmem<const double> q = as_global(it.w.q);
     for (int e = tid; e < 6 * Mp; e += 256) {
         const int row = e / 6, k = e % 6;
         double v = 0.0;
         if (row < m) {
             const int i = row / 3, c = row % 3;
-            const double *ri = it.w.pos + 3 * (it.w.blob0 + i);
+            const gmem<const double> ri = as_global(it.w.pos + 3 * (it.w.blob0 + i));
             const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
             v = K_entry(d, c, k);
         }
         Y[e] = v;
     }
     __syncthreads();
-    forward_rl<NB, 6>(L, big_Dinv(it), Mp, Y, Dj, T);
+    forward_rl<NB, 6>(L, as_global((const double *)big_Dinv(it)), Mp, Y, Dj, T);
     if (tid < 36) {
         const int r = tid / 6, c = tid % 6;
         double acc = 0.0;
@@ -415,9 +415,9 @@ __global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__res
     }
     __syncthreads();
     double *Yg = big_Y(it);
-    for (int e = tid; e < 6 * Mp; e += 256) Yg[e] = Y[e];
+    for (int e = tid; e < 6 * Mp; e += 256) as_global(Yg)[e] = Y[e];
     double *Sc = big_Sc(it);
-    if (tid < 36) Sc[tid] = ((tid % 6) <= (tid / 6)) ? S[tid] : 0.0;
+    if (tid < 36) as_global(Sc)[tid] = ((tid % 6) <= (tid / 6)) ? S[tid] : 0.0;
     if (tid == 0 && bad) atomicOr(it.w.flag, 8);
 }
 
@@ -442,16 +442,16 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     const int r0 = R * blockIdx.y;
     const int nr = min(R, J.nrhs - r0);
     if (nr <= 0) return;
-    const double *L = it.w.factor;
+    const gmem<const double> L = as_global(it.w.factor);
     const double *Y = big_Y(it), *Dinv = big_Dinv(it), *Sc = big_Sc(it);
     double *X = lds;  // Mp x 8
     const int64_t b3 = 3 * it.w.blob0, u6 = J.nb3 + 6 * (int64_t)it.w.body;
     for (int e = tid; e < Mp * R; e += 256) {
         const int row = e / R, c = e % R;
-        X[e] = (row < m && c < nr) ? J.in[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
+        X[e] = (row < m && c < nr) ? as_global(J.in)[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
     }
     __syncthreads();
-    forward_rl<NB, R>(L, Dinv, Mp, X, Dj, T);
+    forward_rl<NB, R>(L, as_global(Dinv), Mp, X, Dj, T);
     // g = F - Y^T t, F = -bottom: thread (c, qp) sums rows l = qp (mod QP)
     // for k = 0..5, then the QP partials are added in order
     double *part = Dj;  // [QP][R][6]
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         for (int l = qp; l < Mp; l += QP) {
             const double x = X[l * R + c];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[k] += Y[l * 6 + k] * x;
+            for (int k = 0; k < 6; ++k) acc[k] += as_global(Y)[l * 6 + k] * x;
         }
 #pragma unroll
         for (int k = 0; k < 6; ++k) part[(qp * R + c) * 6 + k] = acc[k];
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         const int c = tid / 6, k = tid % 6;
         double acc = 0.0;
         for (int qp = 0; qp < QP; ++qp) acc += part[(qp * R + c) * 6 + k];
-        g[c][k] = c < nr ? -J.in[(int64_t)(r0 + c) * J.ld + u6 + k] - acc : 0.0;
+        g[c][k] = c < nr ? -as_global(J.in)[(int64_t)(r0 + c) * J.ld + u6 + k] - acc : 0.0;
     }
     __syncthreads();
     if (tid < nr) {
@@ -480,20 +480,20 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         double *gg = g[tid];
         for (int i = 0; i < 6; ++i) {
             double v = gg[i];
-            for (int k = 0; k < i; ++k) v -= Sc[i * 6 + k] * u[k];
-            u[i] = v / Sc[i * 6 + i];
+            for (int k = 0; k < i; ++k) v -= as_global(Sc)[i * 6 + k] * u[k];
+            u[i] = v / as_global(Sc)[i * 6 + i];
         }
         for (int i = 5; i >= 0; --i) {
             double v = u[i];
-            for (int k = i + 1; k < 6; ++k) v -= Sc[k * 6 + i] * gg[k];
-            gg[i] = v / Sc[i * 6 + i];
+            for (int k = i + 1; k < 6; ++k) v -= as_global(Sc)[k * 6 + i] * gg[k];
+            gg[i] = v / as_global(Sc)[i * 6 + i];
         }
     }
     __syncthreads();
     for (int row = tid; row < Mp; row += 256) {
         double yk[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) yk[k] = Y[row * 6 + k];
+        for (int k = 0; k < 6; ++k) yk[k] = as_global(Y)[row * 6 + k];
 #pragma unroll
         for (int c = 0; c < R; ++c) {
             double acc = X[row * R + c];
@@ -503,14 +503,14 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         }
     }
     __syncthreads();
-    backward_rl<NB, R>(L, Dinv, Mp, X, Dj, T);
+    backward_rl<NB, R>(L, as_global(Dinv), Mp, X, Dj, T);
     for (int e = tid; e < m * R; e += 256) {
         const int row = e / R, c = e % R;
-        if (c < nr) J.out[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];
+        if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];
     }
     if (tid < R * 6) {
         const int c = tid / 6, k = tid % 6;
-        if (c < nr) J.out[(int64_t)(r0 + c) * J.ld + u6 + k] = g[c][k];
+        if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + u6 + k] = g[c][k];
     }
 }
 

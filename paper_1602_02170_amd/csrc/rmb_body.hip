@@ -36,8 +36,8 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     // 1. assemble M_pp (with prefactor)
     for (int pq = tid; pq < n * n; pq += blockDim.x) {
         const int i = pq / n, j = pq % n;
-        const double *ri = it.pos + 3 * (int64_t)(it.blob0 + i);
-        const double *rj = it.pos + 3 * (int64_t)(it.blob0 + j);
+        const gmem<const double> ri = as_global(it.pos + 3 * (int64_t)(it.blob0 + i));
+        const gmem<const double> rj = as_global(it.pos + 3 * (int64_t)(it.blob0 + j));
         double B[9];
         const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
         pair_block_f64(a_i, a_j, it.a, it.wall != 0, B);
@@ -68,7 +68,7 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     // 3. Li = L^-1: L goes to the factor storage, then lane c forms column c
     //    of Li in LDS (A is overwritten; each column belongs to one lane, so
     //    no barrier is needed inside the loop).
-    double *out = it.factor;
+    gmem<double> out = as_global(it.factor);
     for (int e = tid; e < m * m; e += blockDim.x) out[e] = A[e];  // row-major L (lower part)
     __syncthreads();
     for (int c = tid; c < m; c += blockDim.x) {
@@ -82,13 +82,13 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     }
     __syncthreads();
     // 4. Y = Li K_p, S = Y^T Y
-    const double *q = it.q;
+    const gmem<const double> q = as_global(it.q);
     for (int e = tid; e < 6 * m; e += blockDim.x) {
         const int row = e / 6, k = e % 6;
         double acc = 0.0;
         for (int c = 0; c <= row; ++c) {
             const int i = c / 3, cc = c % 3;
-            const double *ri = it.pos + 3 * (int64_t)(it.blob0 + i);
+            const gmem<const double> ri = as_global(it.pos + 3 * (int64_t)(it.blob0 + i));
             const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
             acc += A[c * m + row] * K_entry(d, cc, k);
         }
@@ -154,9 +154,9 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // then 2m doubles).
 constexpr int kApplyThreads = 64;
 
-__device__ void precond_body_apply(const BodyWork &it, const double *__restrict__ s_in,
-                                   const double *__restrict__ bot_in, double *__restrict__ lam_out,
-                                   double *__restrict__ U_out, double *lds, double *g) {
+__device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gmem<const double> s_in,
+                                                   const gmem<const double> bot_in, const gmem<double> lam_out,
+                                                   const gmem<double> U_out, double *lds, double *g) {
     const int m = 3 * it.n_blobs, tid = threadIdx.x;
     // the whole factor [Li | Y | S^-1] is staged in LDS, eight loads in
     // flight per thread, followed by the right-hand side
@@ -168,7 +168,7 @@ __device__ void precond_body_apply(const BodyWork &it, const double *__restrict_
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int e = e0 + i * kApplyThreads;
-            v[i] = e < nf ? it.factor[e] : 0.0;
+            v[i] = e < nf ? as_global(it.factor)[e] : 0.0;
         }
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
@@ -228,8 +228,8 @@ __global__ __launch_bounds__(kApplyThreads) void precond_apply_small_kernel(cons
     const int64_t rhs = blockIdx.y;
     if (rhs >= J.nrhs) return;
     const BodyWork it = J.items[w - J.wg_begin];
-    const double *in = J.in + rhs * J.ld;
-    double *out = J.out + rhs * J.ld;
+    const gmem<const double> in = as_global(J.in + rhs * J.ld);
+    gmem<double> out = as_global(J.out + rhs * J.ld);
     const int64_t b3 = 3 * it.blob0;
     const int64_t u6 = J.nb3 + 6 * (int64_t)it.body;
     precond_body_apply(it, in + b3, in + u6, out + b3, out + u6, lds, g);
@@ -255,20 +255,20 @@ __global__ void saddle_blob_kernel(const SaddleJob *__restrict__ jobs, int32_t n
     double v[3] = {0.0, 0.0, 0.0};
     const int64_t n3 = 3 * J.nb;
     for (int32_t s = 0; s < J.n_split; ++s) {
-        const double *p = J.partial + s * n3 + 3 * i;
+        const gmem<const double> p = as_global(J.partial + s * n3 + 3 * i);
         v[0] += p[0];
         v[1] += p[1];
         v[2] += p[2];
     }
-    const int p = J.blob_body[i];
-    const double *U = J.x + n3 + 6 * (int64_t)p;
-    const double *q = J.q + 3 * (int64_t)p;
-    const double d[3] = {J.pos[3 * i] - q[0], J.pos[3 * i + 1] - q[1], J.pos[3 * i + 2] - q[2]};
+    const int p = as_global(J.blob_body)[i];
+    const gmem<const double> U = as_global(J.x + n3 + 6 * (int64_t)p);
+    const gmem<const double> q = as_global(J.q + 3 * (int64_t)p);
+    const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1], as_global(J.pos)[3 * i + 2] - q[2]};
     const double ku[3] = {U[0] + U[4] * d[2] - U[5] * d[1], U[1] + U[5] * d[0] - U[3] * d[2],
                           U[2] + U[3] * d[1] - U[4] * d[0]};
     for (int c = 0; c < 3; ++c) {
         const double y = J.pref * v[c] - ku[c];
-        J.y[3 * i + c] = J.b ? J.b[3 * i + c] - y : y;
+        as_global(J.y)[3 * i + c] = J.b ? as_global(J.b)[3 * i + c] - y : y;
     }
 }
 
@@ -283,12 +283,12 @@ __global__ void saddle_body_kernel(const SaddleJob *__restrict__ jobs, int32_t n
     }
     const SaddleJob &J = jobs[lo];
     const int64_t p = w - J.body_begin;
-    const int64_t b0 = J.body_off[p], b1 = J.body_off[p + 1];
-    const double *q = J.q + 3 * p;
+    const int64_t b0 = as_global(J.body_off)[p], b1 = as_global(J.body_off)[p + 1];
+    const gmem<const double> q = as_global(J.q + 3 * p);
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t i = b0 + threadIdx.x; i < b1; i += 64) {
-        const double l[3] = {J.x[3 * i], J.x[3 * i + 1], J.x[3 * i + 2]};
-        const double d[3] = {J.pos[3 * i] - q[0], J.pos[3 * i + 1] - q[1], J.pos[3 * i + 2] - q[2]};
+        const double l[3] = {as_global(J.x)[3 * i], as_global(J.x)[3 * i + 1], as_global(J.x)[3 * i + 2]};
+        const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1], as_global(J.pos)[3 * i + 2] - q[2]};
         acc[0] += l[0];
         acc[1] += l[1];
         acc[2] += l[2];
@@ -303,7 +303,7 @@ __global__ void saddle_body_kernel(const SaddleJob *__restrict__ jobs, int32_t n
     }
     if (threadIdx.x == 0) {
         const int64_t o = 3 * J.nb + 6 * p;
-        for (int k = 0; k < 6; ++k) J.y[o + k] = J.b ? J.b[o + k] + acc[k] : -acc[k];
+        for (int k = 0; k < 6; ++k) as_global(J.y)[o + k] = J.b ? as_global(J.b)[o + k] + acc[k] : -acc[k];
     }
 }
 

@@ -76,7 +76,7 @@ __device__ __forceinline__ double block_sum(const double *red, int k) {
 // out[k] = sum_{s < n_seg} P[k*n_seg + s] for k < kk, in a fixed order:
 // Q threads per k take strided partial sums (s = q, q+Q, ..., eight loads in
 // flight), then a fixed tree over q.  Ends with a sync.
-__device__ void reduce_partials(const double *__restrict__ P, int kk, int n_seg, double *out, double *red) {
+__device__ __forceinline__ void reduce_partials(const double *__restrict__ P, int kk, int n_seg, double *out, double *red) {
     int Q = kThreads;
     while (Q > 1 && Q * kk > kThreads) Q >>= 1;
     const int t = threadIdx.x;
@@ -84,7 +84,7 @@ __device__ void reduce_partials(const double *__restrict__ P, int kk, int n_seg,
         const int k = k0 + t / Q, q = t % Q;
         double acc = 0.0;
         if (k < kk) {
-            const double *Pk = P + (int64_t)k * n_seg;
+            const gmem<const double> Pk = as_global(P + (int64_t)k * n_seg);
             int sg = q;
             for (; sg + 7 * Q < n_seg; sg += 8 * Q) {
                 double v[8];
@@ -109,7 +109,7 @@ __device__ void reduce_partials(const double *__restrict__ P, int kk, int n_seg,
 // Partial dot products <V_k, w> over [r.b0, r.b1) for k < kk into red (see
 // stash_wave_sum), eight basis vectors at a time so that their loads are in
 // flight together and their wave reductions interleave.
-__device__ void block_dots(const KrylovJob &J, Range r, int kk, double *red) {
+__device__ __forceinline__ void block_dots(const KrylovJob &J, Range r, int kk, double *red) {
     constexpr int C = 8;
     int k = 0;
     for (; k < kk; k += C) {
@@ -122,12 +122,12 @@ __device__ void block_dots(const KrylovJob &J, Range r, int kk, double *red) {
             for (int u = 0; u < kPer; ++u) {
                 const int64_t e = e0 + u * kThreads;
                 if (e >= r.b1) continue;
-                const double we = J.w[e];
+                const double we = as_global(J.w)[e];
                 if (nc == C) {
 #pragma unroll
-                    for (int c = 0; c < C; ++c) acc[c] += J.V[(k + c) * J.ldv + e] * we;
+                    for (int c = 0; c < C; ++c) acc[c] += as_global(J.V)[(k + c) * J.ldv + e] * we;
                 } else {
-                    for (int c = 0; c < nc; ++c) acc[c] += J.V[(k + c) * J.ldv + e] * we;
+                    for (int c = 0; c < nc; ++c) acc[c] += as_global(J.V)[(k + c) * J.ldv + e] * we;
                 }
             }
         }
@@ -143,7 +143,7 @@ __device__ void block_dots(const KrylovJob &J, Range r, int kk, double *red) {
 // w -= sum_k h[k] V_k over [r.b0, r.b1), subtracting in the order k = 0, 1,
 // ...  (eight basis vectors loaded at a time), and returns this thread's part
 // of ||w||^2 after the update.
-__device__ double block_subtract(const KrylovJob &J, Range r, const double *h, int kk) {
+__device__ __forceinline__ double block_subtract(const KrylovJob &J, Range r, const double *h, int kk) {
     constexpr int C = 8;
     double sq = 0.0;
     for (int64_t e0 = r.b0 + threadIdx.x; e0 < r.b1; e0 += kSeg) {
@@ -151,7 +151,7 @@ __device__ double block_subtract(const KrylovJob &J, Range r, const double *h, i
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int64_t e = e0 + u * kThreads;
-            wv[u] = e < r.b1 ? J.w[e] : 0.0;
+            wv[u] = e < r.b1 ? as_global(J.w)[e] : 0.0;
         }
         int k = 0;
         for (; k + C <= kk; k += C) {
@@ -161,7 +161,7 @@ __device__ double block_subtract(const KrylovJob &J, Range r, const double *h, i
 #pragma unroll
                 for (int u = 0; u < kPer; ++u) {
                     const int64_t e = e0 + u * kThreads;
-                    v[c][u] = e < r.b1 ? J.V[(k + c) * J.ldv + e] : 0.0;
+                    v[c][u] = e < r.b1 ? as_global(J.V)[(k + c) * J.ldv + e] : 0.0;
                 }
 #pragma unroll
             for (int c = 0; c < C; ++c)
@@ -172,14 +172,14 @@ __device__ double block_subtract(const KrylovJob &J, Range r, const double *h, i
 #pragma unroll
             for (int u = 0; u < kPer; ++u) {
                 const int64_t e = e0 + u * kThreads;
-                if (e < r.b1) wv[u] -= h[k] * J.V[k * J.ldv + e];
+                if (e < r.b1) wv[u] -= h[k] * as_global(J.V)[k * J.ldv + e];
             }
         }
 #pragma unroll
         for (int u = 0; u < kPer; ++u) {
             const int64_t e = e0 + u * kThreads;
             if (e < r.b1) {
-                if (kk > 0) J.w[e] = wv[u];
+                if (kk > 0) as_global(J.w)[e] = wv[u];
                 sq += wv[u] * wv[u];
             }
         }
@@ -197,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void orth_dots_kernel(const KrylovJob *__
     if (kk == 0) return;
     block_dots(J, seg_range(J, sg), kk, red);
     __syncthreads();
-    for (int k = threadIdx.x; k < kk; k += kThreads) J.P1[(int64_t)k * J.n_seg + sg] = block_sum(red, k);
+    for (int k = threadIdx.x; k < kk; k += kThreads) as_global(J.P1)[(int64_t)k * J.n_seg + sg] = block_sum(red, k);
 }
 
 // pass 2: h1 = sum of P1; w -= V h1; partials P2 of <V_k, w>.  Workgroup 0
@@ -213,12 +213,12 @@ __global__ __launch_bounds__(kThreads) void orth_update_dots_kernel(const Krylov
     if (kk == 0) return;
     reduce_partials(J.P1, kk, J.n_seg, h, red);
     if (sg == 0)
-        for (int k = threadIdx.x; k < kk; k += kThreads) J.hred[k] = h[k];
+        for (int k = threadIdx.x; k < kk; k += kThreads) as_global(J.hred)[k] = h[k];
     const Range r = seg_range(J, sg);
     (void)block_subtract(J, r, h, kk);
     block_dots(J, r, kk, red);
     __syncthreads();
-    for (int k = threadIdx.x; k < kk; k += kThreads) J.P2[(int64_t)k * J.n_seg + sg] = block_sum(red, k);
+    for (int k = threadIdx.x; k < kk; k += kThreads) as_global(J.P2)[(int64_t)k * J.n_seg + sg] = block_sum(red, k);
 }
 
 // pass 3: h2 = sum of P2; w -= V h2; partials P3 of ||w||^2.  Workgroup 0
@@ -234,12 +234,12 @@ __global__ __launch_bounds__(kThreads) void orth_update_norm_kernel(const Krylov
     if (kk > 0) {
         reduce_partials(J.P2, kk, J.n_seg, h, red);
         if (sg == 0)
-            for (int k = threadIdx.x; k < kk; k += kThreads) J.hcol[k] = J.hred[k] + h[k];
+            for (int k = threadIdx.x; k < kk; k += kThreads) as_global(J.hcol)[k] = as_global(J.hred)[k] + h[k];
     }
     const double sq = block_subtract(J, seg_range(J, sg), h, kk);
     stash_wave_sum(sq, 0, red);
     __syncthreads();
-    if (threadIdx.x == 0) J.P3[sg] = block_sum(red, 0);
+    if (threadIdx.x == 0) as_global(J.P3)[sg] = block_sum(red, 0);
 }
 
 // pass 4: beta = sqrt(sum of P3); vnext = w / beta.  Workgroup 0 writes
@@ -253,10 +253,10 @@ __global__ __launch_bounds__(kThreads) void orth_normalise_kernel(const KrylovJo
     const int sg = (int)(wgi - J.wg_begin);
     reduce_partials(J.P3, 1, J.n_seg, nrm, red);
     const double beta = sqrt(nrm[0]);
-    if (sg == 0 && threadIdx.x == 0) J.hcol[J.kk] = beta;
+    if (sg == 0 && threadIdx.x == 0) as_global(J.hcol)[J.kk] = beta;
     const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
     const Range r = seg_range(J, sg);
-    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) J.vnext[e] = J.w[e] * inv;
+    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) as_global(J.vnext)[e] = as_global(J.w)[e] * inv;
 }
 
 hipError_t launch_orthogonalise(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {
@@ -276,8 +276,8 @@ __global__ __launch_bounds__(kThreads) void combine_kernel(const KrylovJob *__re
     const Range r = seg_range(J, (int)(wgi - J.wg_begin));
     for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) {
         double acc = 0.0;
-        for (int k = 0; k < J.kk; ++k) acc += J.coef[k] * J.V[k * J.ldv + e];
-        J.w[e] = acc;
+        for (int k = 0; k < J.kk; ++k) acc += as_global(J.coef)[k] * as_global(J.V)[k * J.ldv + e];
+        as_global(J.w)[e] = acc;
     }
 }
 
@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void axpy_kernel(const KrylovJob *__restr
     const int64_t wgi = blockIdx.x;
     const KrylovJob &J = jobs[find_wg_job(jobs, n_jobs, wgi)];
     const Range r = seg_range(J, (int)(wgi - J.wg_begin));
-    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) J.x[e] += J.t[e];
+    for (int64_t e = r.b0 + threadIdx.x; e < r.b1; e += kThreads) as_global(J.x)[e] += as_global(J.t)[e];
 }
 
 hipError_t launch_axpy(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {

@@ -112,17 +112,16 @@ __global__ void pack_table_kernel(const PackJob *__restrict__ jobs, int32_t n_jo
     const PackJob &J = jobs[lo];
     const int64_t j = (w - J.wg_begin) * 256 + threadIdx.x;
     if (j >= J.nb) return;
-    const double x = J.pos[3 * j], y = J.pos[3 * j + 1], z = J.pos[3 * j + 2];
-    const double fx = J.lam[3 * j], fy = J.lam[3 * j + 1], fz = J.lam[3 * j + 2];
+    const gmem<const double> pos = as_global(J.pos), lam = as_global(J.lam);
+    const double x = pos[3 * j], y = pos[3 * j + 1], z = pos[3 * j + 2];
+    const double fx = lam[3 * j], fy = lam[3 * j + 1], fz = lam[3 * j + 2];
     if (J.precision == RMB_PREC_FP32_PAIRS) {
-        SrcF32 r;
-        r.x = x, r.y = y, r.z = z;
-        r.fx = (float)fx, r.fy = (float)fy, r.fz = (float)fz, r.zf = (float)z;
-        ((SrcF32 *)J.src)[j] = r;
+        const gmem<SrcF32> r = as_global((SrcF32 *)J.src) + j;
+        r->x = x, r->y = y, r->z = z;
+        r->fx = (float)fx, r->fy = (float)fy, r->fz = (float)fz, r->zf = (float)z;
     } else {
-        SrcF64 r;
-        r.x = x, r.y = y, r.z = z, r.fx = fx, r.fy = fy, r.fz = fz;
-        ((SrcF64 *)J.src)[j] = r;
+        const gmem<SrcF64> r = as_global((SrcF64 *)J.src) + j;
+        r->x = x, r->y = y, r->z = z, r->fx = fx, r->fy = fy, r->fz = fz;
     }
 }
 
@@ -180,7 +179,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_f32_kernel(const PairJob *__r
     const int64_t i = t0 + threadIdx.x;
     const bool active = i < J.nb;
     const int64_t ii = active ? i : t0;  // idle lanes shadow a valid target
-    const double xi = J.tpos[3 * ii + 0], yi = J.tpos[3 * ii + 1], zi = J.tpos[3 * ii + 2];
+    const double xi = as_global(J.tpos)[3 * ii + 0], yi = as_global(J.tpos)[3 * ii + 1], zi = as_global(J.tpos)[3 * ii + 2];
 
     const float a = J.a_f, four_a2 = J.four_a2_f, kiso = J.k_near_iso_f, krr = J.k_near_rr_f;
     double vx = 0.0, vy = 0.0, vz = 0.0;
@@ -253,7 +252,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_f32_kernel(const PairJob *__r
         vz += (double)az;
     }
     if (active) {
-        double *out = J.partial + ((int64_t)split * J.nb + i) * 3;
+        const gmem<double> out = as_global(J.partial + ((int64_t)split * J.nb + i) * 3);
         out[0] = vx;
         out[1] = vy;
         out[2] = vz;
@@ -276,7 +275,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_f64_kernel(const PairJob *__r
     const int64_t i = t0 + threadIdx.x;
     const bool active = i < J.nb;
     const int64_t ii = active ? i : t0;
-    const double xi = J.tpos[3 * ii + 0], yi = J.tpos[3 * ii + 1], zi = J.tpos[3 * ii + 2];
+    const double xi = as_global(J.tpos)[3 * ii + 0], yi = as_global(J.tpos)[3 * ii + 1], zi = as_global(J.tpos)[3 * ii + 2];
 
     const double a = J.a, four_a2 = J.four_a2, kiso = J.k_near_iso, krr = J.k_near_rr;
     double ax = 0.0, ay = 0.0, az = 0.0;
@@ -333,7 +332,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_f64_kernel(const PairJob *__r
         }
     }
     if (active) {
-        double *out = J.partial + ((int64_t)split * J.nb + i) * 3;
+        const gmem<double> out = as_global(J.partial + ((int64_t)split * J.nb + i) * 3);
         out[0] = ax;
         out[1] = ay;
         out[2] = az;

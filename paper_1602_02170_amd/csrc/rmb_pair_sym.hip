@@ -319,8 +319,8 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
     const R a = (R)J.a, four_a2 = (R)J.four_a2, kiso = (R)J.k_near_iso, krr = (R)J.k_near_rr;
     const R tiny = sizeof(R) == 4 ? (R)1e-30f : (R)1e-280;
-    double *vout = J.vpart + t * (int64_t)B * 3;
-    double *uout = J.upart + t * (int64_t)B * 3;
+    const gmem<double> vout = as_global(J.vpart + t * (int64_t)B * 3);
+    const gmem<double> uout = as_global(J.upart + t * (int64_t)B * 3);
 
     double u64[G][3];
 #pragma unroll
@@ -331,10 +331,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         if ((int64_t)I * B + sub * 64 >= nb) break;  // wave-uniform
         const bool active = i < nb;
         const int64_t ii = active ? i : (int64_t)I * B + sub * 64;
-        const double xi = J.tpos[3 * ii], yi = J.tpos[3 * ii + 1], zi = J.tpos[3 * ii + 2];
+        const double xi = as_global(J.tpos)[3 * ii], yi = as_global(J.tpos)[3 * ii + 1], zi = as_global(J.tpos)[3 * ii + 2];
         // the target's own force enters the transposed contraction
-        const R fix = active ? (R)J.lam[3 * ii] : (R)0, fiy = active ? (R)J.lam[3 * ii + 1] : (R)0,
-                fiz = active ? (R)J.lam[3 * ii + 2] : (R)0;
+        const R fix = active ? (R)as_global(J.lam)[3 * ii] : (R)0, fiy = active ? (R)as_global(J.lam)[3 * ii + 1] : (R)0,
+                fiz = active ? (R)as_global(J.lam)[3 * ii + 2] : (R)0;
         double vx = 0.0, vy = 0.0, vz = 0.0;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
@@ -355,7 +355,7 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 // zero force)
                 const int64_t jl = jb + lane;
                 const bool jvalid = jl < s1;
-                const SRC *rec = (const SRC *)J.src + (jvalid ? jl : jb);
+                const gmem<const SRC> rec = as_global((const SRC *)J.src + (jvalid ? jl : jb));
                 const double px = rec->x, py = rec->y, pz = rec->z;
                 const R gx = jvalid ? (R)rec->fx : (R)0, gy = jvalid ? (R)rec->fy : (R)0,
                         gz = jvalid ? (R)rec->fz : (R)0;
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
             vz += (double)az;
         }
         if (active) {
-            double *o = vout + (sub * 64 + lane) * 3;
+            const gmem<double> o = vout + (sub * 64 + lane) * 3;
             o[0] = vx;
             o[1] = vy;
             o[2] = vz;
@@ -395,7 +395,7 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         for (int g = 0; g < G; ++g) {
             const int64_t j = s0 + 64 * g + lane;
             if (j < s1) {
-                double *o = uout + (64 * g + lane) * 3;
+                const gmem<double> o = uout + (64 * g + lane) * 3;
                 o[0] = u64[g][0];
                 o[1] = u64[g][1];
                 o[2] = u64[g][2];
@@ -429,8 +429,8 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
         auto tile = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i); };
         const int32_t nv = T - K;  // vpart contributions, then K upart ones
         for (int32_t c = q; c < T; c += kRedParts) {
-            const double *p = c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
-                                     : J.upart + (tile(c - nv, K) * B + kk) * 3;
+            const gmem<const double> p = as_global(c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
+                                                          : J.upart + (tile(c - nv, K) * B + kk) * 3);
             s[0] += p[0], s[1] += p[1], s[2] += p[2];
         }
     }
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
     if (q == 0 && k < J.nb) {
         double t[3] = {0.0, 0.0, 0.0};
         for (int r = 0; r < kRedParts; ++r) t[0] += part[r][b][0], t[1] += part[r][b][1], t[2] += part[r][b][2];
-        double *o = J.vel + 3 * k;
+        const gmem<double> o = as_global(J.vel + 3 * k);
         o[0] = J.pref * t[0];
         o[1] = J.pref * t[1];
         o[2] = J.pref * t[2];
