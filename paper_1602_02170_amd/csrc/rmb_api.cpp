@@ -111,8 +111,10 @@ static hipEvent_t take_event(rmb_ctx ctx) {
         ctx->event_pool.pop_back();
         return e;
     }
+    // timestamps only: no system-scope fence when the marker completes (the
+    // fence costs microseconds of idle time around every timed launch)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
 }
 

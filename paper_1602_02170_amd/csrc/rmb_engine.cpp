@@ -45,6 +45,18 @@ static double now_s() {
 
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
+// Waits for the stream by polling for up to 2 ms, then blocking: one GMRES
+// step takes well under that, and polling avoids the blocking wait's
+// wake-up latency on every step.
+static hipError_t wait_stream(hipStream_t s) {
+    const double t0 = now_s();
+    for (;;) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipErrorNotReady) return e;
+        if (now_s() - t0 > 2e-3) return hipStreamSynchronize(s);
+    }
+}
+
 // Host-side description of a system's bodies, split into bodies handled in
 // LDS and large bodies (padded, MFMA path), with their factor offsets.
 struct BodyLists {
@@ -693,7 +705,7 @@ struct Engine {
         if (!orth.empty())
             RMB_HIP(ctx, launch_orthogonalise((const KrylovJob *)D(o_orth), (int32_t)orth.size(), wg_orth, s));
         RMB_HIP(ctx, hipMemcpyAsync(mbox_h, mbox_d, (size_t)max_slot * kSlot * 8, hipMemcpyDeviceToHost, s));
-        RMB_HIP(ctx, hipStreamSynchronize(s));
+        RMB_HIP(ctx, wait_stream(s));
         if (ctx->timing) resolve_timing(ctx, false);
 
         // --- host updates -------------------------------------------------
