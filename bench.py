@@ -151,6 +151,49 @@ def matvec_leg(rmb, torch, ctx, S, reps=20):
     return res
 
 
+def flow_leg(rmb, torch, ctx, S, reps=5):
+    """Flow field of the 16384 x 12-blob monolayer (appendix on computing
+    flow fields): every blob split into 12 tracer blobs (radius a/10) on a
+    sphere of radius 0.4 a, i.e. 2,359,296 sources, evaluated on a 128 x 128
+    plane of points at z = 2.5.  One-sided pair kernel; median of `reps`
+    calls, each timed with its own events, plus the pair kernel's own
+    event-timed share."""
+    sus, lam = S.icosahedra_monolayer()
+    u = S.icosahedron()
+    offs = 0.4 * u / np.linalg.norm(u, axis=1, keepdims=True)
+    lo, hi = sus.pos[:, :2].min(0), sus.pos[:, :2].max(0)
+    gx, gy = np.meshgrid(np.linspace(lo[0], hi[0], 128), np.linspace(lo[1], hi[1], 128))
+    T = np.stack([gx.ravel(), gy.ravel(), np.full(gx.size, 2.5)], 1)
+    sysd = rmb.System.from_suspension(sus)
+    lt = torch.tensor(lam, dtype=torch.float64, device="cuda")
+    tt = torch.tensor(T, dtype=torch.float64, device="cuda")
+    out = torch.empty_like(tt)
+    ns, nt = sus.n_blobs * len(offs), len(T)
+    res = {"workload": f"flow field, {sus.n_blobs} wall blobs x {len(offs)} tracer blobs = {ns} sources, "
+                       f"{nt} targets", "pairs": ns * nt}
+    for prec in ("fp32", "fp64"):
+        k = "pair_f32_wall" if prec == "fp32" else "pair_f64_wall"
+        rmb.flow_field(ctx, sysd, lt, offs, 0.1 * sus.a, tt, prec, out)
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record()
+            rmb.flow_field(ctx, sysd, lt, offs, 0.1 * sus.a, tt, prec, out)
+            e1.record()
+        torch.cuda.synchronize()
+        kms, kn = ctx.kernel_time(k)
+        ctx.set_timing(False)
+        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        kavg = kms / max(kn, 1)
+        tf = FLOPS_PER_PAIR[k] * ns * nt / (kavg * 1e-3) / 1e12
+        res[prec] = {"ms": round(ms, 3), "pairs_per_s": ns * nt / (ms * 1e-3), "kernel_ms": round(kavg, 3),
+                     "kernel_tflops": round(tf, 2), "kernel_frac": round(tf / PEAK_TFLOPS[prec], 4)}
+        log(f"  flow field {prec}: {ms:.2f} ms per call, pair kernel {kavg:.2f} ms, {tf:.1f} TFLOP/s "
+            f"({tf / PEAK_TFLOPS[prec]:.1%} of peak)")
+    return res
+
+
 def factor_leg(rmb, torch, ctx, S, reps=3):
     """Batched per-body factorisation: 512 x 162-blob shells above the wall
     (486 x 486 blocks, padded to 512), all blocks in one launch, then the
@@ -309,6 +352,7 @@ def main():
     ap.add_argument("--no-matvec", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-factor", action="store_true")
+    ap.add_argument("--no-flow", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="timed solves only (for profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -383,6 +427,8 @@ def main():
         log(f"  plain FP64 solve: {ms64:.2f} ms/solve ({infos64[-1]['iterations']} iterations)")
         if not args.no_matvec:
             line["matvec"] = matvec_leg(rmb, torch, ctx, S)
+        if not args.no_flow:
+            line["flow_field"] = flow_leg(rmb, torch, ctx, S)
         if not args.no_factor:
             line["batched_factor"] = factor_leg(rmb, torch, ctx, S)
         if not args.no_serving:

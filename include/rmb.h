@@ -169,6 +169,25 @@ rmb_status rmb_ctx_tune_log(rmb_ctx ctx, int32_t capacity, rmb_tune_record *reco
 rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
                                const double *lambda, double *vel, rmb_stream stream);
 
+/* Flow field at arbitrary points (appendix "Computing flow fields"): every
+ * blob i of `sys` is replaced by n_sub blobs of radius tracer_a placed at
+ * r_i + a * sub_offsets[k], each carrying lambda_i / n_sub, and the velocity
+ * at target point t is
+ *     vel(t) = sum_i sum_k M'(t, r_i + a u_k) lambda_i / n_sub,
+ * M' being the blob-blob mobility (RPY, plus the wall correction in wall
+ * geometry) for blobs of radius tracer_a.  With n_sub = 1, a zero offset
+ * and tracer_a = a it is the mobility product evaluated at the targets.
+ * lambda: device [Nb][3]; sub_offsets: host [n_sub][3], in units of the blob
+ * radius a (the paper leaves the discretisation of each blob's sphere to
+ * the user; a uniform set on the unit sphere matches the RPY construction);
+ * targets, vel: device [n_targets][3], vel must not alias lambda or targets.
+ * Synchronous.  Errors: RMB_EINVAL (bad system or arguments, non-finite
+ * positions, a target or sub-blob at z <= 0 in wall geometry), RMB_ENOMEM,
+ * RMB_EDEVICE. */
+rmb_status rmb_flow_field(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                          int32_t n_sub, const double *sub_offsets, double tracer_a, int64_t n_targets,
+                          const double *targets, double *vel, rmb_stream stream);
+
 
 /* ---------------------------------------------------------------------------
  * Block-diagonal preconditioner (Sec. 2.2.2: eq:M_tilde_block_diag,

@@ -20,6 +20,10 @@ definitions, with library primitives (numpy/scipy dense solves) as steps.
   gmres                      -> right-preconditioned GMRES (Sec. 2.2.2; right
                                 preconditioning so the monitored residual is
                                 the true one, Sec. 3.3)
+  velocity_at, flow_field    -> rectangular product at arbitrary points and
+                                the flow field of the appendix on computing
+                                flow fields (blobs split into tracer-size
+                                blobs carrying equal shares of the force)
 
 Vector layout of a saddle-point vector: [lambda (Nb x 3, blob-major);
 U (N x 6: u then omega)], flattened.
@@ -108,6 +112,28 @@ def matvec_rows(pos, lam, rows, a, eta=1.0, wall=False) -> np.ndarray:
     lib().oracle_matvec_rows(pos.shape[0], _p(pos), _p(lam), 0, len(rows), _p(tgt), a, eta,
                              int(bool(wall)), _p(v))
     return v
+
+
+def velocity_at(src_pos, src_lam, targets, a, eta=1.0, wall=False) -> np.ndarray:
+    """sum_j M(t, r_j) lambda_j at arbitrary target points t (rectangular
+    product; every point is a blob of radius a)."""
+    src_pos, src_lam, targets = _c(src_pos), _c(src_lam), _c(targets)
+    v = np.empty_like(targets)
+    lib().oracle_matvec_rows(src_pos.shape[0], _p(src_pos), _p(src_lam), 0, targets.shape[0], _p(targets), a,
+                             eta, int(bool(wall)), _p(v))
+    return v
+
+
+def flow_field(pos, lam, a, sub_offsets, tracer_a, targets, eta=1.0, wall=False) -> np.ndarray:
+    """Flow field of the appendix on computing flow fields: blob i is
+    replaced by n_sub blobs of radius tracer_a at r_i + a * u_k, each carrying
+    lambda_i / n_sub; the velocity at t is the blob-blob mobility of radius
+    tracer_a summed over all of them."""
+    pos, lam = np.asarray(pos, dtype=np.float64), np.asarray(lam, dtype=np.float64)
+    u = np.asarray(sub_offsets, dtype=np.float64).reshape(-1, 3)
+    sub_pos = (pos[:, None, :] + a * u[None, :, :]).reshape(-1, 3)
+    sub_lam = np.repeat(lam / len(u), len(u), axis=0)
+    return velocity_at(sub_pos, sub_lam, targets, tracer_a, eta, wall)
 
 
 def assemble(pos, a, eta=1.0, wall=False) -> np.ndarray:

@@ -31,7 +31,8 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_mobility_matvec", "rmb_precond_factor", "rmb_precond_apply", "rmb_precond_destroy",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
-           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan"]
+           "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan",
+           "rmb_flow_field"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -86,6 +87,8 @@ def library(path: str = LIB_PATH):
         L.rmb_last_error.restype = ctypes.c_char_p
         L.rmb_version.restype = ctypes.c_char_p
         L.rmb_mobility_matvec.argtypes = [vp, sysp, i32, vp, vp, vp]
+        L.rmb_flow_field.argtypes = [vp, sysp, i32, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
+                                     ctypes.c_int64, vp, vp, vp]
         optp, infop = ctypes.POINTER(rmb_solve_opts), ctypes.POINTER(rmb_solve_info)
         L.rmb_precond_factor.argtypes = [vp, sysp, ctypes.POINTER(vp), vp]
         L.rmb_precond_apply.argtypes = [vp, vp, i32, vp, vp, vp]
@@ -241,6 +244,26 @@ def mobility_matvec(ctx: Context, system: System, lam: torch.Tensor, precision="
     op = _dev(out, "out", (n, 3))
     ctx.check(ctx.lib.rmb_mobility_matvec(ctx.h, ctypes.byref(system.c), _prec(precision), lp, op,
                                           _stream(stream)))
+    return out
+
+
+def flow_field(ctx: Context, system: System, lam: torch.Tensor, sub_offsets, tracer_a: float,
+               targets: torch.Tensor, precision="fp64", out: torch.Tensor = None, stream=None) -> torch.Tensor:
+    """Fluid velocity at `targets` (n, 3) from blob forces `lam` (Nb, 3): each
+    blob replaced by len(sub_offsets) blobs of radius tracer_a at
+    r_i + a * sub_offsets[k] carrying lam_i / n_sub (rmb_flow_field)."""
+    import numpy as np
+    n = system.n_blobs
+    lp = _dev(lam, "lambda", (n, 3))
+    offs = np.ascontiguousarray(np.asarray(sub_offsets, dtype=np.float64).reshape(-1, 3))
+    nt = int(targets.shape[0])
+    tp = _dev(targets, "targets", (nt, 3))
+    if out is None:
+        out = torch.empty((nt, 3), dtype=torch.float64, device=targets.device)
+    op = _dev(out, "out", (nt, 3))
+    ctx.check(ctx.lib.rmb_flow_field(ctx.h, ctypes.byref(system.c), _prec(precision), lp, int(offs.shape[0]),
+                                     offs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), float(tracer_a), nt,
+                                     tp, op, _stream(stream)))
     return out
 
 

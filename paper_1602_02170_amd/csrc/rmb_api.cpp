@@ -324,4 +324,71 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     return RMB_OK;
 }
 
+rmb_status rmb_flow_field(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                          int32_t n_sub, const double *sub_offsets, double tracer_a, int64_t n_targets,
+                          const double *targets, double *vel, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_system(ctx, sys, false));
+    if (precision != RMB_PREC_FP64 && precision != RMB_PREC_FP32_PAIRS)
+        return fail(ctx, RMB_EINVAL, "unknown precision %d", precision);
+    if (!lambda) return fail(ctx, RMB_EINVAL, "lambda is required");
+    if (n_sub < 1 || n_sub > 65536 || !sub_offsets)
+        return fail(ctx, RMB_EINVAL, "n_sub must be in [1, 65536] with sub_offsets given");
+    for (int32_t k = 0; k < 3 * n_sub; ++k)
+        if (!std::isfinite(sub_offsets[k])) return fail(ctx, RMB_EINVAL, "sub_offsets must be finite");
+    if (!(tracer_a > 0.0) || !std::isfinite(tracer_a)) return fail(ctx, RMB_EINVAL, "tracer radius must be > 0");
+    if (n_targets < 0 || n_targets > (int64_t(1) << 31) / 3) return fail(ctx, RMB_EINVAL, "n_targets out of range");
+    if (n_targets == 0) return RMB_OK;
+    if (!targets || !vel) return fail(ctx, RMB_EINVAL, "targets and vel are required");
+    if ((const void *)vel == (const void *)lambda || (const void *)vel == (const void *)targets)
+        return fail(ctx, RMB_EINVAL, "vel must not alias lambda or targets");
+    const int64_t nb = sys->n_blobs, ns = nb * (int64_t)n_sub;
+    if (ns > (int64_t(1) << 31) / 3) return fail(ctx, RMB_EINVAL, "n_blobs * n_sub is above the supported maximum");
+
+    const size_t rec = precision == RMB_PREC_FP32_PAIRS ? sizeof(SrcF32) : sizeof(SrcF64);
+    const bool wall = sys->geometry == RMB_GEOM_WALL;
+    PairJob J;
+    pair_job_init_rect(&J, targets, n_targets, nullptr, ns, nullptr, tracer_a);
+    // scratch layout: [flag | job | offsets | sources | partials]
+    const size_t off_job = 256, off_offs = off_job + 256;
+    const size_t off_src = off_offs + ((size_t)n_sub * 24 + 255) / 256 * 256;
+    const size_t off_part = off_src + ((size_t)ns * rec + 255) / 256 * 256;
+    const size_t total = off_part + (size_t)J.n_split * n_targets * 3 * sizeof(double);
+    char *base = nullptr;
+    RMB_TRY(scratch(ctx, total, (void **)&base));
+    int *flag = (int *)base;
+    // targets: finite, and above the wall in wall geometry
+    rmb_system tsys = *sys;
+    tsys.pos = targets;
+    tsys.n_blobs = n_targets;
+    {
+        const rmb_status st = check_positions(ctx, &tsys, flag, s);
+        if (st != RMB_OK) return fail(ctx, st, "target points: %s", rmb_last_error(ctx));
+    }
+    J.src = base + off_src;
+    J.partial = (double *)(base + off_part);
+    char *h = nullptr;
+    RMB_TRY(pinned(ctx, off_src - off_job, (void **)&h));
+    memcpy(h, &J, sizeof(PairJob));
+    memcpy(h + (off_offs - off_job), sub_offsets, (size_t)n_sub * 24);
+    RMB_HIP(ctx, hipMemcpyAsync(base + off_job, h, off_src - off_job, hipMemcpyHostToDevice, s));
+    RMB_HIP(ctx, hipMemsetAsync(flag, 0, sizeof(int), s));
+    RMB_HIP(ctx, launch_pack_sub_sources(precision, sys->pos, lambda, nb, (const double *)(base + off_offs), n_sub,
+                                         sys->a, wall, base + off_src, flag, s));
+    RMB_TRY(pair_launch(ctx, precision, wall, (const PairJob *)(base + off_job), 1,
+                        (int64_t)J.n_tblock * J.n_split, s));
+    RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, n_targets, mobility_prefactor(tracer_a, sys->eta), vel,
+                                        s));
+    int *hf = nullptr;
+    RMB_TRY(pinned(ctx, sizeof(int), (void **)&hf));
+    RMB_HIP(ctx, hipStreamSynchronize(s));  // the staging above is reused below
+    RMB_HIP(ctx, hipMemcpyAsync(hf, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+    RMB_HIP(ctx, hipStreamSynchronize(s));
+    if (*hf & 1) return fail(ctx, RMB_EINVAL, "non-finite blob position");
+    if (*hf & 2) return fail(ctx, RMB_EINVAL, "a sub-blob lies at or below the wall (z <= 0)");
+    return RMB_OK;
+}
+
 }  // extern "C"

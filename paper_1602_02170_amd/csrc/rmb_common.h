@@ -50,9 +50,10 @@ constexpr int kAccBlock = 64;    // FP32 sums are flushed to FP64 every 64 sourc
 // w / n_tblock.
 struct PairJob {
     const double *tpos;  // [nb][3] target positions
-    const void *src;     // [nb] SrcF32 or SrcF64 records
+    const void *src;     // [ns] SrcF32 or SrcF64 records
     double *partial;     // [n_split][nb][3] per-split sums (no prefactor)
-    int64_t nb;
+    int64_t nb;          // targets
+    int64_t ns;          // sources (= nb for the mobility product)
     int64_t tile_begin;
     int64_t chunk;
     int32_t n_tblock;
@@ -67,9 +68,20 @@ struct PairJob {
 // what else shares the launch.
 void split_plan(int64_t nb, int32_t *n_split, int64_t *chunk, int32_t *n_tblock);
 
-// Fills the plan fields and constants of a PairJob.
+// The same for nt targets and ns sources.
+void split_plan_rect(int64_t nt, int64_t ns, int32_t *n_split, int64_t *chunk, int32_t *n_tblock);
+
+// Fills the plan fields and constants of a PairJob (targets = sources).
 void pair_job_init(PairJob *J, const double *tpos, const void *src, double *partial, int64_t nb,
                    double a);
+// Rectangular product: nt target positions, ns source records, radius a.
+void pair_job_init_rect(PairJob *J, const double *tpos, int64_t nt, const void *src, int64_t ns, double *partial,
+                        double a);
+// Sources for a flow field: record i * n_sub + k is blob i moved by a * off[k]
+// (off: device [n_sub][3]) carrying lambda_i / n_sub; flag |= 1 for a
+// non-finite position, 2 for z <= 0 when `wall`.
+hipError_t launch_pack_sub_sources(int precision, const double *pos, const double *lam, int64_t nb, const double *off,
+                                   int32_t n_sub, double a, int wall, void *src, int *flag, hipStream_t s);
 
 // One system's share of a launch of the pair kernel that evaluates each pair
 // block once (pair_sym_kernel): workgroups [wg_begin, wg_begin + T(T+1)/2)

@@ -26,28 +26,38 @@
 
 namespace rmb {
 
-void split_plan(int64_t nb, int32_t *n_split, int64_t *chunk, int32_t *n_tblock) {
-    int64_t T = (nb + kPairBlock - 1) / kPairBlock;
+void split_plan_rect(int64_t nt, int64_t ns, int32_t *n_split, int64_t *chunk, int32_t *n_tblock) {
+    int64_t T = std::max<int64_t>((nt + kPairBlock - 1) / kPairBlock, 1);
     // enough workgroups to fill 256 CUs several times over, and no source
     // chunk longer than 4096 blobs
-    int64_t want = std::max<int64_t>((nb + 4095) / 4096, (4096 + T - 1) / T);
-    int64_t maxs = (nb + kAccBlock - 1) / kAccBlock;
+    int64_t want = std::max<int64_t>((ns + 4095) / 4096, (4096 + T - 1) / T);
+    int64_t maxs = (ns + kAccBlock - 1) / kAccBlock;
     want = std::min(std::max<int64_t>(want, 1), std::max<int64_t>(maxs, 1));
-    int64_t c = (nb + want - 1) / want;
-    c = (c + kAccBlock - 1) / kAccBlock * kAccBlock;
+    int64_t c = (ns + want - 1) / want;
+    c = std::max<int64_t>((c + kAccBlock - 1) / kAccBlock * kAccBlock, kAccBlock);
     *chunk = c;
-    *n_split = (int32_t)((nb + c - 1) / c);
+    *n_split = (int32_t)std::max<int64_t>((ns + c - 1) / c, 1);
     *n_tblock = (int32_t)T;
+}
+
+void split_plan(int64_t nb, int32_t *n_split, int64_t *chunk, int32_t *n_tblock) {
+    split_plan_rect(nb, nb, n_split, chunk, n_tblock);
 }
 
 void pair_job_init(PairJob *J, const double *tpos, const void *src, double *partial, int64_t nb,
                    double a) {
+    pair_job_init_rect(J, tpos, nb, src, nb, partial, a);
+}
+
+void pair_job_init_rect(PairJob *J, const double *tpos, int64_t nt, const void *src, int64_t ns, double *partial,
+                        double a) {
     J->tpos = tpos;
     J->src = src;
     J->partial = partial;
-    J->nb = nb;
+    J->nb = nt;
+    J->ns = ns;
     J->tile_begin = 0;
-    split_plan(nb, &J->n_split, &J->chunk, &J->n_tblock);
+    split_plan_rect(nt, ns, &J->n_split, &J->chunk, &J->n_tblock);
     J->a = a;
     J->four_a2 = 4.0 * a * a;
     J->k_near_iso = 9.0 / (32.0 * a);
@@ -125,6 +135,41 @@ __global__ void pack_table_kernel(const PackJob *__restrict__ jobs, int32_t n_jo
     }
 }
 
+__global__ void pack_sub_kernel(const double *__restrict__ pos, const double *__restrict__ lam, int64_t nb,
+                                const double *__restrict__ off, int32_t n_sub, double a, int wall, int precision,
+                                void *src, int *flag) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nb * n_sub) return;
+    const int64_t i = s / n_sub;
+    const int k = (int)(s % n_sub);
+    const gmem<const double> P = as_global(pos), F = as_global(lam), O = as_global(off);
+    const double x = P[3 * i] + a * O[3 * k], y = P[3 * i + 1] + a * O[3 * k + 1],
+                 z = P[3 * i + 2] + a * O[3 * k + 2];
+    const double w = 1.0 / n_sub;
+    const double fx = F[3 * i] * w, fy = F[3 * i + 1] * w, fz = F[3 * i + 2] * w;
+    int bad = 0;
+    if (!isfinite(x) || !isfinite(y) || !isfinite(z)) bad |= 1;
+    if (wall && !(z > 0.0)) bad |= 2;
+    if (bad) atomicOr(flag, bad);
+    if (precision == RMB_PREC_FP32_PAIRS) {
+        const gmem<SrcF32> r = as_global((SrcF32 *)src) + s;
+        r->x = x, r->y = y, r->z = z;
+        r->fx = (float)fx, r->fy = (float)fy, r->fz = (float)fz, r->zf = (float)z;
+    } else {
+        const gmem<SrcF64> r = as_global((SrcF64 *)src) + s;
+        r->x = x, r->y = y, r->z = z, r->fx = fx, r->fy = fy, r->fz = fz;
+    }
+}
+
+hipError_t launch_pack_sub_sources(int precision, const double *pos, const double *lam, int64_t nb, const double *off,
+                                   int32_t n_sub, double a, int wall, void *src, int *flag, hipStream_t s) {
+    const int64_t n = nb * n_sub;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(pack_sub_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, pos, lam, nb, off, n_sub,
+                       a, wall, precision, src, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_pack_table(const PackJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {
     if (n_wg <= 0) return hipSuccess;
     hipLaunchKernelGGL(pack_table_kernel, dim3((unsigned)n_wg), dim3(256), 0, s, jobs, n_jobs);
@@ -173,7 +218,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_f32_kernel(const PairJob *__r
     const int32_t split = (int32_t)(lt / J.n_tblock);
     const int64_t t0 = (lt % J.n_tblock) * kPairBlock;
     const int64_t s0 = split * J.chunk;
-    const int64_t s1 = min(s0 + J.chunk, J.nb);
+    const int64_t s1 = min(s0 + J.chunk, J.ns);
     global_ptr<SrcF32> __restrict__ src = (global_ptr<SrcF32>)J.src;
 
     const int64_t i = t0 + threadIdx.x;
@@ -269,7 +314,7 @@ __global__ __launch_bounds__(kPairBlock) void pair_f64_kernel(const PairJob *__r
     const int32_t split = (int32_t)(lt / J.n_tblock);
     const int64_t t0 = (lt % J.n_tblock) * kPairBlock;
     const int64_t s0 = split * J.chunk;
-    const int64_t s1 = min(s0 + J.chunk, J.nb);
+    const int64_t s1 = min(s0 + J.chunk, J.ns);
     global_ptr<SrcF64> __restrict__ src = (global_ptr<SrcF64>)J.src;
 
     const int64_t i = t0 + threadIdx.x;
