@@ -239,6 +239,68 @@ def factor_leg(rmb, torch, ctx, S, reps=3):
     return res
 
 
+def shared_leg(rmb, torch, ctx, S, reps=5):
+    """One factorisation per reference shape, rotated per body (free-space
+    blocks; for these wall problems the approximate preconditioner that
+    neglects the wall): (1) the 512 x 162-blob shells, factor and apply to 8
+    right-hand sides; (2) the 1000-boomerang solve to 1e-8 (FP32 pairs, FP64
+    refinement) with prebuilt shared blocks, against the wall blocks built
+    inside every solve."""
+    res = {}
+    sus, rhs = S.shells_wall()
+    sysd = rmb.System.from_suspension(sus)
+    shell = S.sphere_shell(162)
+    shapes = [shell - shell.mean(axis=0)]
+    idx = np.zeros(sus.n_bodies, np.int32)
+    qd = torch.tensor(sus.quat, dtype=torch.float64, device="cuda")
+    r = torch.tensor(rhs, dtype=torch.float64, device="cuda")
+    ts = []
+    for k in range(reps):
+        t = time.perf_counter()
+        pc = rmb.Precond.from_shapes(ctx, sysd, shapes, idx, qd)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+        if k < reps - 1:
+            pc.close()
+    out = pc.apply(r)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        pc.apply(r, out)
+    e1.record()
+    torch.cuda.synchronize()
+    pc.close()
+    res["shells"] = {"factor_ms": min(ts) * 1e3, "apply_8rhs_ms": e0.elapsed_time(e1) / reps}
+    log(f"  shared shells: factor {res['shells']['factor_ms']:.3f} ms, apply 8 rhs "
+        f"{res['shells']['apply_8rhs_ms']:.3f} ms")
+
+    sus = S.boomerangs_wall()
+    sysd = rmb.System.from_suspension(sus)
+    boo = S.boomerang()
+    qd = torch.tensor(sus.quat, dtype=torch.float64, device="cuda")
+    FT = torch.tensor(sus.FT, dtype=torch.float64, device="cuda")
+    t = time.perf_counter()
+    pc = rmb.Precond.from_shapes(ctx, sysd, [boo - boo.mean(axis=0)], np.zeros(sus.n_bodies, np.int32), qd)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t) * 1e3
+    rmb.solve_mobility(ctx, sysd, FT, precond=pc, tol=1e-8, precision="fp32")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, _, info = rmb.solve_mobility(ctx, sysd, FT, precond=pc, tol=1e-8, precision="fp32")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / reps * 1e3
+    _, _, iw = rmb.solve_mobility(ctx, sysd, FT, tol=1e-8, precision="fp32")
+    pc.close()
+    res["boomerangs"] = {"build_ms": build_ms, "ms_per_solve": ms, "iterations": info["iterations"],
+                         "iterations_wall_blocks": iw["iterations"], "rel_residual": info["rel_residual"],
+                         "status": info["status"]}
+    log(f"  shared boomerangs: build {build_ms:.2f} ms, solve {ms:.2f} ms, {info['iterations']} iterations "
+        f"({iw['iterations']} with the wall blocks)")
+    return res
+
+
 def serving_leg(rmb, torch, ctx, S, n_req, rate):
     t_gen = time.perf_counter()
     reqs = [S.mixed_wall_request(i) for i in range(n_req)]
@@ -431,6 +493,7 @@ def main():
             line["flow_field"] = flow_leg(rmb, torch, ctx, S)
         if not args.no_factor:
             line["batched_factor"] = factor_leg(rmb, torch, ctx, S)
+            line["shared_precond"] = shared_leg(rmb, torch, ctx, S)
         if not args.no_serving:
             line["serving"] = serving_leg(rmb, torch, ctx, S, args.requests, args.rate)
         if not args.no_cpu:

@@ -211,6 +211,50 @@ rmb_status rmb_precond_factor(rmb_ctx ctx, const rmb_system *sys, rmb_precond *o
 rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, const double *in,
                              double *out, rmb_stream stream);
 
+/* Reference shapes for a shared factorisation: blobs of shape k are
+ * ref_pos[shape_off[k] .. shape_off[k+1]) (host, [3] each, FP64), given in
+ * the body frame relative to the body's tracking point.  shape_off is host
+ * [n_shapes + 1] with shape_off[0] = 0. */
+typedef struct {
+    int32_t n_shapes;
+    int32_t reserved;
+    const int64_t *shape_off;
+    const double *ref_pos;
+} rmb_shapes;
+
+/* Block-diagonal preconditioner from one factorisation per reference shape
+ * (Sec. 2.2.2, after eq:saddle_M_precon: in an unbounded domain the RPY
+ * block of a body is that of its reference configuration, rotated, so
+ * bodies of one shape share one factorisation; in wall geometry this is the
+ * approximate preconditioner that neglects the boundary, Sec. 5.4).
+ * Body p uses shape body_shape[p] (host int32 [N]; its blob count must
+ * equal the shape's) and orientation body_quat[p] (device [N][4] FP64,
+ * (w, x, y, z), normalised here), i.e. its blob i is taken to sit at
+ * q_p + R_p ref_i.  Each shape's block is factorised once, in free space,
+ * with the system's a and eta; applying the preconditioner to body p rotates
+ * its blob velocities, force and torque into the body frame (R_p^T),
+ * applies the shape's factor, and rotates lambda, u and omega back (R_p).
+ * When the system's blobs are exactly at q_p + R_p ref_i in free space the
+ * result equals rmb_precond_factor's up to rounding.  The handle is used
+ * like one from rmb_precond_factor (rmb_precond_apply, rmb_solve_mobility)
+ * and holds factor memory for each shape only, plus 9 doubles per body.
+ * Errors: RMB_EINVAL (bad system, shapes, shape indices, blob-count
+ * mismatch, a zero or non-finite quaternion), RMB_ENOTSPD (a shape's block
+ * is not positive definite, or its K^T M^-1 K is singular), RMB_ENOMEM,
+ * RMB_EDEVICE.  Synchronises `stream`. */
+rmb_status rmb_precond_factor_shapes(rmb_ctx ctx, const rmb_system *sys, const rmb_shapes *shapes,
+                                     const int32_t *body_shape, const double *body_quat, rmb_precond *out,
+                                     rmb_stream stream);
+
+/* New body orientations (device [N][4], as above) for a preconditioner
+ * from rmb_precond_factor_shapes: the shape factors are kept, so a moving
+ * configuration needs no refactorisation (Sec. 2.2.2).  Work already queued
+ * with `pc` on other streams must have completed.  Errors: RMB_EINVAL (pc
+ * not from rmb_precond_factor_shapes, NULL quaternions, a zero or non-finite
+ * quaternion; rotations of such bodies are then the identity), RMB_EDEVICE.
+ * Synchronises `stream`. */
+rmb_status rmb_precond_set_orientations(rmb_ctx ctx, rmb_precond pc, const double *body_quat, rmb_stream stream);
+
 /* Releases the factors (after work using them has completed).  Safe on NULL. */
 void rmb_precond_destroy(rmb_precond pc);
 
@@ -245,7 +289,8 @@ typedef struct {
 /* Mobility problem: given F (device [N][6], force then torque about q_p) and
  * optional slip (device [Nb][3] or NULL), returns U (device [N][6]) and
  * lambda (device [Nb][3]) with b = [slip; -F], x0 = 0.  `pc` may be a
- * preconditioner built by rmb_precond_factor for this same system, or NULL
+ * preconditioner built by rmb_precond_factor or rmb_precond_factor_shapes
+ * for this same system, or NULL
  * (factorised internally).  opts may be NULL (defaults).  info may be NULL.
  * Errors: RMB_EINVAL, RMB_ENOTSPD, RMB_ENOCONV (outputs hold the last
  * iterate; info->rel_residual its FP64 residual), RMB_ENOMEM, RMB_EDEVICE.

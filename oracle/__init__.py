@@ -17,6 +17,9 @@ definitions, with library primitives (numpy/scipy dense solves) as steps.
   BlockPreconditioner        -> indefinite block-diagonal preconditioner
                                 (eq:M_tilde_block_diag, eq:indef_block_P,
                                 eq:saddle_M_precon)
+  ShapePreconditioner        -> the same with one free-space block per
+                                reference shape, rotated per body (Sec. 2.2.2
+                                after eq:saddle_M_precon; Sec. 5.4)
   gmres                      -> right-preconditioned GMRES (Sec. 2.2.2; right
                                 preconditioning so the monitored residual is
                                 the true one, Sec. 3.3)
@@ -279,6 +282,51 @@ class BlockPreconditioner:
         return np.concatenate([lam.ravel(), U.ravel()])
 
 
+class ShapePreconditioner:
+    """Block-diagonal preconditioner from one block per reference shape
+    (Sec. 2.2.2, after eq:saddle_M_precon: the free-space RPY block of a body
+    is its reference configuration's, rotated; Sec. 5.4: the same blocks used
+    for a wall problem give the approximate preconditioner that neglects the
+    boundary).  Shape k's saddle block [M_ref -K_ref; -K_ref^T 0] is formed
+    in free space from its body-frame blob positions (tracking point at the
+    origin).  For body p with rotation R_p (from its quaternion), the blob
+    velocities, force and torque of the input are rotated into the body
+    frame (R_p^T), the shape's block is solved, and lambda, u and omega are
+    rotated back (R_p)."""
+
+    def __init__(self, sus, shapes, body_shape, quats):
+        from scipy.spatial.transform import Rotation
+        self.sus = sus
+        self.body_shape = np.asarray(body_shape, dtype=np.int64)
+        q = np.asarray(quats, dtype=np.float64).reshape(-1, 4)
+        # scipy orders quaternions (x, y, z, w) and normalises them
+        self.R = Rotation.from_quat(q[:, [1, 2, 3, 0]]).as_matrix()
+        self.blocks = []
+        for ref in shapes:
+            ref = np.asarray(ref, dtype=np.float64).reshape(-1, 3)
+            M = assemble(ref, sus.a, sus.eta, False)
+            K = K_dense(ref, np.array([0, len(ref)]), np.zeros((1, 3)))
+            self.blocks.append(np.block([[M, -K], [-K.T, np.zeros((6, 6))]]))
+
+    def apply(self, v) -> np.ndarray:
+        sus = self.sus
+        sv, Fv = split(sus, np.asarray(v, dtype=np.float64))
+        lam = np.empty_like(sv)
+        U = np.empty_like(Fv)
+        off = sus.body_off
+        for p in range(sus.n_bodies):
+            s, e = off[p], off[p + 1]
+            R = self.R[p]
+            # row vectors: (R^T x)^T = x^T R
+            top = sv[s:e] @ R
+            bot = np.concatenate([Fv[p, 0:3] @ R, Fv[p, 3:6] @ R])
+            x = np.linalg.solve(self.blocks[self.body_shape[p]], np.concatenate([top.ravel(), bot]))
+            lam[s:e] = x[:3 * (e - s)].reshape(-1, 3) @ R.T
+            U[p, 0:3] = x[-6:-3] @ R.T
+            U[p, 3:6] = x[-3:] @ R.T
+        return np.concatenate([lam.ravel(), U.ravel()])
+
+
 # ----------------------------------------------------------------------------
 # GMRES
 # ----------------------------------------------------------------------------
@@ -335,11 +383,12 @@ def gmres(apply_A, apply_Pinv, b, tol=1e-12, restart=100, maxiter=1000):
         x = x + apply_Pinv(V[:k_used].T @ y)
 
 
-def solve_mobility(sus, FT, slip=None, tol=1e-12, restart=100, maxiter=1000):
+def solve_mobility(sus, FT, slip=None, tol=1e-12, restart=100, maxiter=1000, precond=None):
     """Mobility problem by right-preconditioned GMRES with the block-diagonal
-    preconditioner.  Returns (U, lambda, info)."""
+    preconditioner (or `precond`, e.g. a ShapePreconditioner).  Returns
+    (U, lambda, info)."""
     t0 = time.perf_counter()
-    P = BlockPreconditioner(sus)
+    P = BlockPreconditioner(sus) if precond is None else precond
     b = rhs(sus, FT, slip)
     x, it, hist = gmres(lambda v: saddle_apply(sus, v), P.apply, b, tol, restart, maxiter)
     lam, U = split(sus, x)

@@ -32,7 +32,7 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
            "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan",
-           "rmb_flow_field"]
+           "rmb_flow_field", "rmb_precond_factor_shapes", "rmb_precond_set_orientations"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -46,6 +46,11 @@ class rmb_system(ctypes.Structure):
     _fields_ = [("n_blobs", ctypes.c_int64), ("n_bodies", ctypes.c_int64),
                 ("pos", ctypes.c_void_p), ("body_off", ctypes.c_void_p), ("q", ctypes.c_void_p),
                 ("a", ctypes.c_double), ("eta", ctypes.c_double), ("geometry", ctypes.c_int32)]
+
+
+class rmb_shapes(ctypes.Structure):
+    _fields_ = [("n_shapes", ctypes.c_int32), ("reserved", ctypes.c_int32), ("shape_off", ctypes.c_void_p),
+                ("ref_pos", ctypes.c_void_p)]
 
 
 class rmb_solve_opts(ctypes.Structure):
@@ -92,6 +97,9 @@ def library(path: str = LIB_PATH):
         optp, infop = ctypes.POINTER(rmb_solve_opts), ctypes.POINTER(rmb_solve_info)
         L.rmb_precond_factor.argtypes = [vp, sysp, ctypes.POINTER(vp), vp]
         L.rmb_precond_apply.argtypes = [vp, vp, i32, vp, vp, vp]
+        L.rmb_precond_factor_shapes.argtypes = [vp, sysp, ctypes.POINTER(rmb_shapes), vp, vp, ctypes.POINTER(vp),
+                                                vp]
+        L.rmb_precond_set_orientations.argtypes = [vp, vp, vp, vp]
         L.rmb_precond_destroy.argtypes = [vp]
         L.rmb_precond_destroy.restype = None
         L.rmb_solve_mobility.argtypes = [vp, sysp, vp, vp, vp, vp, vp, optp, infop, vp]
@@ -280,13 +288,41 @@ def _vec(t, name, n):
 class Precond:
     """Block-diagonal preconditioner factors of one system (rmb_precond)."""
 
-    def __init__(self, ctx: Context, system: System, stream=None):
+    def __init__(self, ctx: Context, system: System, stream=None, _handle=None):
         self.ctx, self.system = ctx, system
         h = ctypes.c_void_p()
-        ctx.check(ctx.lib.rmb_precond_factor(ctx.h, ctypes.byref(system.c), ctypes.byref(h),
-                                             _stream(stream)))
+        if _handle is None:
+            ctx.check(ctx.lib.rmb_precond_factor(ctx.h, ctypes.byref(system.c), ctypes.byref(h),
+                                                 _stream(stream)))
+        else:
+            h = _handle
         self.h = h
         ctx._adopt(self)
+
+    @classmethod
+    def from_shapes(cls, ctx: Context, system: System, shapes, body_shape, quat: torch.Tensor, stream=None):
+        """One factorisation per reference shape (rmb_precond_factor_shapes):
+        shapes is a list of (n_k, 3) body-frame blob positions relative to the
+        tracking point, body_shape the shape index of every body, quat the
+        (N, 4) device orientations (w, x, y, z)."""
+        import numpy as np
+        refs = [np.asarray(r, dtype=np.float64).reshape(-1, 3) for r in shapes]
+        off = np.ascontiguousarray(np.concatenate([[0], np.cumsum([len(r) for r in refs])]).astype(np.int64))
+        ref = np.ascontiguousarray(np.concatenate(refs, axis=0))
+        bs = np.ascontiguousarray(np.asarray(body_shape, dtype=np.int32).reshape(-1))
+        if bs.shape[0] != system.n_bodies:
+            raise ValueError(f"body_shape has {bs.shape[0]} entries for {system.n_bodies} bodies")
+        qp = _dev(quat, "quat", (system.n_bodies, 4))
+        sh = rmb_shapes(len(refs), 0, off.ctypes.data, ref.ctypes.data)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.rmb_precond_factor_shapes(ctx.h, ctypes.byref(system.c), ctypes.byref(sh),
+                                                    bs.ctypes.data, qp, ctypes.byref(h), _stream(stream)))
+        return cls(ctx, system, _handle=h)
+
+    def set_orientations(self, quat: torch.Tensor, stream=None):
+        """New (N, 4) device orientations for a shared-shape preconditioner."""
+        qp = _dev(quat, "quat", (self.system.n_bodies, 4))
+        self.ctx.check(self.ctx.lib.rmb_precond_set_orientations(self.ctx.h, self.h, qp, _stream(stream)))
 
     def apply(self, rhs: torch.Tensor, out: torch.Tensor = None, stream=None) -> torch.Tensor:
         """P^-1 applied to each row of rhs (nrhs, 3 Nb + 6 N)."""

@@ -446,9 +446,25 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     const double *Y = big_Y(it), *Dinv = big_Dinv(it), *Sc = big_Sc(it);
     double *X = lds;  // Mp x 8
     const int64_t b3 = 3 * it.w.blob0, u6 = J.nb3 + 6 * (int64_t)it.w.body;
-    for (int e = tid; e < Mp * R; e += 256) {
-        const int row = e / R, c = e % R;
-        X[e] = (row < m && c < nr) ? as_global(J.in)[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
+    // with a shared reference-shape factor, the right-hand sides are taken
+    // into the body frame (R^T on every 3-vector) and the results back (R)
+    const gmem<const double> Rot = as_global(it.w.rot);
+    if (it.w.rot) {
+        for (int e = tid; e < Mp * R; e += 256) {
+            const int row = e / R, c = e % R;
+            double v = 0.0;
+            if (row < m && c < nr) {
+                const gmem<const double> x = as_global(J.in) + (int64_t)(r0 + c) * J.ld + b3 + row - row % 3;
+                const int k = row % 3;
+                v = Rot[k] * x[0] + Rot[3 + k] * x[1] + Rot[6 + k] * x[2];
+            }
+            X[e] = v;
+        }
+    } else {
+        for (int e = tid; e < Mp * R; e += 256) {
+            const int row = e / R, c = e % R;
+            X[e] = (row < m && c < nr) ? as_global(J.in)[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
+        }
     }
     __syncthreads();
     forward_rl<NB, R>(L, as_global(Dinv), Mp, X, Dj, T);
@@ -472,7 +488,17 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         const int c = tid / 6, k = tid % 6;
         double acc = 0.0;
         for (int qp = 0; qp < QP; ++qp) acc += part[(qp * R + c) * 6 + k];
-        g[c][k] = c < nr ? -as_global(J.in)[(int64_t)(r0 + c) * J.ld + u6 + k] - acc : 0.0;
+        double bot = 0.0;
+        if (c < nr) {
+            const gmem<const double> x = as_global(J.in) + (int64_t)(r0 + c) * J.ld + u6;
+            if (it.w.rot) {
+                const int b = k - k % 3, kk = k % 3;
+                bot = Rot[kk] * x[b] + Rot[3 + kk] * x[b + 1] + Rot[6 + kk] * x[b + 2];
+            } else {
+                bot = x[k];
+            }
+        }
+        g[c][k] = c < nr ? -bot - acc : 0.0;
     }
     __syncthreads();
     if (tid < nr) {
@@ -504,6 +530,25 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     }
     __syncthreads();
     backward_rl<NB, R>(L, as_global(Dinv), Mp, X, Dj, T);
+    if (it.w.rot) {
+        // backward_rl ends with a barrier, so all of X is final here
+        for (int e = tid; e < m * R; e += 256) {
+            const int row = e / R, c = e % R;
+            if (c < nr) {
+                const int b = row - row % 3, k = row % 3;
+                as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] =
+                    Rot[3 * k] * X[b * R + c] + Rot[3 * k + 1] * X[(b + 1) * R + c] + Rot[3 * k + 2] * X[(b + 2) * R + c];
+            }
+        }
+        if (tid < R * 6) {
+            const int c = tid / 6, k = tid % 6;
+            const int b = k - k % 3, kk = k % 3;
+            if (c < nr)
+                as_global(J.out)[(int64_t)(r0 + c) * J.ld + u6 + k] =
+                    Rot[3 * kk] * g[c][b] + Rot[3 * kk + 1] * g[c][b + 1] + Rot[3 * kk + 2] * g[c][b + 2];
+        }
+        return;
+    }
     for (int e = tid; e < m * R; e += 256) {
         const int row = e / R, c = e % R;
         if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];

@@ -22,6 +22,9 @@ struct BodyWork {
     int32_t pad;
     double a, pref;     // blob radius, 1/(6 pi eta a)
     int *flag;          // build status of the body's system (bits 4: not SPD, 8: singular)
+    const double *rot;  // apply only: NULL, or the body's rotation R (3 x 3, row-major) when the
+                        // factor is that of a shared reference shape; the body's block is then
+                        // R~ P_ref^-1 R~^T (R~ = R on every 3-vector)
 };
 
 // A body whose block exceeds the LDS path: padded to Mp (multiple of 32).
@@ -90,6 +93,11 @@ hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int
 // `panel`: the panel width (16 or 32) the bodies' factors were built with.
 hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
                                       int max_Mp, int panel, hipStream_t s);
+// Rotation matrices (row-major, 9 doubles per body) of N quaternions
+// (w, x, y, z), normalised on the fly; a zero or non-finite quaternion sets
+// bit 16 of *flag and yields the identity.
+hipError_t launch_quat_rotations(const double *quat, int64_t N, double *rot, int *flag, hipStream_t s);
+
 hipError_t launch_saddle(const SaddleJob *jobs, int32_t n_jobs, int64_t n_blob_blocks, int64_t n_bodies,
                          hipStream_t s);
 

@@ -151,7 +151,11 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 
 // Solves one body's [M_pp -K_p; -K_p^T 0][lambda; U] = [s; bottom] with the
 // body's factor staged in LDS (lds: m*m + 6m + 36 doubles of the factor,
-// then 2m doubles).
+// then 2m doubles).  With a rotation R (shared reference-shape factor), the
+// inputs are taken into the body frame (R^T on every 3-vector: blob
+// velocities, force, torque) and the results back (R on lambda, u, omega):
+// the RPY tensor and K are rotation-covariant, M_pp = R~ M_ref R~^T and
+// K_p = R~ K_ref diag(R, R)^T.
 constexpr int kApplyThreads = 64;
 
 __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gmem<const double> s_in,
@@ -176,7 +180,15 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
             if (e < nf) F[e] = v[i];
         }
     }
-    for (int e = tid; e < m; e += kApplyThreads) sv[e] = s_in[e];
+    const gmem<const double> R = as_global(it.rot);
+    if (it.rot) {
+        for (int e = tid; e < m; e += kApplyThreads) {
+            const int b = e - e % 3, c = e % 3;
+            sv[e] = R[c] * s_in[b] + R[3 + c] * s_in[b + 1] + R[6 + c] * s_in[b + 2];
+        }
+    } else {
+        for (int e = tid; e < m; e += kApplyThreads) sv[e] = s_in[e];
+    }
     __syncthreads();
     // t = Li s
     for (int r = tid; r < m; r += kApplyThreads) {
@@ -189,7 +201,12 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
     if (tid < 6) {
         double acc = 0.0;
         for (int l = 0; l < m; ++l) acc += Y[l * 6 + tid] * t[l];
-        g[tid] = -bot_in[tid] - acc;
+        double bot = bot_in[tid];
+        if (it.rot) {
+            const int b = tid - tid % 3, c = tid % 3;
+            bot = R[c] * bot_in[b] + R[3 + c] * bot_in[b + 1] + R[6 + c] * bot_in[b + 2];
+        }
+        g[tid] = -bot - acc;
     }
     __syncthreads();
     // U = S^-1 g
@@ -206,12 +223,29 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         sv[r] = acc;
     }
     __syncthreads();
+    if (!it.rot) {
+        for (int r = tid; r < m; r += kApplyThreads) {
+            double acc = 0.0;
+            for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
+            lam_out[r] = acc;
+        }
+        if (tid < 6) U_out[tid] = g[6 + tid];
+        return;
+    }
     for (int r = tid; r < m; r += kApplyThreads) {
         double acc = 0.0;
         for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
-        lam_out[r] = acc;
+        t[r] = acc;
     }
-    if (tid < 6) U_out[tid] = g[6 + tid];
+    __syncthreads();
+    for (int e = tid; e < m; e += kApplyThreads) {
+        const int b = e - e % 3, c = e % 3;
+        lam_out[e] = R[3 * c] * t[b] + R[3 * c + 1] * t[b + 1] + R[3 * c + 2] * t[b + 2];
+    }
+    if (tid < 6) {
+        const int b = 6 + tid - tid % 3, c = tid % 3;
+        U_out[tid] = R[3 * c] * g[b] + R[3 * c + 1] * g[b + 1] + R[3 * c + 2] * g[b + 2];
+    }
 }
 
 __global__ __launch_bounds__(kApplyThreads) void precond_apply_small_kernel(const PrecondApplyJob *__restrict__ jobs,
@@ -233,6 +267,42 @@ __global__ __launch_bounds__(kApplyThreads) void precond_apply_small_kernel(cons
     const int64_t b3 = 3 * it.blob0;
     const int64_t u6 = J.nb3 + 6 * (int64_t)it.body;
     precond_body_apply(it, in + b3, in + u6, out + b3, out + u6, lds, g);
+}
+
+// ---------------------------------------------------------------------------
+// body orientations
+// ---------------------------------------------------------------------------
+
+// R of the unit quaternion q / |q| (w, x, y, z), row-major; the factor
+// s = 2 / |q|^2 folds the normalisation into the usual formula.
+__global__ void quat_rot_kernel(const double *__restrict__ quat, int64_t N, double *__restrict__ rot, int *flag) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const gmem<const double> Q = as_global(quat) + 4 * p;
+    const double w = Q[0], x = Q[1], y = Q[2], z = Q[3];
+    const double n2 = w * w + x * x + y * y + z * z;
+    gmem<double> R = as_global(rot) + 9 * p;
+    if (!(n2 > 0.0) || !isfinite(n2)) {
+        atomicOr(flag, 16);
+        for (int e = 0; e < 9; ++e) R[e] = (e % 4 == 0) ? 1.0 : 0.0;
+        return;
+    }
+    const double s = 2.0 / n2;
+    R[0] = 1.0 - s * (y * y + z * z);
+    R[1] = s * (x * y - w * z);
+    R[2] = s * (x * z + w * y);
+    R[3] = s * (x * y + w * z);
+    R[4] = 1.0 - s * (x * x + z * z);
+    R[5] = s * (y * z - w * x);
+    R[6] = s * (x * z - w * y);
+    R[7] = s * (y * z + w * x);
+    R[8] = 1.0 - s * (x * x + y * y);
+}
+
+hipError_t launch_quat_rotations(const double *quat, int64_t N, double *rot, int *flag, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(quat_rot_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, quat, N, rot, flag);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

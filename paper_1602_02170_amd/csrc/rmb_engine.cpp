@@ -35,6 +35,9 @@ struct rmb_precond_s {
     BigBody *bigs_d = nullptr;
     double *factor = nullptr;
     int *flag_d = nullptr;
+    // shared reference-shape factors: one factor per shape, per-body rotations
+    int32_t n_shapes = 0;
+    double *rot_d = nullptr;
 };
 
 namespace rmb {
@@ -121,15 +124,22 @@ static rmb_status check_body_sizes(rmb_ctx ctx, const int64_t *off, int64_t N) {
     return RMB_OK;
 }
 
+// Batches smaller than this are not timed (too few workgroups to show what
+// a full batch would do); they use the tuned shape if there is one, else
+// the first.
+constexpr int32_t kTuneMinBodies = 64;
+
 // Tile shape of the large-body factorisation for padded size Mp, chosen by
-// timing every candidate shape on the first batch of that size (cached per
-// context; the timings are kept in the context's tune log).
+// timing every candidate shape on the first batch of that size with at
+// least kTuneMinBodies bodies (cached per context; the timings are kept in
+// the context's tune log).
 static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, int max_Mp, hipStream_t s,
                               int *variant_out) {
     auto it = ctx->tuned_panel.find(max_Mp);
-    if (it != ctx->tuned_panel.end()) {
-        *variant_out = it->second;
-        RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, it->second, s));
+    if (it != ctx->tuned_panel.end() || n < kTuneMinBodies) {
+        const int v = it != ctx->tuned_panel.end() ? it->second : 0;
+        *variant_out = v;
+        RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, v, s));
         return RMB_OK;
     }
     const int nv = large_variant_count();
@@ -873,6 +883,169 @@ rmb_status rmb_precond_factor(rmb_ctx ctx, const rmb_system *sys, rmb_precond *o
     if (*hf & 4) return cleanup(fail(ctx, RMB_ENOTSPD, "a body's mobility block is not positive definite"));
     if (*hf & 8) return cleanup(fail(ctx, RMB_ENOTSPD, "a body's K^T M^-1 K block is singular"));
     *out = pc;
+    return RMB_OK;
+}
+
+rmb_status rmb_precond_factor_shapes(rmb_ctx ctx, const rmb_system *sys, const rmb_shapes *shapes,
+                                     const int32_t *body_shape, const double *body_quat, rmb_precond *out,
+                                     rmb_stream stream) {
+    if (!ctx || !out) return RMB_EINVAL;
+    *out = nullptr;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_system(ctx, sys, true));
+    if (!shapes || shapes->n_shapes < 1 || !shapes->shape_off || !shapes->ref_pos)
+        return fail(ctx, RMB_EINVAL, "shapes: n_shapes >= 1, shape_off and ref_pos are required");
+    if (!body_shape || !body_quat) return fail(ctx, RMB_EINVAL, "body_shape and body_quat are required");
+    const int32_t S = shapes->n_shapes;
+    const int64_t *so = shapes->shape_off;
+    if (so[0] != 0) return fail(ctx, RMB_EINVAL, "shape_off[0] must be 0");
+    for (int32_t k = 0; k < S; ++k)
+        if (so[k + 1] <= so[k]) return fail(ctx, RMB_EINVAL, "shape %d has no blobs", k);
+    const int64_t n_ref = so[S];
+    for (int64_t e = 0; e < 3 * n_ref; ++e)
+        if (!std::isfinite(shapes->ref_pos[e])) return fail(ctx, RMB_EINVAL, "shape positions must be finite");
+    RMB_TRY(check_body_sizes(ctx, so, S));
+    const int64_t N = sys->n_bodies;
+    for (int64_t p = 0; p < N; ++p) {
+        const int32_t k = body_shape[p];
+        if (k < 0 || k >= S) return fail(ctx, RMB_EINVAL, "body %lld: shape index %d out of range", (long long)p, k);
+        const int64_t nbp = sys->body_off[p + 1] - sys->body_off[p];
+        if (nbp != so[k + 1] - so[k])
+            return fail(ctx, RMB_EINVAL, "body %lld has %lld blobs, its shape %d has %lld", (long long)p,
+                        (long long)nbp, k, (long long)(so[k + 1] - so[k]));
+    }
+
+    auto pc = new rmb_precond_s();
+    pc->ctx = ctx;
+    pc->nb = sys->n_blobs;
+    pc->N = N;
+    pc->n_shapes = S;
+    // device: [factors | ref positions | shape tracking points (0) | shape
+    // build items | shape big items | body items | body big items | rotations | flag]
+    const size_t fbytes = al(factor_total(so, S) * 8), rbytes = al(n_ref * 24), qbytes = al(S * 24);
+    const size_t sib = al(S * sizeof(BodyWork)), sgb = al(S * sizeof(BigBody));
+    const size_t ibytes = al(N * sizeof(BodyWork)), gbytes = al(N * sizeof(BigBody)), tbytes = al(N * 72);
+    const size_t total = fbytes + rbytes + qbytes + sib + sgb + ibytes + gbytes + tbytes + 256;
+    pc->dbuf = (char *)ctx->arena->alloc(total);
+    if (!pc->dbuf) {
+        delete pc;
+        return fail(ctx, RMB_ENOMEM, "shared preconditioner (%zu bytes) exceeds the budget", total);
+    }
+    char *p0 = pc->dbuf;
+    pc->factor = (double *)p0;
+    double *ref_d = (double *)(p0 += fbytes);
+    double *q0_d = (double *)(p0 += rbytes);
+    BodyWork *sitems_d = (BodyWork *)(p0 += qbytes);
+    BigBody *sbigs_d = (BigBody *)(p0 += sib);
+    pc->items_d = (BodyWork *)(p0 += sgb);
+    pc->bigs_d = (BigBody *)(p0 += ibytes);
+    pc->rot_d = (double *)(p0 += gbytes);
+    pc->flag_d = (int *)(p0 += tbytes);
+    auto cleanup = [&](rmb_status st) {
+        (void)hipStreamSynchronize(s);
+        ctx->arena->free(pc->dbuf);
+        delete pc;
+        return st;
+    };
+
+    // the shapes as a free-space system of S bodies with tracking points at
+    // the origin of their reference frames
+    rmb_system ref = *sys;
+    ref.n_blobs = n_ref;
+    ref.n_bodies = S;
+    ref.pos = ref_d;
+    ref.body_off = so;
+    ref.q = q0_d;
+    ref.geometry = RMB_GEOM_FREE;
+    BodyLists sl;
+    body_items(ref, so, pc->factor, pc->flag_d, sl);
+    // per body: the shape's factor, the body's blob range and rotation
+    std::vector<int32_t> sidx(S, -1);
+    for (size_t i = 0; i < sl.small.size(); ++i) sidx[sl.small[i].body] = (int32_t)i;
+    for (size_t i = 0; i < sl.large.size(); ++i) sidx[sl.large[i].w.body] = (int32_t)i;
+    std::vector<BodyWork> bs;
+    std::vector<BigBody> bl;
+    int max_m = 0, max_Mp = 0;
+    for (int64_t p = 0; p < N; ++p) {
+        const int32_t k = body_shape[p];
+        const bool large = is_large_body(so[k + 1] - so[k]);
+        BodyWork w = large ? sl.large[sidx[k]].w : sl.small[sidx[k]];
+        w.pos = sys->pos;
+        w.q = sys->q + 3 * p;
+        w.blob0 = sys->body_off[p];
+        w.body = (int32_t)p;
+        w.wall = 0;
+        w.rot = pc->rot_d + 9 * p;
+        if (large) {
+            BigBody g{};
+            g.w = w;
+            g.Mp = (int32_t)padded_dim(w.n_blobs);
+            bl.push_back(g);
+            max_Mp = std::max(max_Mp, g.Mp);
+        } else {
+            bs.push_back(w);
+            max_m = std::max(max_m, 3 * w.n_blobs);
+        }
+    }
+    pc->n_small = (int32_t)bs.size();
+    pc->n_large = (int32_t)bl.size();
+    pc->max_m = max_m;
+    pc->max_Mp = max_Mp;
+
+    const size_t h_ref = n_ref * 24, h_ss = sl.small.size() * sizeof(BodyWork), h_sl = sl.large.size() * sizeof(BigBody);
+    const size_t h_bs = bs.size() * sizeof(BodyWork), h_bl = bl.size() * sizeof(BigBody);
+    const size_t o_ss = al(h_ref), o_sl = o_ss + al(h_ss), o_bs = o_sl + al(h_sl), o_bl = o_bs + al(h_bs),
+                 o_hf = o_bl + al(h_bl);
+    char *h = nullptr;
+    rmb_status st = pinned(ctx, o_hf + 64, (void **)&h);
+    if (st != RMB_OK) return cleanup(st);
+    memcpy(h, shapes->ref_pos, h_ref);
+    memcpy(h + o_ss, sl.small.data(), h_ss);
+    memcpy(h + o_sl, sl.large.data(), h_sl);
+    memcpy(h + o_bs, bs.data(), h_bs);
+    memcpy(h + o_bl, bl.data(), h_bl);
+    if (hipMemsetAsync(pc->flag_d, 0, sizeof(int), s) != hipSuccess ||
+        hipMemsetAsync(q0_d, 0, S * 24, s) != hipSuccess ||
+        hipMemcpyAsync(ref_d, h, h_ref, hipMemcpyHostToDevice, s) != hipSuccess ||
+        (h_ss && hipMemcpyAsync(sitems_d, h + o_ss, h_ss, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (h_sl && hipMemcpyAsync(sbigs_d, h + o_sl, h_sl, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (h_bs && hipMemcpyAsync(pc->items_d, h + o_bs, h_bs, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        (h_bl && hipMemcpyAsync(pc->bigs_d, h + o_bl, h_bl, hipMemcpyHostToDevice, s) != hipSuccess) ||
+        launch_precond_build_small(sitems_d, (int32_t)sl.small.size(), sl.max_m, s) != hipSuccess ||
+        launch_quat_rotations(body_quat, N, pc->rot_d, pc->flag_d, s) != hipSuccess)
+        return cleanup(fail(ctx, RMB_EDEVICE, "shared preconditioner build launch failed"));
+    if (!sl.large.empty()) {
+        int variant = 0;
+        st = build_large(ctx, sbigs_d, (int32_t)sl.large.size(), sl.max_Mp, s, &variant);
+        if (st != RMB_OK) return cleanup(st);
+        pc->variant = variant;
+    }
+    int *hf = (int *)(h + o_hf);
+    if (hipMemcpyAsync(hf, pc->flag_d, sizeof(int), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup(fail(ctx, RMB_EDEVICE, "shared preconditioner build failed"));
+    if (*hf & 16) return cleanup(fail(ctx, RMB_EINVAL, "a body quaternion is zero or not finite"));
+    if (*hf & 4) return cleanup(fail(ctx, RMB_ENOTSPD, "a shape's mobility block is not positive definite"));
+    if (*hf & 8) return cleanup(fail(ctx, RMB_ENOTSPD, "a shape's K^T M^-1 K block is singular"));
+    *out = pc;
+    return RMB_OK;
+}
+
+rmb_status rmb_precond_set_orientations(rmb_ctx ctx, rmb_precond pc, const double *body_quat, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    if (!pc || pc->ctx != ctx) return fail(ctx, RMB_EINVAL, "preconditioner is NULL or from another context");
+    if (!pc->rot_d) return fail(ctx, RMB_EINVAL, "preconditioner has no shared shape factors");
+    if (!body_quat) return fail(ctx, RMB_EINVAL, "body_quat is required");
+    int *hf = nullptr;
+    RMB_TRY(pinned(ctx, sizeof(int), (void **)&hf));
+    RMB_HIP(ctx, hipMemsetAsync(pc->flag_d, 0, sizeof(int), s));
+    RMB_HIP(ctx, launch_quat_rotations(body_quat, pc->N, pc->rot_d, pc->flag_d, s));
+    RMB_HIP(ctx, hipMemcpyAsync(hf, pc->flag_d, sizeof(int), hipMemcpyDeviceToHost, s));
+    RMB_HIP(ctx, hipStreamSynchronize(s));
+    if (*hf & 16) return fail(ctx, RMB_EINVAL, "a body quaternion is zero or not finite");
     return RMB_OK;
 }
 
