@@ -87,6 +87,14 @@ typedef struct {
     double a;                /* blob hydrodynamic radius, > 0 */
     double eta;              /* viscosity, > 0 */
     int32_t geometry;        /* RMB_GEOM_FREE or RMB_GEOM_WALL (then every z_i > 0) */
+    int32_t reserved;
+    const double *blob_shift; /* device [Nb] or NULL.  Permeable bodies (appendix on permeable
+                                 bodies, eq:permeable_slip): d_i = kappa_p / (eta dV_i) >= 0 for
+                                 blob i of body p, i.e. a slip -d_i lambda_i, which adds d_i to
+                                 the diagonal of M.  Every operation on the system then uses
+                                 M + diag(d) (product, preconditioner factors, solves), except
+                                 the flow field and the shared-shape factors, which leave it
+                                 out.  NULL: rigid impermeable bodies (d = 0). */
 } rmb_system;
 
 /* ---------------------------------------------------------------------------
@@ -160,12 +168,13 @@ rmb_status rmb_ctx_tune_log(rmb_ctx ctx, int32_t capacity, rmb_tune_record *reco
  * wall-corrected form of Sec. 2.1.1 and Sec. 5)
  * ------------------------------------------------------------------------- */
 
-/* vel[i] = sum_j M_ij lambda[j] over all blobs of `sys` (bodies are ignored;
+/* vel[i] = sum_j M_ij lambda[j] (+ d_i lambda[i] with sys->blob_shift) over
+ * all blobs of `sys` (bodies are ignored;
  * n_bodies, body_off and q may be 0/NULL).  lambda and vel: device
  * [Nb][3] FP64, must not alias.  `precision` is an RMB_PREC_* value.
  * Errors: RMB_EINVAL (bad system, z_i <= 0 in wall geometry, non-finite
- * positions), RMB_ENOMEM, RMB_EDEVICE.  Synchronises `stream` once for
- * validation. */
+ * positions, a negative or non-finite blob_shift), RMB_ENOMEM, RMB_EDEVICE.
+ * Synchronises `stream` once for validation. */
 rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
                                const double *lambda, double *vel, rmb_stream stream);
 

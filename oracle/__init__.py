@@ -10,7 +10,9 @@ definitions, with library primitives (numpy/scipy dense solves) as steps.
            the wall-corrected RPY (Sec. 2.1.1, Sec. 5)
   K U, K^T lambda            -> rigid no-slip kinematics (eq:noslip_rigid,
                                 eq:rigidSystem)
-  saddle operator A [lambda; U] = [M lambda - K U; -K^T lambda] (eq:saddle_M)
+  saddle operator A [lambda; U] = [M lambda - K U; -K^T lambda] (eq:saddle_M);
+  permeable bodies (eq:permeable_slip) put d_i on the diagonal of M in the
+  operator, the dense solve and the per-body blocks
   dense_solve                -> U = N (F - K^T M^-1 slip), N = (K^T M^-1 K)^-1,
                                 lambda = M^-1 (K U + slip)  (Schur complement
                                 below eq:saddle_M, eq:BodyMob)
@@ -189,6 +191,14 @@ def K_dense(pos, off, q) -> np.ndarray:
 # saddle-point system (eq:saddle_M)
 # ----------------------------------------------------------------------------
 
+def _shift3(sus):
+    """Permeable bodies (eq:permeable_slip): the slip -d_i lambda_i, i.e.
+    d_i added to the three diagonal entries of blob i in M; None if the
+    bodies are impermeable."""
+    d = getattr(sus, "blob_shift", None)
+    return None if d is None else np.repeat(np.asarray(d, dtype=np.float64), 3)
+
+
 def split(sus, x):
     nb3 = 3 * sus.n_blobs
     return x[:nb3].reshape(-1, 3), x[nb3:].reshape(-1, 6)
@@ -204,6 +214,9 @@ def saddle_apply(sus, x) -> np.ndarray:
     """A [lambda; U] = [M lambda - K U; -K^T lambda]."""
     lam, U = split(sus, x)
     top = matvec(sus.pos, lam, sus.a, sus.eta, sus.wall) - K_apply(sus.pos, sus.body_off, sus.q, U)
+    d3 = _shift3(sus)
+    if d3 is not None:
+        top = top + (d3 * lam.ravel()).reshape(-1, 3)
     bot = -KT_apply(sus.pos, sus.body_off, sus.q, lam)
     return np.concatenate([top.ravel(), bot.ravel()])
 
@@ -222,6 +235,9 @@ def dense_solve(sus, FT, slip=None):
     U = N (F - K^T M^-1 slip), N = (K^T M^-1 K)^-1, lambda = M^-1 (K U + slip).
     Returns (U (N x 6), lambda (Nb x 3))."""
     M = assemble(sus.pos, sus.a, sus.eta, sus.wall)
+    d3 = _shift3(sus)
+    if d3 is not None:
+        M[np.diag_indices_from(M)] += d3
     K = K_dense(sus.pos, sus.body_off, sus.q)
     cf = sla.cho_factor(M, lower=True)
     MinvK = sla.cho_solve(cf, K)
@@ -236,6 +252,9 @@ def dense_solve(sus, FT, slip=None):
 def body_mobility(sus) -> np.ndarray:
     """Dense body mobility N = (K^T M^-1 K)^-1 (6N x 6N), eq:BodyMob."""
     M = assemble(sus.pos, sus.a, sus.eta, sus.wall)
+    d3 = _shift3(sus)
+    if d3 is not None:
+        M[np.diag_indices_from(M)] += d3
     K = K_dense(sus.pos, sus.body_off, sus.q)
     MinvK = sla.cho_solve(sla.cho_factor(M, lower=True), K)
     return np.linalg.inv(K.T @ MinvK)
@@ -255,10 +274,13 @@ class BlockPreconditioner:
         self.sus = sus
         self.blocks = []
         off = sus.body_off
+        d3 = _shift3(sus)
         for p in range(sus.n_bodies):
             s, e = off[p], off[p + 1]
             pos = sus.pos[s:e]
             Mpp = assemble(pos, sus.a, sus.eta, sus.wall)
+            if d3 is not None:
+                Mpp[np.diag_indices_from(Mpp)] += d3[3 * s:3 * e]
             Kp = K_dense(pos, np.array([0, e - s]), sus.q[p:p + 1])
             cf = sla.cho_factor(Mpp, lower=True)
             MinvK = sla.cho_solve(cf, Kp)
@@ -287,9 +309,9 @@ class ShapePreconditioner:
     (Sec. 2.2.2, after eq:saddle_M_precon: the free-space RPY block of a body
     is its reference configuration's, rotated; Sec. 5.4: the same blocks used
     for a wall problem give the approximate preconditioner that neglects the
-    boundary).  Shape k's saddle block [M_ref -K_ref; -K_ref^T 0] is formed
-    in free space from its body-frame blob positions (tracking point at the
-    origin).  For body p with rotation R_p (from its quaternion), the blob
+    boundary; permeability shifts are left out as well).  Shape k's saddle
+    block [M_ref -K_ref; -K_ref^T 0] is formed in free space from its
+    body-frame blob positions (tracking point at the origin).  For body p with rotation R_p (from its quaternion), the blob
     velocities, force and torque of the input are rotated into the body
     frame (R_p^T), the shape's block is solved, and lambda, u and omega are
     rotated back (R_p)."""

@@ -45,7 +45,8 @@ class RmbError(RuntimeError):
 class rmb_system(ctypes.Structure):
     _fields_ = [("n_blobs", ctypes.c_int64), ("n_bodies", ctypes.c_int64),
                 ("pos", ctypes.c_void_p), ("body_off", ctypes.c_void_p), ("q", ctypes.c_void_p),
-                ("a", ctypes.c_double), ("eta", ctypes.c_double), ("geometry", ctypes.c_int32)]
+                ("a", ctypes.c_double), ("eta", ctypes.c_double), ("geometry", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("blob_shift", ctypes.c_void_p)]
 
 
 class rmb_shapes(ctypes.Structure):
@@ -214,9 +215,12 @@ class System:
     """Holds the tensors of one suspension and its rmb_system struct."""
 
     def __init__(self, pos: torch.Tensor, a: float, eta: float = 1.0, wall: bool = False,
-                 body_off=None, q: torch.Tensor = None):
+                 body_off=None, q: torch.Tensor = None, blob_shift: torch.Tensor = None):
+        """blob_shift: optional (Nb,) device tensor of permeability shifts
+        d_i = kappa_p / (eta dV_i) added to the diagonal of M."""
         self.pos = pos
         self.q = q
+        self.blob_shift = blob_shift
         self.a, self.eta, self.wall = float(a), float(eta), bool(wall)
         self.body_off = None if body_off is None else np.ascontiguousarray(body_off, dtype=np.int64)
         n_b = 0 if self.body_off is None else len(self.body_off) - 1
@@ -225,13 +229,17 @@ class System:
         self.c = rmb_system(self.n_blobs, n_b, _dev(pos, "pos", (self.n_blobs, 3)).value,
                             None if self.body_off is None else self.body_off.ctypes.data,
                             None if q is None else _dev(q, "q", (n_b, 3)).value,
-                            self.a, self.eta, GEOM_WALL if self.wall else GEOM_FREE)
+                            self.a, self.eta, GEOM_WALL if self.wall else GEOM_FREE, 0,
+                            None if blob_shift is None else _dev(blob_shift, "blob_shift", (self.n_blobs,)).value)
 
     @classmethod
     def from_suspension(cls, sus, device="cuda"):
         pos = torch.as_tensor(sus.pos, dtype=torch.float64, device=device).contiguous()
         q = torch.as_tensor(sus.q, dtype=torch.float64, device=device).contiguous()
-        return cls(pos, sus.a, sus.eta, sus.wall, sus.body_off, q)
+        shift = getattr(sus, "blob_shift", None)
+        if shift is not None:
+            shift = torch.as_tensor(shift, dtype=torch.float64, device=device).contiguous()
+        return cls(pos, sus.a, sus.eta, sus.wall, sus.body_off, q, shift)
 
 
 def _prec(p):

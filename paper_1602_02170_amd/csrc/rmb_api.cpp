@@ -97,11 +97,13 @@ rmb_status check_positions(rmb_ctx ctx, const rmb_system *sys, int *flag_dev, hi
     int *h = nullptr;
     RMB_TRY(pinned(ctx, sizeof(int), (void **)&h));
     RMB_HIP(ctx, hipMemsetAsync(flag_dev, 0, sizeof(int), s));
-    RMB_HIP(ctx, launch_validate_positions(sys->pos, sys->n_blobs, sys->geometry == RMB_GEOM_WALL, flag_dev, s));
+    RMB_HIP(ctx, launch_validate_positions(sys->pos, sys->n_blobs, sys->geometry == RMB_GEOM_WALL, sys->blob_shift,
+                                           flag_dev, s));
     RMB_HIP(ctx, hipMemcpyAsync(h, flag_dev, sizeof(int), hipMemcpyDeviceToHost, s));
     RMB_HIP(ctx, hipStreamSynchronize(s));
     if (*h & 1) return fail(ctx, RMB_EINVAL, "non-finite blob position");
     if (*h & 2) return fail(ctx, RMB_EINVAL, "a blob has z <= 0 in wall geometry");
+    if (*h & 32) return fail(ctx, RMB_EINVAL, "blob_shift must be finite and >= 0");
     return RMB_OK;
 }
 
@@ -298,6 +300,7 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
         RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
         RMB_TRY(sym_launch(ctx, precision, wall, J.B, (const SymJob *)(base + off_job), 1, tiles, s));
         RMB_HIP(ctx, launch_sym_reduce((const SymJob *)(base + off_job), 1, sym_reduce_groups(nb), s));
+        RMB_HIP(ctx, launch_add_shift(sys->blob_shift, lambda, nb, vel, s));
         return RMB_OK;
     }
     PairJob J;
@@ -321,6 +324,7 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     RMB_TRY(pair_launch(ctx, precision, wall, (const PairJob *)(base + off_job), 1,
                         (int64_t)J.n_tblock * J.n_split, s));
     RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, nb, pref, vel, s));
+    RMB_HIP(ctx, launch_add_shift(sys->blob_shift, lambda, nb, vel, s));
     return RMB_OK;
 }
 
@@ -363,6 +367,7 @@ rmb_status rmb_flow_field(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
     rmb_system tsys = *sys;
     tsys.pos = targets;
     tsys.n_blobs = n_targets;
+    tsys.blob_shift = nullptr;
     {
         const rmb_status st = check_positions(ctx, &tsys, flag, s);
         if (st != RMB_OK) return fail(ctx, st, "target points: %s", rmb_last_error(ctx));

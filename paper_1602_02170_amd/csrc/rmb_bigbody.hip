@@ -86,8 +86,11 @@ __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__re
             const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
             double B[9];
             pair_block_f64(a_i, a_j, it.w.a, it.w.wall != 0, B);
+            // permeable bodies: d_i on the diagonal (eq:permeable_slip)
+            const double d = (i == j && it.w.shift) ? as_global(it.w.shift)[it.w.blob0 + i] : 0.0;
             for (int p = 0; p < 3; ++p)
-                for (int q = 0; q < 3; ++q) tile[3 * jl + q][3 * il + p] = it.w.pref * B[3 * p + q];
+                for (int q = 0; q < 3; ++q)
+                    tile[3 * jl + q][3 * il + p] = it.w.pref * B[3 * p + q] + (p == q ? d : 0.0);
         }
         __syncthreads();
         const int r0 = E * I, c0 = E * J;

@@ -22,6 +22,7 @@ struct BodyWork {
     int32_t pad;
     double a, pref;     // blob radius, 1/(6 pi eta a)
     int *flag;          // build status of the body's system (bits 4: not SPD, 8: singular)
+    const double *shift;  // build only: the system's permeability shifts d (indexed by blob) or NULL
     const double *rot;  // apply only: NULL, or the body's rotation R (3 x 3, row-major) when the
                         // factor is that of a shared reference shape; the body's block is then
                         // R~ P_ref^-1 R~^T (R~ = R on every 3-vector)
@@ -70,6 +71,7 @@ struct SaddleJob {
     const double *partial;    // [n_split][nb][3] pair sums
     const double *x;          // input [lambda; U] (only U read for blob rows, lambda for body rows)
     const double *b;          // NULL: y = A x; else y = b - A x
+    const double *shift;      // permeability shifts d [nb] (M + diag(d)) or NULL
     double *y;
     int64_t nb;
     int64_t blk_begin;        // first blob-row workgroup of this system

@@ -41,8 +41,11 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
         double B[9];
         const double a_i[3] = {ri[0], ri[1], ri[2]}, a_j[3] = {rj[0], rj[1], rj[2]};
         pair_block_f64(a_i, a_j, it.a, it.wall != 0, B);
+        // permeable bodies: d_i on the diagonal (eq:permeable_slip)
+        const double d = (i == j && it.shift) ? as_global(it.shift)[it.blob0 + i] : 0.0;
         for (int p = 0; p < 3; ++p)
-            for (int q = 0; q < 3; ++q) A[(3 * i + p) * m + 3 * j + q] = it.pref * B[3 * p + q];
+            for (int q = 0; q < 3; ++q)
+                A[(3 * i + p) * m + 3 * j + q] = it.pref * B[3 * p + q] + (p == q ? d : 0.0);
     }
     __syncthreads();
 
@@ -336,8 +339,9 @@ __global__ void saddle_blob_kernel(const SaddleJob *__restrict__ jobs, int32_t n
     const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1], as_global(J.pos)[3 * i + 2] - q[2]};
     const double ku[3] = {U[0] + U[4] * d[2] - U[5] * d[1], U[1] + U[5] * d[0] - U[3] * d[2],
                           U[2] + U[3] * d[1] - U[4] * d[0]};
+    const double shift = J.shift ? as_global(J.shift)[i] : 0.0;
     for (int c = 0; c < 3; ++c) {
-        const double y = J.pref * v[c] - ku[c];
+        const double y = J.pref * v[c] + shift * as_global(J.x)[3 * i + c] - ku[c];
         as_global(J.y)[3 * i + c] = J.b ? as_global(J.b)[3 * i + c] - y : y;
     }
 }

@@ -139,9 +139,12 @@ hipError_t launch_pair_tiles(int precision, bool wall, const PairJob *jobs, int3
 // v[i] = pref * sum_s partial[s][i]
 hipError_t launch_reduce_partials(const double *partial, int32_t n_split, int64_t nb, double pref,
                                   double *v, hipStream_t s);
-// flag |= 1 for a non-finite coordinate, |= 2 for z <= 0 when wall != 0
-hipError_t launch_validate_positions(const double *pos, int64_t nb, int wall, int *flag,
+// flag |= 1 for a non-finite coordinate, |= 2 for z <= 0 when wall != 0,
+// |= 32 for a permeability shift (if given) that is negative or not finite
+hipError_t launch_validate_positions(const double *pos, int64_t nb, int wall, const double *shift, int *flag,
                                      hipStream_t s);
+// v_i += shift_i lambda_i for every blob (no-op when shift is NULL)
+hipError_t launch_add_shift(const double *shift, const double *lam, int64_t nb, double *v, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // device memory

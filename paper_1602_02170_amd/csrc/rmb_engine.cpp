@@ -83,6 +83,7 @@ static void body_items(const rmb_system &sys, const int64_t *off, double *factor
         b.n_blobs = (int32_t)(off[p + 1] - off[p]);
         b.body = (int32_t)p;
         b.wall = sys.geometry == RMB_GEOM_WALL;
+        b.shift = sys.blob_shift;
         b.a = sys.a;
         b.pref = pref;
         b.flag = flag;
@@ -580,6 +581,7 @@ struct Engine {
             sj.partial = J->sym ? J->vel : J->partial;
             sj.x = xin;
             sj.b = is_iter ? nullptr : J->b;
+            sj.shift = J->sys.blob_shift;
             sj.y = J->w;
             sj.nb = J->nb;
             sj.blk_begin = wg_sd_blob;
@@ -667,7 +669,8 @@ struct Engine {
         for (size_t i = 0; i < setup.size(); ++i) {
             Job *J = setup[i];
             RMB_HIP(ctx, hipMemsetAsync(flag_d(J), 0, sizeof(int), s));
-            RMB_HIP(ctx, launch_validate_positions(J->sys.pos, J->nb, J->sys.geometry == RMB_GEOM_WALL, flag_d(J), s));
+            RMB_HIP(ctx, launch_validate_positions(J->sys.pos, J->nb, J->sys.geometry == RMB_GEOM_WALL,
+                                                   J->sys.blob_shift, flag_d(J), s));
             RMB_HIP(ctx, hipMemcpyAsync(J->off_d, D(o_off[i]), J->off.size() * 8, hipMemcpyDeviceToDevice, s));
             if (!J->pc && J->n_small)
                 RMB_HIP(ctx, hipMemcpyAsync(J->items_d, D(o_items[i]), J->n_small * sizeof(BodyWork),
@@ -722,6 +725,7 @@ struct Engine {
         for (Job *J : setup) {
             const int f = flag_h(J);
             if (f & 3) { finish_job(J, RMB_EINVAL, (f & 1) ? "non-finite blob position" : "a blob has z <= 0 in wall geometry"); continue; }
+            if (f & 32) { finish_job(J, RMB_EINVAL, "blob_shift must be finite and >= 0"); continue; }
             if (f & 4) { finish_job(J, RMB_ENOTSPD, "a body's mobility block is not positive definite"); continue; }
             if (f & 8) { finish_job(J, RMB_ENOTSPD, "a body's K^T M^-1 K block is singular"); continue; }
             J->bnorm = hcol_h(J)[0];
@@ -958,6 +962,7 @@ rmb_status rmb_precond_factor_shapes(rmb_ctx ctx, const rmb_system *sys, const r
     ref.body_off = so;
     ref.q = q0_d;
     ref.geometry = RMB_GEOM_FREE;
+    ref.blob_shift = nullptr;
     BodyLists sl;
     body_items(ref, so, pc->factor, pc->flag_d, sl);
     // per body: the shape's factor, the body's blob range and rotation

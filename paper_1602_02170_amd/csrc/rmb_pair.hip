@@ -425,21 +425,41 @@ hipError_t launch_reduce_partials(const double *partial, int32_t n_split, int64_
 }
 
 __global__ void validate_positions_kernel(const double *__restrict__ pos, int64_t nb, int wall,
-                                          int *__restrict__ flag) {
+                                          const double *__restrict__ shift, int *__restrict__ flag) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nb) return;
     double x = pos[3 * i], y = pos[3 * i + 1], z = pos[3 * i + 2];
     int f = 0;
     if (!isfinite(x) || !isfinite(y) || !isfinite(z)) f |= 1;
     if (wall && !(z > 0.0)) f |= 2;
+    if (shift) {
+        const double d = shift[i];
+        if (!(d >= 0.0) || !isfinite(d)) f |= 32;
+    }
     if (f) atomicOr(flag, f);
 }
 
-hipError_t launch_validate_positions(const double *pos, int64_t nb, int wall, int *flag,
+hipError_t launch_validate_positions(const double *pos, int64_t nb, int wall, const double *shift, int *flag,
                                      hipStream_t s) {
     if (nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(validate_positions_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0,
-                       s, pos, nb, wall, flag);
+                       s, pos, nb, wall, shift, flag);
+    return hipGetLastError();
+}
+
+// v_i += d_i lambda_i: the permeable-body slip -d_i lambda_i moved to the
+// operator side (eq:permeable_slip), i.e. d on the diagonal of M.
+__global__ void add_shift_kernel(const double *__restrict__ shift, const double *__restrict__ lam, int64_t nb,
+                                 double *__restrict__ v) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 3 * nb) return;
+    v[e] += shift[e / 3] * lam[e];
+}
+
+hipError_t launch_add_shift(const double *shift, const double *lam, int64_t nb, double *v, hipStream_t s) {
+    if (nb <= 0 || !shift) return hipSuccess;
+    hipLaunchKernelGGL(add_shift_kernel, dim3((unsigned)((3 * nb + 255) / 256)), dim3(256), 0, s, shift, lam, nb,
+                       v);
     return hipGetLastError();
 }
 

@@ -154,6 +154,8 @@ class Suspension:
     slip     (Nb, 3) float64  active slip (or None for passive bodies)
     tol                       requested relative residual of the solve
     quat     (N, 4)           orientations used to place the bodies
+    blob_shift (Nb,)          permeable bodies: kappa_p / (eta dV_i) per blob
+                              (or None for impermeable bodies)
     """
     pos: np.ndarray
     body_off: np.ndarray
@@ -166,6 +168,7 @@ class Suspension:
     tol: float = 1e-8
     quat: Optional[np.ndarray] = None
     name: str = ""
+    blob_shift: Optional[np.ndarray] = None
 
     @property
     def n_blobs(self) -> int:
