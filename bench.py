@@ -301,6 +301,30 @@ def shared_leg(rmb, torch, ctx, S, reps=5):
     return res
 
 
+def resistance_leg(rmb, torch, ctx, S, reps=3):
+    """Resistance problem (M lambda = K U, F = K^T lambda) on the
+    1000-boomerang suspension with seeded random body velocities, FP32 pairs
+    with FP64 refinement to 1e-8; the mobility solve's iteration count on the
+    same system for comparison."""
+    sus = S.boomerangs_wall()
+    sysd = rmb.System.from_suspension(sus)
+    U = torch.tensor(np.random.default_rng(8).standard_normal((sus.n_bodies, 6)), dtype=torch.float64,
+                     device="cuda")
+    rmb.solve_resistance(ctx, sysd, U, tol=1e-8, precision="fp32")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for _ in range(reps):
+        _, _, info = rmb.solve_resistance(ctx, sysd, U, tol=1e-8, precision="fp32")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t) / reps * 1e3
+    res = {"workload": "resistance problem, 1000 x 15-blob boomerangs, random U, FP32 pairs + FP64 refinement "
+                       "to 1e-8", "ms_per_solve": ms, "iterations": info["iterations"],
+           "fp32_products": info["matvecs_fp32"], "fp64_products": info["matvecs_fp64"],
+           "rel_residual": info["rel_residual"], "status": info["status"]}
+    log(f"  resistance solve: {ms:.2f} ms, {info['iterations']} iterations")
+    return res
+
+
 def serving_leg(rmb, torch, ctx, S, n_req, rate):
     t_gen = time.perf_counter()
     reqs = [S.mixed_wall_request(i) for i in range(n_req)]
@@ -489,6 +513,7 @@ def main():
         log(f"  plain FP64 solve: {ms64:.2f} ms/solve ({infos64[-1]['iterations']} iterations)")
         if not args.no_matvec:
             line["matvec"] = matvec_leg(rmb, torch, ctx, S)
+        line["resistance"] = resistance_leg(rmb, torch, ctx, S)
         if not args.no_flow:
             line["flow_field"] = flow_leg(rmb, torch, ctx, S)
         if not args.no_factor:

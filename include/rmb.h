@@ -309,6 +309,23 @@ rmb_status rmb_solve_mobility(rmb_ctx ctx, const rmb_system *sys, const rmb_prec
                               const double *slip, double *U, double *lambda, const rmb_solve_opts *opts,
                               rmb_solve_info *info, rmb_stream stream);
 
+/* Resistance problem (eq:resistance_problem): given body velocities U
+ * (device [N][6]: u then omega) and optional slip (device [Nb][3] or NULL),
+ * solves M lambda = K U + slip (M + diag(d) for permeable bodies) and
+ * returns F = K^T lambda (device [N][6]: force, then torque about q_p) and
+ * lambda (device [Nb][3]).  Right-preconditioned GMRES from lambda = 0 with
+ * the block-diagonal preconditioner M_pp^-1 (the same per-body factors as
+ * the mobility solve; `pc` from rmb_precond_factor or
+ * rmb_precond_factor_shapes for this system, or NULL); opts as for the
+ * mobility solve, the tolerance applying to ||K U + slip - M lambda|| /
+ * ||K U + slip||.  Unlike the mobility problem, its iteration count grows
+ * with the linear extent of the suspension (Sec. 4.4).  Errors:
+ * RMB_EINVAL, RMB_ENOTSPD (a body's M_pp not positive definite),
+ * RMB_ENOCONV, RMB_ENOMEM, RMB_EDEVICE.  Blocks until complete. */
+rmb_status rmb_solve_resistance(rmb_ctx ctx, const rmb_system *sys, const rmb_precond pc, const double *U,
+                                const double *slip, double *F, double *lambda, const rmb_solve_opts *opts,
+                                rmb_solve_info *info, rmb_stream stream);
+
 /* `count` independent mobility problems solved together: every active
  * system advances one Arnoldi step per batched launch, and systems are
  * admitted as device memory frees up.  Arrays of length `count` (host

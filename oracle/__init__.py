@@ -22,6 +22,9 @@ definitions, with library primitives (numpy/scipy dense solves) as steps.
   ShapePreconditioner        -> the same with one free-space block per
                                 reference shape, rotated per body (Sec. 2.2.2
                                 after eq:saddle_M_precon; Sec. 5.4)
+  resistance_dense,          -> resistance problem M lambda = K U + slip,
+  solve_resistance              F = K^T lambda (eq:resistance_problem), dense
+                                and by GMRES with the blocks M_pp^-1
   gmres                      -> right-preconditioned GMRES (Sec. 2.2.2; right
                                 preconditioning so the monitored residual is
                                 the true one, Sec. 3.3)
@@ -249,6 +252,21 @@ def dense_solve(sus, FT, slip=None):
     return U.reshape(-1, 6), lam.reshape(-1, 3)
 
 
+def resistance_dense(sus, U, slip=None):
+    """Resistance problem (eq:resistance_problem) by a dense Cholesky solve:
+    lambda = M^-1 (K U + slip), F = K^T lambda.  Returns (F (N x 6),
+    lambda (Nb x 3))."""
+    M = assemble(sus.pos, sus.a, sus.eta, sus.wall)
+    d3 = _shift3(sus)
+    if d3 is not None:
+        M[np.diag_indices_from(M)] += d3
+    rhs_ = K_apply(sus.pos, sus.body_off, sus.q, U).ravel()
+    if slip is not None:
+        rhs_ = rhs_ + np.asarray(slip, dtype=np.float64).ravel()
+    lam = sla.cho_solve(sla.cho_factor(M, lower=True), rhs_).reshape(-1, 3)
+    return KT_apply(sus.pos, sus.body_off, sus.q, lam), lam
+
+
 def body_mobility(sus) -> np.ndarray:
     """Dense body mobility N = (K^T M^-1 K)^-1 (6N x 6N), eq:BodyMob."""
     M = assemble(sus.pos, sus.a, sus.eta, sus.wall)
@@ -303,6 +321,14 @@ class BlockPreconditioner:
             U[p] = Up
         return np.concatenate([lam.ravel(), U.ravel()])
 
+    def apply_resistance(self, v) -> np.ndarray:
+        """M_pp^-1 s per body (preconditioner of the resistance problem)."""
+        sv = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+        out = np.empty_like(sv)
+        for (s, e, cf, Kp, MinvK, Np) in self.blocks:
+            out[s:e] = sla.cho_solve(cf, sv[s:e].ravel()).reshape(-1, 3)
+        return out.ravel()
+
 
 class ShapePreconditioner:
     """Block-diagonal preconditioner from one block per reference shape
@@ -347,6 +373,20 @@ class ShapePreconditioner:
             U[p, 0:3] = x[-6:-3] @ R.T
             U[p, 3:6] = x[-3:] @ R.T
         return np.concatenate([lam.ravel(), U.ravel()])
+
+    def apply_resistance(self, v) -> np.ndarray:
+        """Per body R_p M_ref^-1 R_p^T s (the shape's mobility block alone)."""
+        sus = self.sus
+        sv = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+        out = np.empty_like(sv)
+        off = sus.body_off
+        for p in range(sus.n_bodies):
+            s, e = off[p], off[p + 1]
+            m = 3 * (e - s)
+            R = self.R[p]
+            x = np.linalg.solve(self.blocks[self.body_shape[p]][:m, :m], (sv[s:e] @ R).ravel())
+            out[s:e] = x.reshape(-1, 3) @ R.T
+        return out.ravel()
 
 
 # ----------------------------------------------------------------------------
@@ -403,6 +443,27 @@ def gmres(apply_A, apply_Pinv, b, tol=1e-12, restart=100, maxiter=1000):
                 break
         y = sla.solve_triangular(H[:k_used, :k_used], g[:k_used])
         x = x + apply_Pinv(V[:k_used].T @ y)
+
+
+def solve_resistance(sus, U, slip=None, tol=1e-12, restart=100, maxiter=1000, precond=None):
+    """Resistance problem by right-preconditioned GMRES on M lambda = K U +
+    slip with the block-diagonal M_pp^-1 (or `precond`'s apply_resistance),
+    then F = K^T lambda.  Returns (F, lambda, info)."""
+    t0 = time.perf_counter()
+    P = BlockPreconditioner(sus) if precond is None else precond
+    b = K_apply(sus.pos, sus.body_off, sus.q, U).ravel()
+    if slip is not None:
+        b = b + np.asarray(slip, dtype=np.float64).ravel()
+    d3 = _shift3(sus)
+
+    def apply_M(x):
+        y = matvec(sus.pos, x.reshape(-1, 3), sus.a, sus.eta, sus.wall).ravel()
+        return y if d3 is None else y + d3 * x
+
+    lam, it, hist = gmres(apply_M, P.apply_resistance, b, tol, restart, maxiter)
+    lam = lam.reshape(-1, 3)
+    return KT_apply(sus.pos, sus.body_off, sus.q, lam), lam, {
+        "iterations": it, "history": hist, "seconds": time.perf_counter() - t0}
 
 
 def solve_mobility(sus, FT, slip=None, tol=1e-12, restart=100, maxiter=1000, precond=None):

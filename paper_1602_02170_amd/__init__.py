@@ -32,7 +32,8 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_solve_mobility", "rmb_solve_batch", "rmb_server_create", "rmb_server_submit",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
            "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan",
-           "rmb_flow_field", "rmb_precond_factor_shapes", "rmb_precond_set_orientations"]
+           "rmb_flow_field", "rmb_precond_factor_shapes", "rmb_precond_set_orientations",
+           "rmb_solve_resistance"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -104,6 +105,7 @@ def library(path: str = LIB_PATH):
         L.rmb_precond_destroy.argtypes = [vp]
         L.rmb_precond_destroy.restype = None
         L.rmb_solve_mobility.argtypes = [vp, sysp, vp, vp, vp, vp, vp, optp, infop, vp]
+        L.rmb_solve_resistance.argtypes = [vp, sysp, vp, vp, vp, vp, vp, optp, infop, vp]
         L.rmb_solve_batch.argtypes = [vp, i32, sysp, ctypes.POINTER(vp), ctypes.POINTER(vp),
                                       ctypes.POINTER(vp), ctypes.POINTER(vp), optp, infop, vp]
         L.rmb_server_create.argtypes = [vp, i32, vp, ctypes.POINTER(vp)]
@@ -375,6 +377,25 @@ def solve_mobility(ctx: Context, system: System, FT: torch.Tensor, slip: torch.T
     if st != RMB_OK and (st != RMB_ENOCONV or raise_on_noconv):
         ctx.check(st)
     return U, lam, info.as_dict()
+
+
+def solve_resistance(ctx: Context, system: System, U: torch.Tensor, slip: torch.Tensor = None,
+                     precond: Precond = None, stream=None, raise_on_noconv=False, **opts):
+    """Resistance problem (eq:resistance_problem): M lambda = K U + slip,
+    F = K^T lambda.  Returns (F (N, 6), lambda (Nb, 3), info dict)."""
+    nb, N = system.n_blobs, system.n_bodies
+    Up = _dev(U, "U", (N, 6))
+    sp = _vec(slip, "slip", nb)
+    F = torch.empty((N, 6), dtype=torch.float64, device=U.device)
+    lam = torch.empty((nb, 3), dtype=torch.float64, device=U.device)
+    o = solve_opts(**opts)
+    info = rmb_solve_info()
+    st = ctx.lib.rmb_solve_resistance(ctx.h, ctypes.byref(system.c), precond.h if precond else None, Up, sp,
+                                      ctypes.c_void_p(F.data_ptr()), ctypes.c_void_p(lam.data_ptr()),
+                                      ctypes.byref(o), ctypes.byref(info), _stream(stream))
+    if st != RMB_OK and (st != RMB_ENOCONV or raise_on_noconv):
+        ctx.check(st)
+    return F, lam, info.as_dict()
 
 
 def solve_batch(ctx: Context, systems, FTs, slips=None, stream=None, **opts):

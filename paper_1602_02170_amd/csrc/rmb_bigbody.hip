@@ -448,7 +448,8 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     const gmem<const double> L = as_global(it.w.factor);
     const double *Y = big_Y(it), *Dinv = big_Dinv(it), *Sc = big_Sc(it);
     double *X = lds;  // Mp x 8
-    const int64_t b3 = 3 * it.w.blob0, u6 = J.nb3 + 6 * (int64_t)it.w.body;
+    const bool resist = J.mode != 0;  // resistance problem: lambda = M_pp^-1 s only
+    const int64_t b3 = 3 * it.w.blob0, u6 = resist ? 0 : J.nb3 + 6 * (int64_t)it.w.body;
     // with a shared reference-shape factor, the right-hand sides are taken
     // into the body frame (R^T on every 3-vector) and the results back (R)
     const gmem<const double> Rot = as_global(it.w.rot);
@@ -471,67 +472,69 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     }
     __syncthreads();
     forward_rl<NB, R>(L, as_global(Dinv), Mp, X, Dj, T);
-    // g = F - Y^T t, F = -bottom: thread (c, qp) sums rows l = qp (mod QP)
-    // for k = 0..5, then the QP partials are added in order
-    double *part = Dj;  // [QP][R][6]
-    if (tid < QP * R) {
-        const int c = tid % R, qp = tid / R;
-        double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (!resist) {
+        // g = F - Y^T t, F = -bottom: thread (c, qp) sums rows l = qp (mod QP)
+        // for k = 0..5, then the QP partials are added in order
+        double *part = Dj;  // [QP][R][6]
+        if (tid < QP * R) {
+            const int c = tid % R, qp = tid / R;
+            double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-        for (int l = qp; l < Mp; l += QP) {
-            const double x = X[l * R + c];
+            for (int l = qp; l < Mp; l += QP) {
+                const double x = X[l * R + c];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc[k] += as_global(Y)[l * 6 + k] * x;
+                for (int k = 0; k < 6; ++k) acc[k] += as_global(Y)[l * 6 + k] * x;
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) part[(qp * R + c) * 6 + k] = acc[k];
         }
-#pragma unroll
-        for (int k = 0; k < 6; ++k) part[(qp * R + c) * 6 + k] = acc[k];
-    }
-    __syncthreads();
-    if (tid < R * 6) {
-        const int c = tid / 6, k = tid % 6;
-        double acc = 0.0;
-        for (int qp = 0; qp < QP; ++qp) acc += part[(qp * R + c) * 6 + k];
-        double bot = 0.0;
-        if (c < nr) {
-            const gmem<const double> x = as_global(J.in) + (int64_t)(r0 + c) * J.ld + u6;
-            if (it.w.rot) {
-                const int b = k - k % 3, kk = k % 3;
-                bot = Rot[kk] * x[b] + Rot[3 + kk] * x[b + 1] + Rot[6 + kk] * x[b + 2];
-            } else {
-                bot = x[k];
+        __syncthreads();
+        if (tid < R * 6) {
+            const int c = tid / 6, k = tid % 6;
+            double acc = 0.0;
+            for (int qp = 0; qp < QP; ++qp) acc += part[(qp * R + c) * 6 + k];
+            double bot = 0.0;
+            if (c < nr) {
+                const gmem<const double> x = as_global(J.in) + (int64_t)(r0 + c) * J.ld + u6;
+                if (it.w.rot) {
+                    const int b = k - k % 3, kk = k % 3;
+                    bot = Rot[kk] * x[b] + Rot[3 + kk] * x[b + 1] + Rot[6 + kk] * x[b + 2];
+                } else {
+                    bot = x[k];
+                }
+            }
+            g[c][k] = c < nr ? -bot - acc : 0.0;
+        }
+        __syncthreads();
+        if (tid < nr) {
+            double u[6];
+            double *gg = g[tid];
+            for (int i = 0; i < 6; ++i) {
+                double v = gg[i];
+                for (int k = 0; k < i; ++k) v -= as_global(Sc)[i * 6 + k] * u[k];
+                u[i] = v / as_global(Sc)[i * 6 + i];
+            }
+            for (int i = 5; i >= 0; --i) {
+                double v = u[i];
+                for (int k = i + 1; k < 6; ++k) v -= as_global(Sc)[k * 6 + i] * gg[k];
+                gg[i] = v / as_global(Sc)[i * 6 + i];
             }
         }
-        g[c][k] = c < nr ? -bot - acc : 0.0;
-    }
-    __syncthreads();
-    if (tid < nr) {
-        double u[6];
-        double *gg = g[tid];
-        for (int i = 0; i < 6; ++i) {
-            double v = gg[i];
-            for (int k = 0; k < i; ++k) v -= as_global(Sc)[i * 6 + k] * u[k];
-            u[i] = v / as_global(Sc)[i * 6 + i];
-        }
-        for (int i = 5; i >= 0; --i) {
-            double v = u[i];
-            for (int k = i + 1; k < 6; ++k) v -= as_global(Sc)[k * 6 + i] * gg[k];
-            gg[i] = v / as_global(Sc)[i * 6 + i];
-        }
-    }
-    __syncthreads();
-    for (int row = tid; row < Mp; row += 256) {
-        double yk[6];
+        __syncthreads();
+        for (int row = tid; row < Mp; row += 256) {
+            double yk[6];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) yk[k] = as_global(Y)[row * 6 + k];
+            for (int k = 0; k < 6; ++k) yk[k] = as_global(Y)[row * 6 + k];
 #pragma unroll
-        for (int c = 0; c < R; ++c) {
-            double acc = X[row * R + c];
+            for (int c = 0; c < R; ++c) {
+                double acc = X[row * R + c];
 #pragma unroll
-            for (int k = 0; k < 6; ++k) acc += yk[k] * g[c][k];
-            X[row * R + c] = acc;
+                for (int k = 0; k < 6; ++k) acc += yk[k] * g[c][k];
+                X[row * R + c] = acc;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
     backward_rl<NB, R>(L, as_global(Dinv), Mp, X, Dj, T);
     if (it.w.rot) {
         // backward_rl ends with a barrier, so all of X is final here
@@ -543,7 +546,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
                     Rot[3 * k] * X[b * R + c] + Rot[3 * k + 1] * X[(b + 1) * R + c] + Rot[3 * k + 2] * X[(b + 2) * R + c];
             }
         }
-        if (tid < R * 6) {
+        if (tid < R * 6 && !resist) {
             const int c = tid / 6, k = tid % 6;
             const int b = k - k % 3, kk = k % 3;
             if (c < nr)
@@ -556,7 +559,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         const int row = e / R, c = e % R;
         if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];
     }
-    if (tid < R * 6) {
+    if (tid < R * 6 && !resist) {
         const int c = tid / 6, k = tid % 6;
         if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + u6 + k] = g[c][k];
     }

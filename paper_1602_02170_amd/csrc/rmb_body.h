@@ -51,6 +51,8 @@ inline int64_t factor_doubles(int64_t n_blobs) {
 }
 
 // P^-1 applied to `nrhs` saddle vectors of one system (vector r at in + r*ld).
+// mode 1 (resistance problem): the vectors hold blob forces only and the
+// apply is lambda_p = M_pp^-1 s_p per body, with the same factors.
 struct PrecondApplyJob {
     const BodyWork *items;  // the system's bodies (BigBody records for the large-body kernel)
     const double *in;
@@ -60,6 +62,8 @@ struct PrecondApplyJob {
     int64_t wg_begin;       // first workgroup of this system in the launch
     int32_t n_items;
     int32_t nrhs;
+    int32_t mode;
+    int32_t pad;
 };
 
 // Saddle-point operator rows around a finished pair product.
@@ -77,7 +81,7 @@ struct SaddleJob {
     int64_t blk_begin;        // first blob-row workgroup of this system
     int64_t body_begin;       // first body-row workgroup of this system
     int32_t n_split;
-    int32_t pad;
+    int32_t resist;           // 1: resistance operator y = (M + diag(d)) lambda, no K terms or body rows
     double pref;
 };
 
@@ -95,6 +99,14 @@ hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int
 // `panel`: the panel width (16 or 32) the bodies' factors were built with.
 hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
                                       int max_Mp, int panel, hipStream_t s);
+// Resistance problem (eq:resistance_problem): b_i = u_p + omega_p x (r_i - q_p)
+// + slip_i for blob i of body p (U device [N][6], slip [nb][3] or NULL).
+hipError_t launch_build_rhs_resist(const double *U, const double *slip, const double *pos, const double *q,
+                                   const int32_t *blob_body, int64_t nb, double *b, hipStream_t s);
+// F_p = K_p^T lambda = (sum_i lambda_i, sum_i (r_i - q_p) x lambda_i), [N][6].
+hipError_t launch_body_forces(const double *pos, const double *q, const int64_t *body_off, const double *lam,
+                              int64_t N, double *F, hipStream_t s);
+
 // Rotation matrices (row-major, 9 doubles per body) of N quaternions
 // (w, x, y, z), normalised on the fly; a zero or non-finite quaternion sets
 // bit 16 of *flag and yields the identity.

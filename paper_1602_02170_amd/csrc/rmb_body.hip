@@ -161,9 +161,11 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // K_p = R~ K_ref diag(R, R)^T.
 constexpr int kApplyThreads = 64;
 
+// With `resist` (resistance problem) only lambda = M_pp^-1 s is formed:
+// bot_in and U_out are not touched.
 __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gmem<const double> s_in,
                                                    const gmem<const double> bot_in, const gmem<double> lam_out,
-                                                   const gmem<double> U_out, double *lds, double *g) {
+                                                   const gmem<double> U_out, double *lds, double *g, bool resist) {
     const int m = 3 * it.n_blobs, tid = threadIdx.x;
     // the whole factor [Li | Y | S^-1] is staged in LDS, eight loads in
     // flight per thread, followed by the right-hand side
@@ -201,7 +203,7 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
     }
     __syncthreads();
     // g = F - Y^T t, F = -bottom
-    if (tid < 6) {
+    if (tid < 6 && !resist) {
         double acc = 0.0;
         for (int l = 0; l < m; ++l) acc += Y[l * 6 + tid] * t[l];
         double bot = bot_in[tid];
@@ -212,10 +214,11 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         g[tid] = -bot - acc;
     }
     __syncthreads();
-    // U = S^-1 g
+    // U = S^-1 g (U = 0 for the resistance problem)
     if (tid < 6) {
         double u = 0.0;
-        for (int k = 0; k < 6; ++k) u += Si[tid * 6 + k] * g[k];
+        if (!resist)
+            for (int k = 0; k < 6; ++k) u += Si[tid * 6 + k] * g[k];
         g[6 + tid] = u;
     }
     __syncthreads();
@@ -232,7 +235,7 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
             for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
             lam_out[r] = acc;
         }
-        if (tid < 6) U_out[tid] = g[6 + tid];
+        if (tid < 6 && !resist) U_out[tid] = g[6 + tid];
         return;
     }
     for (int r = tid; r < m; r += kApplyThreads) {
@@ -245,7 +248,7 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         const int b = e - e % 3, c = e % 3;
         lam_out[e] = R[3 * c] * t[b] + R[3 * c + 1] * t[b + 1] + R[3 * c + 2] * t[b + 2];
     }
-    if (tid < 6) {
+    if (tid < 6 && !resist) {
         const int b = 6 + tid - tid % 3, c = tid % 3;
         U_out[tid] = R[3 * c] * g[b] + R[3 * c + 1] * g[b + 1] + R[3 * c + 2] * g[b + 2];
     }
@@ -268,8 +271,70 @@ __global__ __launch_bounds__(kApplyThreads) void precond_apply_small_kernel(cons
     const gmem<const double> in = as_global(J.in + rhs * J.ld);
     gmem<double> out = as_global(J.out + rhs * J.ld);
     const int64_t b3 = 3 * it.blob0;
-    const int64_t u6 = J.nb3 + 6 * (int64_t)it.body;
-    precond_body_apply(it, in + b3, in + u6, out + b3, out + u6, lds, g);
+    const int64_t u6 = J.mode ? 0 : J.nb3 + 6 * (int64_t)it.body;
+    precond_body_apply(it, in + b3, in + u6, out + b3, out + u6, lds, g, J.mode != 0);
+}
+
+// ---------------------------------------------------------------------------
+// resistance problem: right-hand side K U + slip, and F = K^T lambda
+// ---------------------------------------------------------------------------
+
+__global__ void build_rhs_resist_kernel(const double *__restrict__ U, const double *__restrict__ slip,
+                                        const double *__restrict__ pos, const double *__restrict__ q,
+                                        const int32_t *__restrict__ blob_body, int64_t nb, double *__restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb) return;
+    const int64_t p = as_global(blob_body)[i];
+    const gmem<const double> u = as_global(U) + 6 * p, qp = as_global(q) + 3 * p, r = as_global(pos) + 3 * i;
+    const double d[3] = {r[0] - qp[0], r[1] - qp[1], r[2] - qp[2]};
+    double v[3] = {u[0] + u[4] * d[2] - u[5] * d[1], u[1] + u[5] * d[0] - u[3] * d[2],
+                   u[2] + u[3] * d[1] - u[4] * d[0]};
+    if (slip)
+        for (int c = 0; c < 3; ++c) v[c] += as_global(slip)[3 * i + c];
+    for (int c = 0; c < 3; ++c) as_global(b)[3 * i + c] = v[c];
+}
+
+hipError_t launch_build_rhs_resist(const double *U, const double *slip, const double *pos, const double *q,
+                                   const int32_t *blob_body, int64_t nb, double *b, hipStream_t s) {
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(build_rhs_resist_kernel, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s, U, slip, pos, q,
+                       blob_body, nb, b);
+    return hipGetLastError();
+}
+
+// One wave per body: force sum and torque about q_p, reduced across lanes
+// in a fixed order.
+__global__ void body_forces_kernel(const double *__restrict__ pos, const double *__restrict__ q,
+                                   const int64_t *__restrict__ body_off, const double *__restrict__ lam,
+                                   double *__restrict__ F) {
+    const int64_t p = blockIdx.x;
+    const int64_t b0 = as_global(body_off)[p], b1 = as_global(body_off)[p + 1];
+    const gmem<const double> qp = as_global(q) + 3 * p;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = b0 + threadIdx.x; i < b1; i += 64) {
+        const gmem<const double> l = as_global(lam) + 3 * i, r = as_global(pos) + 3 * i;
+        const double d[3] = {r[0] - qp[0], r[1] - qp[1], r[2] - qp[2]};
+        acc[0] += l[0];
+        acc[1] += l[1];
+        acc[2] += l[2];
+        acc[3] += d[1] * l[2] - d[2] * l[1];
+        acc[4] += d[2] * l[0] - d[0] * l[2];
+        acc[5] += d[0] * l[1] - d[1] * l[0];
+    }
+    for (int k = 0; k < 6; ++k) {
+        double v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[k] = v;
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 6; ++k) as_global(F)[6 * p + k] = acc[k];
+}
+
+hipError_t launch_body_forces(const double *pos, const double *q, const int64_t *body_off, const double *lam,
+                              int64_t N, double *F, hipStream_t s) {
+    if (N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(body_forces_kernel, dim3((unsigned)N), dim3(64), 0, s, pos, q, body_off, lam, F);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -333,12 +398,17 @@ __global__ void saddle_blob_kernel(const SaddleJob *__restrict__ jobs, int32_t n
         v[1] += p[1];
         v[2] += p[2];
     }
-    const int p = as_global(J.blob_body)[i];
-    const gmem<const double> U = as_global(J.x + n3 + 6 * (int64_t)p);
-    const gmem<const double> q = as_global(J.q + 3 * (int64_t)p);
-    const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1], as_global(J.pos)[3 * i + 2] - q[2]};
-    const double ku[3] = {U[0] + U[4] * d[2] - U[5] * d[1], U[1] + U[5] * d[0] - U[3] * d[2],
-                          U[2] + U[3] * d[1] - U[4] * d[0]};
+    double ku[3] = {0.0, 0.0, 0.0};
+    if (!J.resist) {
+        const int p = as_global(J.blob_body)[i];
+        const gmem<const double> U = as_global(J.x + n3 + 6 * (int64_t)p);
+        const gmem<const double> q = as_global(J.q + 3 * (int64_t)p);
+        const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1],
+                             as_global(J.pos)[3 * i + 2] - q[2]};
+        ku[0] = U[0] + U[4] * d[2] - U[5] * d[1];
+        ku[1] = U[1] + U[5] * d[0] - U[3] * d[2];
+        ku[2] = U[2] + U[3] * d[1] - U[4] * d[0];
+    }
     const double shift = J.shift ? as_global(J.shift)[i] : 0.0;
     for (int c = 0; c < 3; ++c) {
         const double y = J.pref * v[c] + shift * as_global(J.x)[3 * i + c] - ku[c];

@@ -176,8 +176,11 @@ struct Job {
     int64_t tag = 0;
     rmb_system sys{};
     std::vector<int64_t> off;
+    // mobility problem: FT in, U_out and lam_out out; resistance problem
+    // (resist): FT holds the body velocities U, U_out receives F = K^T lambda
     const double *FT = nullptr, *slip = nullptr;
     double *U_out = nullptr, *lam_out = nullptr;
+    bool resist = false;
     double tol = 1e-8, inner_tol = 1e-5;
     int prec = RMB_PREC_FP64, m = 100, max_iters = 1000;
     rmb_precond pc = nullptr;  // external factors (not owned) or null
@@ -325,9 +328,10 @@ struct Engine {
     }
 
     rmb_status submit(const rmb_system *sys, const double *FT, const double *slip, double *U, double *lam,
-                      const rmb_solve_opts *o, rmb_precond pc, int64_t tag, Job **out) {
+                      const rmb_solve_opts *o, rmb_precond pc, int64_t tag, Job **out, bool resist = false) {
         RMB_TRY(check_system(ctx, sys, true));
-        if (!FT || !U || !lam) return fail(ctx, RMB_EINVAL, "FT, U and lambda are required");
+        if (!FT || !U || !lam)
+            return fail(ctx, RMB_EINVAL, resist ? "U, F and lambda are required" : "FT, U and lambda are required");
         RMB_TRY(check_body_sizes(ctx, sys->body_off, sys->n_bodies));
         auto J = std::make_unique<Job>();
         J->tag = tag;
@@ -351,8 +355,9 @@ struct Engine {
                 return fail(ctx, RMB_EINVAL, "preconditioner was built for a different system");
             J->pc = pc;
         }
+        J->resist = resist;
         J->nb = sys->n_blobs, J->N = sys->n_bodies;
-        J->n = 3 * J->nb + 6 * J->N;
+        J->n = resist ? 3 * J->nb : 3 * J->nb + 6 * J->N;
         J->ldv = (J->n + 31) / 32 * 32;
         {
             int32_t ns = 0;
@@ -494,6 +499,7 @@ struct Engine {
             a.ld = J->n;
             a.nb3 = 3 * J->nb;
             a.nrhs = 1;
+            a.mode = J->resist ? 1 : 0;
             if (J->n_small) {
                 a.items = J->items_d;
                 a.wg_begin = wg_app;
@@ -587,10 +593,11 @@ struct Engine {
             sj.blk_begin = wg_sd_blob;
             sj.body_begin = wg_sd_body;
             sj.n_split = J->sym ? 1 : J->pj.n_split;
+            sj.resist = J->resist ? 1 : 0;
             sj.pref = J->sym ? 1.0 : mobility_prefactor(J->sys.a, J->sys.eta);
             sd.push_back(sj);
             wg_sd_blob += (J->nb + 255) / 256;
-            wg_sd_body += J->N;
+            wg_sd_body += J->resist ? 0 : J->N;
             if (f32) J->mv32++; else J->mv64++;
         }
 
@@ -679,7 +686,11 @@ struct Engine {
                 RMB_HIP(ctx, hipMemcpyAsync(J->bigs_d, D(o_bigs[i]), J->n_large * sizeof(BigBody),
                                             hipMemcpyDeviceToDevice, s));
             RMB_HIP(ctx, launch_blob_body(J->off_d, J->N, J->blob_body, s));
-            RMB_HIP(ctx, launch_build_rhs(J->FT, J->slip, J->nb, J->N, J->b, s));
+            if (J->resist)
+                RMB_HIP(ctx, launch_build_rhs_resist(J->FT, J->slip, J->sys.pos, J->sys.q, J->blob_body, J->nb, J->b,
+                                                     s));
+            else
+                RMB_HIP(ctx, launch_build_rhs(J->FT, J->slip, J->nb, J->N, J->b, s));
             RMB_HIP(ctx, hipMemsetAsync(J->x, 0, J->n * 8, s));
         }
         if (!build_items.empty())
@@ -727,7 +738,8 @@ struct Engine {
             if (f & 3) { finish_job(J, RMB_EINVAL, (f & 1) ? "non-finite blob position" : "a blob has z <= 0 in wall geometry"); continue; }
             if (f & 32) { finish_job(J, RMB_EINVAL, "blob_shift must be finite and >= 0"); continue; }
             if (f & 4) { finish_job(J, RMB_ENOTSPD, "a body's mobility block is not positive definite"); continue; }
-            if (f & 8) { finish_job(J, RMB_ENOTSPD, "a body's K^T M^-1 K block is singular"); continue; }
+            // the resistance problem uses M_pp^-1 alone
+            if ((f & 8) && !J->resist) { finish_job(J, RMB_ENOTSPD, "a body's K^T M^-1 K block is singular"); continue; }
             J->bnorm = hcol_h(J)[0];
             if (!(J->bnorm > 0.0)) {
                 J->rel = 0.0;
@@ -788,7 +800,11 @@ struct Engine {
             for (Job *J : fin) {
                 if (J->status == RMB_OK || J->status == RMB_ENOCONV) {
                     RMB_HIP(ctx, hipMemcpyAsync(J->lam_out, J->x, 3 * J->nb * 8, hipMemcpyDeviceToDevice, s));
-                    RMB_HIP(ctx, hipMemcpyAsync(J->U_out, J->x + 3 * J->nb, 6 * J->N * 8, hipMemcpyDeviceToDevice, s));
+                    if (J->resist)
+                        RMB_HIP(ctx, launch_body_forces(J->sys.pos, J->sys.q, J->off_d, J->x, J->N, J->U_out, s));
+                    else
+                        RMB_HIP(ctx, hipMemcpyAsync(J->U_out, J->x + 3 * J->nb, 6 * J->N * 8,
+                                                    hipMemcpyDeviceToDevice, s));
                 }
             }
             RMB_HIP(ctx, hipStreamSynchronize(s));
@@ -1185,13 +1201,13 @@ void rmb_server_destroy(rmb_server srv) {
 static rmb_status run_batch(rmb_ctx ctx, int32_t count, const rmb_system *systems, const rmb_precond *pcs,
                             const double *const *FT, const double *const *slip, double *const *U,
                             double *const *lambda, const rmb_solve_opts *opts, rmb_solve_info *infos,
-                            hipStream_t s) {
+                            hipStream_t s, bool resist = false) {
     Engine E(ctx, s, std::max(1, std::min<int32_t>(count, 1024)));
     RMB_TRY(E.init());
     std::vector<Job *> jobs(count, nullptr);
     for (int32_t i = 0; i < count; ++i) {
         rmb_status st = E.submit(&systems[i], FT[i], slip ? slip[i] : nullptr, U[i], lambda[i], opts,
-                                 pcs ? pcs[i] : nullptr, i, &jobs[i]);
+                                 pcs ? pcs[i] : nullptr, i, &jobs[i], resist);
         if (st != RMB_OK) return st;
     }
     std::vector<rmb_status> status(count, RMB_OK);
@@ -1223,6 +1239,18 @@ rmb_status rmb_solve_mobility(rmb_ctx ctx, const rmb_system *sys, const rmb_prec
     rmb_precond pcs[1] = {pc};
     const double *slips[1] = {slip};
     return run_batch(ctx, 1, sys, pc ? pcs : nullptr, &FT, slips, &U, &lambda, opts, info ? info : &tmp, s);
+}
+
+rmb_status rmb_solve_resistance(rmb_ctx ctx, const rmb_system *sys, const rmb_precond pc, const double *U,
+                                const double *slip, double *F, double *lambda, const rmb_solve_opts *opts,
+                                rmb_solve_info *info, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    rmb_solve_info tmp{};
+    rmb_precond pcs[1] = {pc};
+    const double *slips[1] = {slip};
+    return run_batch(ctx, 1, sys, pc ? pcs : nullptr, &U, slips, &F, &lambda, opts, info ? info : &tmp, s, true);
 }
 
 rmb_status rmb_solve_batch(rmb_ctx ctx, int32_t count, const rmb_system *systems, const double *const *FT,
