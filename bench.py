@@ -511,6 +511,15 @@ def main():
         k64 = kt64["pair_f64_wall"]
         line["solve"]["pair_f64_wall_avg_launch_ms"] = k64[0] / max(k64[1], 1)
         log(f"  plain FP64 solve: {ms64:.2f} ms/solve ({infos64[-1]['iterations']} iterations)")
+        dtr, infosr, _ = solve_leg(rmb, torch, ctx, sysd, FT, "relaxed", args.steps, 1)
+        msr = dtr / args.steps * 1e3
+        line["solve"]["relaxed"] = {"ms_per_solve": msr, "iterations": infosr[-1]["iterations"],
+                                    "fp32_products": infosr[-1]["matvecs_fp32"],
+                                    "fp64_products": infosr[-1]["matvecs_fp64"],
+                                    "rel_residual": infosr[-1]["rel_residual"],
+                                    "failed": len([i for i in infosr if i["status"] != 0 or i["rel_residual"] > 1e-8])}
+        log(f"  relaxed-precision solve: {msr:.2f} ms/solve ({infosr[-1]['iterations']} iterations, fp32/fp64 "
+            f"products {infosr[-1]['matvecs_fp32']}/{infosr[-1]['matvecs_fp64']})")
         if not args.no_matvec:
             line["matvec"] = matvec_leg(rmb, torch, ctx, S)
         line["resistance"] = resistance_leg(rmb, torch, ctx, S)

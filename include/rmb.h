@@ -70,7 +70,7 @@ enum { RMB_GEOM_FREE = 0, RMB_GEOM_WALL = 1 };
  *                       pair blocks and products in FP32, sums of each
  *                       target's velocity in FP32 over blocks of 64 sources
  *                       and FP64 across blocks. */
-enum { RMB_PREC_FP64 = 0, RMB_PREC_FP32_PAIRS = 1 };
+enum { RMB_PREC_FP64 = 0, RMB_PREC_FP32_PAIRS = 1, RMB_PREC_RELAXED = 2 /* solves only, see rmb_solve_opts */ };
 
 typedef struct rmb_ctx_s *rmb_ctx;
 typedef struct rmb_precond_s *rmb_precond;
@@ -276,7 +276,14 @@ typedef struct {
     int32_t precision;   /* RMB_PREC_FP64: GMRES on the FP64 operator.
                             RMB_PREC_FP32_PAIRS: inner GMRES cycles on the FP32-pair
                             operator, each followed by an FP64 residual (iterative
-                            refinement); the stopping test always uses FP64. */
+                            refinement); the stopping test always uses FP64.
+                            RMB_PREC_RELAXED: GMRES whose product accuracy is relaxed
+                            as the residual falls (inexact Krylov, the remark in
+                            Sec. 2.2.1): FP64 products while the residual estimate
+                            is above tol / 1e-7 relative to ||b||, FP32-pair products
+                            below it (their error, under 1e-7 relative, is then
+                            within tol ||b|| / ||r_k||); each cycle still ends with
+                            an FP64 residual, which alone decides convergence. */
     int32_t restart;     /* GMRES cycle length m in 1..255; 0 -> 100 */
     int32_t max_iters;   /* Arnoldi steps over all cycles; 0 -> 1000 */
     int32_t pad;

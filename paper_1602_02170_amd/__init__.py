@@ -24,7 +24,7 @@ RMB_OK, RMB_EINVAL, RMB_ENOTSPD, RMB_ENOCONV, RMB_ENOMEM, RMB_EDEVICE, RMB_EBUSY
 STATUS_NAMES = {0: "RMB_OK", 1: "RMB_EINVAL", 2: "RMB_ENOTSPD", 3: "RMB_ENOCONV", 4: "RMB_ENOMEM",
                 5: "RMB_EDEVICE", 6: "RMB_EBUSY"}
 GEOM_FREE, GEOM_WALL = 0, 1
-PREC_FP64, PREC_FP32_PAIRS = 0, 1
+PREC_FP64, PREC_FP32_PAIRS, PREC_RELAXED = 0, 1, 2
 
 # Exported symbols, as declared in include/rmb.h.
 EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
@@ -249,6 +249,8 @@ def _prec(p):
         return PREC_FP64
     if p in ("fp32", "fp32_pairs", PREC_FP32_PAIRS):
         return PREC_FP32_PAIRS
+    if p in ("relaxed", PREC_RELAXED):
+        return PREC_RELAXED
     raise ValueError(f"unknown precision {p!r}")
 
 

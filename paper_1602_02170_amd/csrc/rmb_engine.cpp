@@ -213,6 +213,7 @@ struct Job {
     int k = 0, iters = 0, cycles = 0, mv64 = 0, mv32 = 0;
     double bnorm = 0, rel = 1, target = 0;
     bool cycle_fp32 = false;
+    bool step_fp32 = false;  // relaxed precision: the next product in FP32
     std::vector<double> R, cs, sn, g, y;
     rmb_status status = RMB_OK;
     std::string msg;
@@ -342,7 +343,8 @@ struct Engine {
         if (o) {
             if (o->tol < 0 || o->inner_tol < 0 || o->restart < 0 || o->restart > 255 || o->max_iters < 0)
                 return fail(ctx, RMB_EINVAL, "bad solve options");
-            if (o->precision != RMB_PREC_FP64 && o->precision != RMB_PREC_FP32_PAIRS)
+            if (o->precision != RMB_PREC_FP64 && o->precision != RMB_PREC_FP32_PAIRS &&
+                o->precision != RMB_PREC_RELAXED)
                 return fail(ctx, RMB_EINVAL, "unknown precision %d", o->precision);
             if (o->tol > 0) J->tol = o->tol;
             if (o->inner_tol > 0) J->inner_tol = o->inner_tol;
@@ -437,12 +439,21 @@ struct Engine {
         J->cycles++;
         J->cycle_fp32 = J->prec == RMB_PREC_FP32_PAIRS;
         J->target = J->cycle_fp32 ? std::max(J->inner_tol * beta, 0.5 * J->tol * J->bnorm) : J->tol * J->bnorm;
+        J->step_fp32 = relaxed_fp32(J, beta);
         J->R.assign((size_t)J->m * J->m, 0.0);
         J->cs.assign(J->m, 0.0);
         J->sn.assign(J->m, 0.0);
         J->g.assign(J->m + 1, 0.0);
         J->g[0] = beta;
         J->phase = ITER;
+    }
+
+    // Relaxed precision: an FP32-pair product (relative error below
+    // kFp32ProductError) is accurate enough once tol ||b|| / ||r_k|| exceeds
+    // that error, ||r_k|| being the current residual (estimate).
+    static constexpr double kFp32ProductError = 1e-7;
+    static bool relaxed_fp32(const Job *J, double rnorm) {
+        return J->prec == RMB_PREC_RELAXED && rnorm * kFp32ProductError <= J->tol * J->bnorm;
     }
 
     void finish_job(Job *J, rmb_status st, const char *msg) {
@@ -538,7 +549,7 @@ struct Engine {
         int64_t wg_sd_blob = 0, wg_sd_body = 0;
         for (Job *J : mv) {
             const bool is_iter = J->phase == ITER;
-            const bool f32 = is_iter && J->cycle_fp32;
+            const bool f32 = is_iter && (J->cycle_fp32 || J->step_fp32);
             const double *xin = is_iter ? J->z : J->x;
             PackJob p{};
             p.pos = J->sys.pos;
@@ -777,6 +788,7 @@ struct Engine {
             for (int i = 0; i <= k; ++i) J->R[(size_t)i * J->m + k] = c[i];
             J->k = k + 1;
             J->iters++;
+            J->step_fp32 = relaxed_fp32(J, std::fabs(J->g[J->k]));
             const bool lucky = !(h[k + 1] > 1e-300 * std::max(1.0, J->bnorm));
             if (breakdown || lucky || std::fabs(J->g[J->k]) <= J->target || J->k >= J->m || J->iters >= J->max_iters) {
                 // y = R^-1 g over the first kk columns (drop a singular last column)
