@@ -66,10 +66,13 @@ enum { RMB_GEOM_FREE = 0, RMB_GEOM_WALL = 1 };
 
 /* Pair arithmetic of the blob mobility product.
  *  RMB_PREC_FP64:       every pair block in FP64, FP64 sums.
- *  RMB_PREC_FP32_PAIRS: r_i - r_j formed in FP64 and rounded once to FP32,
+ *  RMB_PREC_FP32_PAIRS: r_i - r_j to FP32 accuracy (one rounding, or the
+ *                       two-float difference of the symmetric product),
  *                       pair blocks and products in FP32, sums of each
  *                       target's velocity in FP32 over blocks of 64 sources
- *                       and FP64 across blocks. */
+ *                       and FP64 across blocks (the symmetric product keeps
+ *                       each tile's sum, over 64 to 512 sources, as an FP32
+ *                       value before the FP64 sum over tiles). */
 enum { RMB_PREC_FP64 = 0, RMB_PREC_FP32_PAIRS = 1, RMB_PREC_RELAXED = 2 /* solves only, see rmb_solve_opts */ };
 
 typedef struct rmb_ctx_s *rmb_ctx;

@@ -293,6 +293,7 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
         J.k_near_iso = 9.0 / (32.0 * sys->a);
         J.k_near_rr = 3.0 / (32.0 * sys->a);
         J.pref = pref;
+        J.f32 = precision == RMB_PREC_FP32_PAIRS;
         SymJob *hJ = nullptr;
         RMB_TRY(pinned(ctx, sizeof(SymJob), (void **)&hJ));
         *hJ = J;

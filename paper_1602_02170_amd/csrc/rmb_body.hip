@@ -159,7 +159,7 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // velocities, force, torque) and the results back (R on lambda, u, omega):
 // the RPY tensor and K are rotation-covariant, M_pp = R~ M_ref R~^T and
 // K_p = R~ K_ref diag(R, R)^T.
-constexpr int kApplyThreads = 64;
+constexpr int kApplyThreads = 256;  // four waves: more factor loads in flight per body
 
 // With `resist` (resistance problem) only lambda = M_pp^-1 s is formed:
 // bot_in and U_out are not touched.

@@ -92,14 +92,16 @@ struct SymJob {
     const double *tpos;  // [nb][3] positions
     const double *lam;   // [nb][3] operand (the target's own force for M^T lambda)
     const void *src;     // [nb] SrcF32 or SrcF64 records
-    double *vpart;       // [tiles][B][3] target-side sums
-    double *upart;       // [tiles][B][3] source-side sums
+    double *vpart;       // [tiles][B][3] target-side sums (FP32 pairs: floats at the same base)
+    double *upart;       // [tiles][B][3] source-side sums (likewise)
     double *vel;         // [nb][3] result, prefactor applied
     int64_t nb;
     int64_t wg_begin;
     int64_t red_begin;
     int32_t n_blk;
     int32_t B;
+    int32_t f32;         // partials are floats (FP32 pairs: each tile's sums are FP32 values)
+    int32_t pad;
     double a, four_a2, k_near_iso, k_near_rr;
     double pref;
 };

@@ -577,6 +577,7 @@ struct Engine {
                 y.k_near_iso = 9.0 / (32.0 * J->sys.a);
                 y.k_near_rr = 3.0 / (32.0 * J->sys.a);
                 y.pref = mobility_prefactor(J->sys.a, J->sys.eta);
+                y.f32 = f32 ? 1 : 0;
                 const int bi = bidx(J->symB);
                 y.wg_begin = stiles[f32][wl][bi];
                 y.red_begin = wg_sred;

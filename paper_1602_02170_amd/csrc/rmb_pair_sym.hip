@@ -175,20 +175,30 @@ struct PairCoef {
     R c2, c3, c4, c5, invL;      // wall image (R = (rx, ry, Rz), e = R invL)
     R Rz;
 
+    // NEAR_POSSIBLE = false: the caller knows r > 2a (far branch only).
+    template <bool NEAR_POSSIBLE = true>
     __device__ __forceinline__ void eval(R rx, R ry, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
         const R rxy2 = P::fma(ry, ry, P::mul(rx, rx));
         const R d2 = P::fma(rz, rz, rxy2);
+        eval_d2<NEAR_POSSIBLE>(rxy2, d2, rz, zj, a, four_a2, kiso, krr, tiny);
+    }
+    template <bool NEAR_POSSIBLE>
+    __device__ __forceinline__ void eval_d2(R rxy2, R d2, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
         const R inv_d = rsqrt_r(d2 + tiny);
-        const R d = P::mul(d2, inv_d);
         const R t = P::mul(a, inv_d);
         const R t2 = P::mul(t, t);
         const R iso_far = P::mul(t, (R)0.5 * t2 + (R)0.75);
         const R rr_far = P::mul(P::mul(t, (R)-1.5 * t2 + (R)0.75), P::mul(inv_d, inv_d));
-        const R iso_near = P::one_minus(kiso, d);
-        const R rr_near = P::mul(krr, inv_d);
-        const bool near = d2 <= four_a2;
-        const R ciso = near ? iso_near : iso_far;
-        crr = near ? rr_near : rr_far;
+        R ciso = iso_far;
+        crr = rr_far;
+        if (NEAR_POSSIBLE) {
+            const R d = P::mul(d2, inv_d);
+            const R iso_near = P::one_minus(kiso, d);
+            const R rr_near = P::mul(krr, inv_d);
+            const bool near = d2 <= four_a2;
+            ciso = near ? iso_near : iso_far;
+            crr = near ? rr_near : rr_far;
+        }
         if (WALL) {
             Rz = (R)2 * zj + rz;
             const R L2 = P::fma(Rz, Rz, rxy2);
@@ -252,22 +262,46 @@ __device__ __forceinline__ double src_z(const gptr<SrcF64> s, int64_t j) { retur
 // entry l - s + 64 without wrapping.
 template <typename R>
 struct SymStage;
+// FP32 pairs: positions as two floats, p = hi + lo with hi = fl32(p) and
+// lo = fl32(p - hi).  The difference of two positions is then formed as
+// (hi_i - hi_j) + (lo_i - lo_j) in FP32: the hi difference is exact when the
+// two coordinates are within a factor of two of each other (Sterbenz) and
+// otherwise rounded once at the scale of the result, the lo difference
+// carries an error of about 2^-48 |p|, so the result matches the FP64
+// difference rounded to FP32 to within an ulp, without FP64 arithmetic.
+struct Pos2 {
+    float xh, yh, zh, xl, yl, zl;
+    __device__ __forceinline__ void set(double x, double y, double z) {
+        xh = (float)x, yh = (float)y, zh = (float)z;
+        xl = (float)(x - (double)xh), yl = (float)(y - (double)yh), zl = (float)(z - (double)zh);
+    }
+};
+
+struct Pos64 {
+    double v[3];
+};
+
 template <>
 struct SymStage<float> {
-    double x[128], y[128], z[128];
-    float2 fxy[128], fzz[128];  // (fx, fy), (fz, z rounded to float)
-    __device__ __forceinline__ void put(int l, double px, double py, double pz, float fx, float fy, float fz) {
-        x[l] = x[l + 64] = px;
-        y[l] = y[l + 64] = py;
-        z[l] = z[l + 64] = pz;
+    float2 xy[128], zx[128], yz[128], fxy[128], fz[128];  // (xh, yh), (zh, xl), (yl, zl), (fx, fy), (fz, -)
+    __device__ __forceinline__ void put(int l, double px, double py, double pz, float fx, float fy, float gz) {
+        Pos2 q;
+        q.set(px, py, pz);
+        xy[l] = xy[l + 64] = make_float2(q.xh, q.yh);
+        zx[l] = zx[l + 64] = make_float2(q.zh, q.xl);
+        yz[l] = yz[l + 64] = make_float2(q.yl, q.zl);
         fxy[l] = fxy[l + 64] = make_float2(fx, fy);
-        fzz[l] = fzz[l + 64] = make_float2(fz, (float)pz);
+        fz[l] = fz[l + 64] = make_float2(gz, 0.f);
     }
-    __device__ __forceinline__ void get(int e, double &px, double &py, double &pz, float &fx, float &fy, float &fz,
-                                        float &zj) const {
-        px = x[e], py = y[e], pz = z[e];
-        const float2 a = fxy[e], b = fzz[e];
-        fx = a.x, fy = a.y, fz = b.x, zj = b.y;
+    // r = target - source in FP32; zj = the source's height (its hi part)
+    __device__ __forceinline__ void diff(int e, const Pos2 &t, float &rx, float &ry, float &rz, float &fx, float &fy,
+                                         float &gz, float &zj) const {
+        using P = VOp<float>;
+        const float2 a = xy[e], b = zx[e], c = yz[e], f = fxy[e], g = fz[e];
+        rx = P::add(P::sub(t.xh, a.x), P::sub(t.xl, b.y));
+        ry = P::add(P::sub(t.yh, a.y), P::sub(t.yl, c.x));
+        rz = P::add(P::sub(t.zh, b.x), P::sub(t.zl, c.y));
+        fx = f.x, fy = f.y, gz = g.x, zj = b.x;
     }
 };
 template <>
@@ -281,12 +315,30 @@ struct SymStage<double> {
         fy[l] = fy[l + 64] = gy;
         fz[l] = fz[l + 64] = gz;
     }
-    __device__ __forceinline__ void get(int e, double &px, double &py, double &pz, double &gx, double &gy,
-                                        double &gz, double &zj) const {
-        px = x[e], py = y[e], pz = z[e];
+    __device__ __forceinline__ void diff(int e, const Pos64 &t, double &rx, double &ry, double &rz, double &gx,
+                                         double &gy, double &gz, double &zj) const {
+        rx = t.v[0] - x[e], ry = t.v[1] - y[e], rz = t.v[2] - z[e];
         gx = fx[e], gy = fy[e], gz = fz[e];
-        zj = pz;
+        zj = z[e];
     }
+};
+
+// Target position in the form the stage's diff expects.
+template <typename R>
+struct TargetPos;
+template <>
+struct TargetPos<float> {
+    using T = Pos2;
+    static __device__ __forceinline__ T make(double x, double y, double z) {
+        Pos2 p;
+        p.set(x, y, z);
+        return p;
+    }
+};
+template <>
+struct TargetPos<double> {
+    using T = Pos64;
+    static __device__ __forceinline__ T make(double x, double y, double z) { return Pos64{{x, y, z}}; }
 };
 
 // One tile per wave.  B: block size (multiple of 64).
@@ -319,8 +371,11 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
     const R a = (R)J.a, four_a2 = (R)J.four_a2, kiso = (R)J.k_near_iso, krr = (R)J.k_near_rr;
     const R tiny = sizeof(R) == 4 ? (R)1e-30f : (R)1e-280;
-    const gmem<double> vout = as_global(J.vpart + t * (int64_t)B * 3);
-    const gmem<double> uout = as_global(J.upart + t * (int64_t)B * 3);
+    // tile sums are stored in the pair precision: with FP32 pairs each one is
+    // an FP32 sum over 64 sources (exact as a float for B = 64; for larger B
+    // the FP64 sum over the tile's groups, rounded once)
+    const gmem<R> vout = as_global((R *)J.vpart + t * (int64_t)B * 3);
+    const gmem<R> uout = as_global((R *)J.upart + t * (int64_t)B * 3);
 
     double u64[G][3];
 #pragma unroll
@@ -332,6 +387,7 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         const bool active = i < nb;
         const int64_t ii = active ? i : (int64_t)I * B + sub * 64;
         const double xi = as_global(J.tpos)[3 * ii], yi = as_global(J.tpos)[3 * ii + 1], zi = as_global(J.tpos)[3 * ii + 2];
+        const auto tp = TargetPos<R>::make(xi, yi, zi);
         // the target's own force enters the transposed contraction
         const R fix = active ? (R)as_global(J.lam)[3 * ii] : (R)0, fiy = active ? (R)as_global(J.lam)[3 * ii + 1] : (R)0,
                 fiz = active ? (R)as_global(J.lam)[3 * ii + 2] : (R)0;
@@ -364,12 +420,18 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 __syncthreads();
                 R ux = 0, uy = 0, uz = 0;
                 for (int step = 0; step < 64; ++step) {
-                    double sx, sy, sz;
-                    R sfx, sfy, sfz, szj;
-                    st.get(lane - step + 64, sx, sy, sz, sfx, sfy, sfz, szj);
-                    const R rx = (R)(xi - sx), ry = (R)(yi - sy), rz = (R)(zi - sz);
+                    R rx, ry, rz, sfx, sfy, sfz, szj;
+                    st.diff(lane - step + 64, tp, rx, ry, rz, sfx, sfy, sfz, szj);
                     PairCoef<R, WALL> pc;
-                    pc.eval(rx, ry, rz, szj, a, four_a2, kiso, krr, tiny);
+                    const R rxy2 = VOp<R>::fma(ry, ry, VOp<R>::mul(rx, rx));
+                    const R d2 = VOp<R>::fma(rz, rz, rxy2);
+                    // overlapping pairs (r <= 2a) are rare away from the
+                    // diagonal tiles: when no lane of the wave has one, the
+                    // far branch alone is evaluated (wave-uniform branch)
+                    if (__ballot(d2 <= four_a2) != 0)
+                        pc.template eval_d2<true>(rxy2, d2, rz, szj, a, four_a2, kiso, krr, tiny);
+                    else
+                        pc.template eval_d2<false>(rxy2, d2, rz, szj, a, four_a2, kiso, krr, tiny);
                     pc.template apply<false>(rx, ry, rz, sfx, sfy, sfz, ax, ay, az);
                     pc.template apply<true>(rx, ry, rz, fix, fiy, fiz, ux, uy, uz);
                     ux = rot1(ux), uy = rot1(uy), uz = rot1(uz);
@@ -384,10 +446,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
             vz += (double)az;
         }
         if (active) {
-            const gmem<double> o = vout + (sub * 64 + lane) * 3;
-            o[0] = vx;
-            o[1] = vy;
-            o[2] = vz;
+            const gmem<R> o = vout + (sub * 64 + lane) * 3;
+            o[0] = (R)vx;
+            o[1] = (R)vy;
+            o[2] = (R)vz;
         }
     }
     if (!diag) {
@@ -395,10 +457,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         for (int g = 0; g < G; ++g) {
             const int64_t j = s0 + 64 * g + lane;
             if (j < s1) {
-                const gmem<double> o = uout + (64 * g + lane) * 3;
-                o[0] = u64[g][0];
-                o[1] = u64[g][1];
-                o[2] = u64[g][2];
+                const gmem<R> o = uout + (64 * g + lane) * 3;
+                o[0] = (R)u64[g][0];
+                o[1] = (R)u64[g][1];
+                o[2] = (R)u64[g][2];
             }
         }
     }
@@ -428,10 +490,18 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
         const int64_t kk = k % B;
         auto tile = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i); };
         const int32_t nv = T - K;  // vpart contributions, then K upart ones
-        for (int32_t c = q; c < T; c += kRedParts) {
-            const gmem<const double> p = as_global(c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
-                                                          : J.upart + (tile(c - nv, K) * B + kk) * 3);
-            s[0] += p[0], s[1] += p[1], s[2] += p[2];
+        if (J.f32) {
+            for (int32_t c = q; c < T; c += kRedParts) {
+                const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + (tile(K, K + c) * B + kk) * 3
+                                                             : (const float *)J.upart + (tile(c - nv, K) * B + kk) * 3);
+                s[0] += (double)p[0], s[1] += (double)p[1], s[2] += (double)p[2];
+            }
+        } else {
+            for (int32_t c = q; c < T; c += kRedParts) {
+                const gmem<const double> p = as_global(c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
+                                                              : J.upart + (tile(c - nv, K) * B + kk) * 3);
+                s[0] += p[0], s[1] += p[1], s[2] += p[2];
+            }
         }
     }
     part[q][b][0] = s[0], part[q][b][1] = s[1], part[q][b][2] = s[2];
