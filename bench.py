@@ -325,7 +325,7 @@ def resistance_leg(rmb, torch, ctx, S, reps=3):
     return res
 
 
-def serving_leg(rmb, torch, ctx, S, n_req, rate):
+def serving_leg(rmb, torch, ctx, S, n_req, rate, precision="fp32"):
     t_gen = time.perf_counter()
     reqs = [S.mixed_wall_request(i) for i in range(n_req)]
     arrivals = S.poisson_arrivals(n_req, rate)
@@ -335,7 +335,7 @@ def serving_leg(rmb, torch, ctx, S, n_req, rate):
     nb = np.array([r.n_blobs for r in reqs])
     log(f"  serving: generated {n_req} requests ({nb.sum()} blobs, max {nb.max()}) "
         f"in {time.perf_counter() - t_gen:.1f}s")
-    opts = dict(tol=1e-8, precision="fp32")
+    opts = dict(tol=1e-8, precision=precision)
     # warm-up of the server path
     srv = rmb.Server(ctx)
     srv.submit(0, systems[0], FTs[0], **opts)
@@ -370,7 +370,8 @@ def serving_leg(rmb, torch, ctx, S, n_req, rate):
     ok = sum(1 for i in infos if i["status"] == 0 and i["rel_residual"] <= 1e-8)
     res = {
         "workload": f"{n_req} wall suspensions, 10-4000 mixed icosahedra/boomerangs, Poisson {rate:g}/s, "
-                    "FP32 pairs + FP64 refinement to 1e-8",
+                    f"{'FP32 pairs + FP64 refinement' if precision == 'fp32' else 'relaxed-precision GMRES'} to 1e-8",
+        "precision": precision,
         "p50_latency_ms": float(np.percentile(lat, 50) * 1e3),
         "p99_latency_ms": float(np.percentile(lat, 99) * 1e3),
         "solves_per_s": n_req / (comp.max() - arrivals.min()),
@@ -439,6 +440,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-factor", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--serve-precision", default="relaxed", choices=["fp32", "relaxed"])
+    ap.add_argument("--serve-budget-gib", type=int, default=0, help="server context budget (0: 16 GiB)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="timed solves only (for profiling)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -538,7 +541,11 @@ def main():
             line["batched_factor"] = factor_leg(rmb, torch, ctx, S)
             line["shared_precond"] = shared_leg(rmb, torch, ctx, S)
         if not args.no_serving:
-            line["serving"] = serving_leg(rmb, torch, ctx, S, args.requests, args.rate)
+            sctx = rmb.Context(0, args.serve_budget_gib << 30) if args.serve_budget_gib else ctx
+            line["serving"] = serving_leg(rmb, torch, sctx, S, args.requests, args.rate, args.serve_precision)
+            line["serving"]["device_budget_gib"] = args.serve_budget_gib or 16
+            if sctx is not ctx:
+                sctx.close()
         if not args.no_cpu:
             line["cpu_baseline"] = cpu_baseline(S, sus)
             log(f"  cpu oracle: {line['cpu_baseline']['value']:.3e} pairs/s on {line['cpu_baseline']['cores']} threads")

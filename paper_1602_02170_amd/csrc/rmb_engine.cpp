@@ -322,7 +322,10 @@ struct Engine {
     double *hcol_h(Job *j) { return mbox_h + (size_t)j->slot * kSlot + 1; }
 
     void release(Job *j) {
-        if (j->dbuf) ctx->arena->free(j->dbuf);
+        if (j->dbuf) {
+            ctx->arena->free(j->dbuf);
+            stage_reserved -= stage_need(*j);
+        }
         j->dbuf = nullptr;
         if (j->slot >= 0) free_slots.push_back(j->slot);
         j->slot = -1;
@@ -382,7 +385,8 @@ struct Engine {
     void admit() {
         while (!queue.empty() && (int)active.size() < max_active && !free_slots.empty()) {
             Job *J = queue.front();
-            void *p = ctx->arena->alloc(J->bytes);
+            const bool staged = grow_stage(stage_reserved + stage_need(*J));
+            void *p = staged ? ctx->arena->alloc(J->bytes) : nullptr;
             if (!p) {
                 if (active.empty()) {  // can never fit beside the server's own buffers
                     queue.pop_front();
@@ -397,6 +401,7 @@ struct Engine {
             }
             queue.pop_front();
             J->dbuf = (char *)p;
+            stage_reserved += stage_need(*J);
             job_carve(*J);
             J->slot = free_slots.back();
             free_slots.pop_back();
@@ -421,18 +426,43 @@ struct Engine {
         }
     }
 
-    rmb_status ensure_stage(size_t bytes) {
-        if (bytes <= stage_cap) return RMB_OK;
-        if (stage_d) ctx->arena->free(stage_d);
-        if (stage_h) RMB_HIP(ctx, hipHostFree(stage_h));
-        stage_d = nullptr, stage_h = nullptr;
+    // Grows the staging buffers to at least `bytes` (twice that if it fits).
+    // The new buffers are allocated before the old ones are released, so a
+    // failed attempt leaves the current buffers in place.  Called only
+    // between ticks, when no work reads the old buffers.
+    bool grow_stage(size_t bytes) {
+        if (bytes <= stage_cap) return true;
         size_t want = std::max<size_t>(bytes * 2, 1 << 20);
-        stage_d = (char *)ctx->arena->alloc(want);
-        if (!stage_d) return fail(ctx, RMB_ENOMEM, "staging buffer does not fit the budget");
-        RMB_HIP(ctx, hipHostMalloc(&stage_h, want, hipHostMallocDefault));
-        stage_cap = want;
-        return RMB_OK;
+        char *d = (char *)ctx->arena->alloc(want);
+        if (!d) {
+            want = std::max<size_t>(bytes, 1 << 20);
+            d = (char *)ctx->arena->alloc(want);
+        }
+        if (!d) return false;
+        char *h = nullptr;
+        if (hipHostMalloc(&h, want, hipHostMallocDefault) != hipSuccess) {
+            ctx->arena->free(d);
+            return false;
+        }
+        if (stage_d) ctx->arena->free(stage_d);
+        if (stage_h) (void)hipHostFree(stage_h);
+        stage_d = d, stage_h = h, stage_cap = want;
+        return true;
     }
+    rmb_status ensure_stage(size_t bytes) {
+        return grow_stage(bytes) ? RMB_OK : fail(ctx, RMB_ENOMEM, "staging buffer does not fit the budget");
+    }
+
+    // Upper bound of what one job adds to a tick's descriptor tables: its
+    // body records and offsets (setup ticks) and a few kilobytes of per-tick
+    // tables and Hessenberg coefficients.  Admission reserves it, so a tick
+    // never needs staging that the budget cannot provide.
+    static size_t stage_need(const Job &J) {
+        return 2 * al(J.N * sizeof(BodyWork)) + al(J.N * sizeof(BigBody)) + al((J.N + 1) * 8) +
+               al((size_t)(J.m + 1) * 8) + 8192;
+    }
+    static constexpr size_t kStageFixed = 32768;  // alignment of the shared tables
+    size_t stage_reserved = kStageFixed;
 
     void begin_cycle(Job *J, double beta) {
         J->k = 0;

@@ -419,6 +419,7 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 st.put(lane, px, py, pz, gx, gy, gz);
                 __syncthreads();
                 R ux = 0, uy = 0, uz = 0;
+#pragma unroll 2
                 for (int step = 0; step < 64; ++step) {
                     R rx, ry, rz, sfx, sfy, sfz, szj;
                     st.diff(lane - step + 64, tp, rx, ry, rz, sfx, sfy, sfz, szj);

@@ -89,3 +89,37 @@ def test_mixed_precisions_and_geometries_in_one_batch(env, oracle_mod):
         assert res <= 1.05e-9
     srv.close()
     ctx.close()
+
+
+def test_staging_is_reserved_when_the_budget_is_full(env, oracle_mod):
+    """Many mid-size requests at once under a budget they fill: the per-tick
+    descriptor staging must already be reserved when admission has used up
+    the budget (growing it at that point used to fail the whole server)."""
+    rmb, torch = env
+    sizes = [300] * 40
+    reqs, systems, FTs = _reqs(rmb, torch, sizes)
+    opts = dict(tol=1e-8, precision="fp32", restart=10)
+    big = rmb.Context(0)
+    alone = [rmb.solve_mobility(big, systems[i], FTs[i], **opts) for i in range(len(sizes))]
+    torch.cuda.synchronize()
+    ctx = rmb.Context(0, hbm_budget=300 << 20)
+    srv = rmb.Server(ctx, max_active=64)
+    for i in range(len(sizes)):
+        srv.submit(i, systems[i], FTs[i], **opts)
+    got, peak, steps = {}, 0, 0
+    while len(got) < len(sizes):
+        a, q = srv.step()
+        peak = max(peak, a)
+        for tag, U, lam, info in srv.poll():
+            got[tag] = (U, lam, info)
+        steps += 1
+        assert steps < 20000
+    print(f"[gpu] staging test: peak active {peak} of {len(sizes)}", flush=True)
+    assert peak < len(sizes)
+    for i, (Ua, la, ia) in enumerate(alone):
+        Um, lm, im = got[i]
+        assert im["status"] == 0
+        assert torch.equal(Ua, Um) and torch.equal(la, lm)
+    srv.close()
+    ctx.close()
+    big.close()
