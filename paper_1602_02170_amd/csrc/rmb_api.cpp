@@ -269,19 +269,19 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     const bool wall = sys->geometry == RMB_GEOM_WALL;
     const double pref = mobility_prefactor(sys->a, sys->eta);
     if (use_sym(nb)) {
-        // scratch layout: [flag | job | sources | vpart, upart]
+        // scratch layout: [flag | job | vpart, upart]; the symmetric kernel
+        // reads positions and forces directly
         SymJob J{};
         sym_plan(nb, &J.B, &J.n_blk);
         const int64_t tiles = sym_tiles(nb);
-        size_t off_job = 256, off_src = off_job + 256;
-        size_t off_part = off_src + (nb * rec + 255) / 256 * 256;
+        size_t off_job = 256;
+        size_t off_part = off_job + 256;
         size_t total = off_part + sym_partial_doubles(nb) * sizeof(double);
         char *base = nullptr;
         RMB_TRY(scratch(ctx, total, (void **)&base));
         RMB_TRY(check_positions(ctx, sys, (int *)base, s));
         J.tpos = sys->pos;
         J.lam = lambda;
-        J.src = base + off_src;
         J.vpart = (double *)(base + off_part);
         J.upart = J.vpart + (size_t)tiles * J.B * 3;
         J.vel = vel;
@@ -298,7 +298,6 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
         RMB_TRY(pinned(ctx, sizeof(SymJob), (void **)&hJ));
         *hJ = J;
         RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(SymJob), hipMemcpyHostToDevice, s));
-        RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
         RMB_TRY(sym_launch(ctx, precision, wall, J.B, (const SymJob *)(base + off_job), 1, tiles, s));
         RMB_HIP(ctx, launch_sym_reduce((const SymJob *)(base + off_job), 1, sym_reduce_groups(nb), s));
         RMB_HIP(ctx, launch_add_shift(sys->blob_shift, lambda, nb, vel, s));

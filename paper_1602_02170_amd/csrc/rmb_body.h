@@ -85,6 +85,29 @@ struct SaddleJob {
     double pref;
 };
 
+// Blob row i of the saddle-point operator from the finished product v_i
+// (prefactor applied): y_i = v_i + d_i x_i - (u_p + omega_p x (r_i - q_p)), or
+// b_i - y_i; the resistance form drops the rigid-motion term.
+__device__ __forceinline__ void saddle_blob_row(const SaddleJob &J, int64_t i, const double v[3]) {
+    const int64_t n3 = 3 * J.nb;
+    double ku[3] = {0.0, 0.0, 0.0};
+    if (!J.resist) {
+        const int p = as_global(J.blob_body)[i];
+        const gmem<const double> U = as_global(J.x + n3 + 6 * (int64_t)p);
+        const gmem<const double> q = as_global(J.q + 3 * (int64_t)p);
+        const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1],
+                             as_global(J.pos)[3 * i + 2] - q[2]};
+        ku[0] = U[0] + U[4] * d[2] - U[5] * d[1];
+        ku[1] = U[1] + U[5] * d[0] - U[3] * d[2];
+        ku[2] = U[2] + U[3] * d[1] - U[4] * d[0];
+    }
+    const double shift = J.shift ? as_global(J.shift)[i] : 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double y = v[c] + shift * as_global(J.x)[3 * i + c] - ku[c];
+        as_global(J.y)[3 * i + c] = J.b ? as_global(J.b)[3 * i + c] - y : y;
+    }
+}
+
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s);
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s);

@@ -398,22 +398,8 @@ __global__ void saddle_blob_kernel(const SaddleJob *__restrict__ jobs, int32_t n
         v[1] += p[1];
         v[2] += p[2];
     }
-    double ku[3] = {0.0, 0.0, 0.0};
-    if (!J.resist) {
-        const int p = as_global(J.blob_body)[i];
-        const gmem<const double> U = as_global(J.x + n3 + 6 * (int64_t)p);
-        const gmem<const double> q = as_global(J.q + 3 * (int64_t)p);
-        const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1],
-                             as_global(J.pos)[3 * i + 2] - q[2]};
-        ku[0] = U[0] + U[4] * d[2] - U[5] * d[1];
-        ku[1] = U[1] + U[5] * d[0] - U[3] * d[2];
-        ku[2] = U[2] + U[3] * d[1] - U[4] * d[0];
-    }
-    const double shift = J.shift ? as_global(J.shift)[i] : 0.0;
-    for (int c = 0; c < 3; ++c) {
-        const double y = J.pref * v[c] + shift * as_global(J.x)[3 * i + c] - ku[c];
-        as_global(J.y)[3 * i + c] = J.b ? as_global(J.b)[3 * i + c] - y : y;
-    }
+    v[0] *= J.pref, v[1] *= J.pref, v[2] *= J.pref;
+    saddle_blob_row(J, i, v);
 }
 
 // Body rows: y_U[p] = -(sum_i lambda_i, sum_i (r_i - q_p) x lambda_i), or the

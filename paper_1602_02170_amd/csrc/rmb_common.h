@@ -91,10 +91,11 @@ hipError_t launch_pack_sub_sources(int precision, const double *pos, const doubl
 struct SymJob {
     const double *tpos;  // [nb][3] positions
     const double *lam;   // [nb][3] operand (the target's own force for M^T lambda)
-    const void *src;     // [nb] SrcF32 or SrcF64 records
     double *vpart;       // [tiles][B][3] target-side sums (FP32 pairs: floats at the same base)
     double *upart;       // [tiles][B][3] source-side sums (likewise)
-    double *vel;         // [nb][3] result, prefactor applied
+    double *vel;         // [nb][3] result, prefactor applied (unused with epi)
+    const void *epi;     // NULL, or the system's saddle-operator rows (a SaddleJob): the
+                         // reduction then writes the blob rows of A x (or b - A x) instead of vel
     int64_t nb;
     int64_t wg_begin;
     int64_t red_begin;

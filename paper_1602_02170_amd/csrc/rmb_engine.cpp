@@ -224,7 +224,7 @@ static size_t job_bytes(Job &J) {
     const int64_t nb = J.nb, N = J.N, n = J.n;
     size_t t = 0;
     const size_t part = J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24;
-    t += al((N + 1) * 8) + al(nb * 4) + al(nb * sizeof(SrcF64)) + al(part) + al(nb * 24);
+    t += al((N + 1) * 8) + al(nb * 4) + al(J.sym ? 0 : nb * sizeof(SrcF64)) + al(part) + al(nb * 24);
     t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
     t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8) + al(256 * 8);
     if (!J.pc) t += al(factor_total(J.off.data(), N) * 8) + al(N * sizeof(BodyWork)) + al(N * sizeof(BigBody));
@@ -241,7 +241,7 @@ static void job_carve(Job &J) {
     const int64_t nb = J.nb, N = J.N, n = J.n;
     J.off_d = (int64_t *)take((N + 1) * 8);
     J.blob_body = (int32_t *)take(nb * 4);
-    J.src = take(nb * sizeof(SrcF64));
+    J.src = J.sym ? nullptr : take(nb * sizeof(SrcF64));  // packed sources: one-sided kernel only
     J.partial = (double *)take(J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24);
     J.vel = (double *)take(nb * 24);
     J.x = (double *)take(n * 8);
@@ -581,21 +581,22 @@ struct Engine {
             const bool is_iter = J->phase == ITER;
             const bool f32 = is_iter && (J->cycle_fp32 || J->step_fp32);
             const double *xin = is_iter ? J->z : J->x;
-            PackJob p{};
-            p.pos = J->sys.pos;
-            p.lam = xin;
-            p.src = J->src;
-            p.nb = J->nb;
-            p.wg_begin = wg_pk;
-            p.precision = f32 ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64;
-            pk.push_back(p);
-            wg_pk += (J->nb + 255) / 256;
+            if (!J->sym) {  // the symmetric kernel reads positions and forces directly
+                PackJob p{};
+                p.pos = J->sys.pos;
+                p.lam = xin;
+                p.src = J->src;
+                p.nb = J->nb;
+                p.wg_begin = wg_pk;
+                p.precision = f32 ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64;
+                pk.push_back(p);
+                wg_pk += (J->nb + 255) / 256;
+            }
             const int wl = J->sys.geometry == RMB_GEOM_WALL;
             if (J->sym) {
                 SymJob y{};
                 y.tpos = J->sys.pos;
                 y.lam = xin;
-                y.src = J->src;
                 y.vpart = J->partial;
                 y.upart = J->partial + (size_t)sym_tiles(J->nb) * J->symB * 3;
                 y.vel = J->vel;
@@ -614,6 +615,7 @@ struct Engine {
                 stiles[f32][wl][bi] += sym_tiles(J->nb);
                 wg_sred += sym_reduce_groups(J->nb);
                 syms[f32][wl][bi].push_back(y);
+                y.epi = (const void *)(uintptr_t)sd.size();  // index of its saddle rows; patched below
                 sred.push_back(y);
             } else {
                 PairJob pj = J->pj;
@@ -638,7 +640,7 @@ struct Engine {
             sj.resist = J->resist ? 1 : 0;
             sj.pref = J->sym ? 1.0 : mobility_prefactor(J->sys.a, J->sys.eta);
             sd.push_back(sj);
-            wg_sd_blob += (J->nb + 255) / 256;
+            wg_sd_blob += J->sym ? 0 : (J->nb + 255) / 256;  // symmetric: rows written by the reduction
             wg_sd_body += J->resist ? 0 : J->N;
             if (f32) J->mv32++; else J->mv64++;
         }
@@ -698,15 +700,17 @@ struct Engine {
                 for (int c = 0; c < 4; ++c)
                     if (!syms[a][b][c].empty())
                         o_sym[a][b][c] = st.put(syms[a][b][c].data(), syms[a][b][c].size() * sizeof(SymJob));
-        size_t o_sred = sred.empty() ? 0 : st.put(sred.data(), sred.size() * sizeof(SymJob));
         size_t o_sd = sd.empty() ? 0 : st.put(sd.data(), sd.size() * sizeof(SaddleJob));
         size_t o_orth = orth.empty() ? 0 : st.put(orth.data(), orth.size() * sizeof(KrylovJob));
         size_t o_axp = axp.empty() ? 0 : st.put(axp.data(), axp.size() * sizeof(KrylovJob));
-        // combine table needs device addresses of the coefficients: patch after sizing
-        size_t o_comb = 0;
-        RMB_TRY(ensure_stage(st.used + comb.size() * sizeof(KrylovJob) + 4096));
+        // the combine and reduction tables hold device addresses inside the
+        // staging buffer (coefficients, saddle rows): patched once it is sized
+        size_t o_comb = 0, o_sred = 0;
+        RMB_TRY(ensure_stage(st.used + comb.size() * sizeof(KrylovJob) + sred.size() * sizeof(SymJob) + 8192));
         for (auto &K : comb) K.coef = (const double *)(stage_d + (size_t)(uintptr_t)K.coef);
+        for (auto &y : sred) y.epi = stage_d + o_sd + (size_t)(uintptr_t)y.epi * sizeof(SaddleJob);
         if (!comb.empty()) o_comb = st.put(comb.data(), comb.size() * sizeof(KrylovJob));
+        if (!sred.empty()) o_sred = st.put(sred.data(), sred.size() * sizeof(SymJob));
         RMB_TRY(ensure_stage(st.used));
         memcpy(stage_h, st.host.data(), st.used);
         RMB_HIP(ctx, hipMemcpyAsync(stage_d, stage_h, st.used, hipMemcpyHostToDevice, s));

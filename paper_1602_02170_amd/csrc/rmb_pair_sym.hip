@@ -26,7 +26,7 @@
 // what shares the launch).
 #include <cmath>
 
-#include "rmb_common.h"
+#include "rmb_body.h"
 
 namespace rmb {
 
@@ -254,8 +254,6 @@ struct SrcView<SrcF64> {
     using R = double;
 };
 
-__device__ __forceinline__ float src_z(const gptr<SrcF32> s, int64_t j) { return s[j].zf; }
-__device__ __forceinline__ double src_z(const gptr<SrcF64> s, int64_t j) { return s[j].z; }
 
 // A group of 64 sources staged in LDS twice over (entries l and l + 64 hold
 // source l), so that lane l reads the source it pairs with at step s at
@@ -366,7 +364,11 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     tile_ij(t, J.n_blk, &I, &Jb);
     const int64_t nb = J.nb;
     const int lane = threadIdx.x;
-    gptr<SRC> __restrict__ src = (gptr<SRC>)J.src;
+    // sources are read straight from the positions and forces (no packed
+    // records): wave-uniform in the diagonal tiles (scalar cache), one per
+    // lane when a group is staged
+    const gptr<double> __restrict__ spos = (gptr<double>)J.tpos;
+    const gptr<double> __restrict__ slam = (gptr<double>)J.lam;
     const bool diag = I == Jb;
     const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
     const R a = (R)J.a, four_a2 = (R)J.four_a2, kiso = (R)J.k_near_iso, krr = (R)J.k_near_rr;
@@ -401,20 +403,22 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 const int je = (int)min((int64_t)64, s1 - jb);
                 for (int jj = 0; jj < je; ++jj) {
                     const int64_t j = jb + jj;
-                    const R rx = (R)(xi - src[j].x), ry = (R)(yi - src[j].y), rz = (R)(zi - src[j].z);
+                    const double sx = spos[3 * j], sy = spos[3 * j + 1], sz = spos[3 * j + 2];
+                    const R rx = (R)(xi - sx), ry = (R)(yi - sy), rz = (R)(zi - sz);
                     PairCoef<R, WALL> pc;
-                    pc.eval(rx, ry, rz, src_z(src, j), a, four_a2, kiso, krr, tiny);
-                    pc.template apply<false>(rx, ry, rz, (R)src[j].fx, (R)src[j].fy, (R)src[j].fz, ax, ay, az);
+                    pc.eval(rx, ry, rz, (R)sz, a, four_a2, kiso, krr, tiny);
+                    pc.template apply<false>(rx, ry, rz, (R)slam[3 * j], (R)slam[3 * j + 1], (R)slam[3 * j + 2], ax, ay,
+                                             az);
                 }
             } else {
                 // stage the group (idle lanes carry a valid position with
                 // zero force)
                 const int64_t jl = jb + lane;
                 const bool jvalid = jl < s1;
-                const gmem<const SRC> rec = as_global((const SRC *)J.src + (jvalid ? jl : jb));
-                const double px = rec->x, py = rec->y, pz = rec->z;
-                const R gx = jvalid ? (R)rec->fx : (R)0, gy = jvalid ? (R)rec->fy : (R)0,
-                        gz = jvalid ? (R)rec->fz : (R)0;
+                const int64_t js = jvalid ? jl : jb;
+                const double px = spos[3 * js], py = spos[3 * js + 1], pz = spos[3 * js + 2];
+                const R gx = jvalid ? (R)slam[3 * js] : (R)0, gy = jvalid ? (R)slam[3 * js + 1] : (R)0,
+                        gz = jvalid ? (R)slam[3 * js + 2] : (R)0;
                 __syncthreads();  // the previous group's reads are done
                 st.put(lane, px, py, pz, gx, gy, gz);
                 __syncthreads();
@@ -510,10 +514,16 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
     if (q == 0 && k < J.nb) {
         double t[3] = {0.0, 0.0, 0.0};
         for (int r = 0; r < kRedParts; ++r) t[0] += part[r][b][0], t[1] += part[r][b][1], t[2] += part[r][b][2];
-        const gmem<double> o = as_global(J.vel + 3 * k);
-        o[0] = J.pref * t[0];
-        o[1] = J.pref * t[1];
-        o[2] = J.pref * t[2];
+        const double v[3] = {J.pref * t[0], J.pref * t[1], J.pref * t[2]};
+        if (J.epi) {
+            // inside a solve: the blob rows of the saddle-point operator
+            saddle_blob_row(*(const SaddleJob *)J.epi, k, v);
+        } else {
+            const gmem<double> o = as_global(J.vel + 3 * k);
+            o[0] = v[0];
+            o[1] = v[1];
+            o[2] = v[2];
+        }
     }
 }
 
