@@ -137,6 +137,9 @@ hipError_t launch_pack_sources(int precision, const double *pos, const double *l
                                void *src, hipStream_t s);
 // jobs: device array of n_jobs PairJob with increasing tile_begin; n_tiles is
 // the total workgroup count.
+// FP32 one-sided product with LDS-staged sources (same jobs and partials as
+// the FP32 case of launch_pair_tiles, which uses it)
+hipError_t launch_pair_lds_f32(bool wall, const PairJob *jobs, int32_t n_jobs, int64_t n_tiles, hipStream_t s);
 hipError_t launch_pair_tiles(int precision, bool wall, const PairJob *jobs, int32_t n_jobs,
                              int64_t n_tiles, hipStream_t s);
 // v[i] = pref * sum_s partial[s][i]

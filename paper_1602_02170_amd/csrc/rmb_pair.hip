@@ -13,9 +13,12 @@
 //
 // Execution model.  One lane owns one target blob (positions kept in FP64
 // registers); a workgroup holds 256 targets (4 wave64s).  Every lane of a
-// wave visits the same source at the same time, so the source records are
-// wave-uniform loads that the compiler serves from the scalar cache into
-// SGPRs: no LDS staging, no barriers.  The source range of a system is split
+// wave visits the same source at the same time.  In the FP64 kernel here the
+// source records are wave-uniform loads that the compiler serves from the
+// scalar cache into SGPRs (no LDS staging, no barriers); the FP32 kernel
+// stages its sources in LDS instead (pair_lds_f32_kernel), because FP32
+// arithmetic with an SGPR operand issues at half the rate of the register
+// form on gfx950.  The source range of a system is split
 // into chunks so that small systems still launch thousands of workgroups;
 // each chunk writes its own FP64 partial sum and a second pass adds the
 // chunks in a fixed order (deterministic, independent of other systems in
@@ -209,102 +212,6 @@ __device__ __forceinline__ double rsqrt_f64(double x) {
 }
 
 template <bool WALL>
-__global__ __launch_bounds__(kPairBlock) void pair_f32_kernel(const PairJob *__restrict__ jobs,
-                                                             int32_t n_jobs) {
-    const int64_t w = blockIdx.x;
-    const int k = find_job(jobs, n_jobs, w);
-    const PairJob &J = jobs[k];
-    const int64_t lt = w - J.tile_begin;
-    const int32_t split = (int32_t)(lt / J.n_tblock);
-    const int64_t t0 = (lt % J.n_tblock) * kPairBlock;
-    const int64_t s0 = split * J.chunk;
-    const int64_t s1 = min(s0 + J.chunk, J.ns);
-    global_ptr<SrcF32> __restrict__ src = (global_ptr<SrcF32>)J.src;
-
-    const int64_t i = t0 + threadIdx.x;
-    const bool active = i < J.nb;
-    const int64_t ii = active ? i : t0;  // idle lanes shadow a valid target
-    const double xi = as_global(J.tpos)[3 * ii + 0], yi = as_global(J.tpos)[3 * ii + 1], zi = as_global(J.tpos)[3 * ii + 2];
-
-    const float a = J.a_f, four_a2 = J.four_a2_f, kiso = J.k_near_iso_f, krr = J.k_near_rr_f;
-    double vx = 0.0, vy = 0.0, vz = 0.0;
-
-    for (int64_t jb = s0; jb < s1; jb += kAccBlock) {
-        const int64_t je = min(jb + (int64_t)kAccBlock, s1);
-        float ax = 0.f, ay = 0.f, az = 0.f;
-#pragma unroll 2
-        for (int64_t j = jb; j < je; ++j) {
-            SrcF32 s;
-            s.x = src[j].x, s.y = src[j].y, s.z = src[j].z;
-            s.fx = src[j].fx, s.fy = src[j].fy, s.fz = src[j].fz, s.zf = src[j].zf;
-            const float rx = (float)(xi - s.x);
-            const float ry = (float)(yi - s.y);
-            const float rz = (float)(zi - s.z);
-            const float rxy2 = fmaf(rx, rx, ry * ry);
-            const float d2 = fmaf(rz, rz, rxy2);
-            // free-space RPY; the tiny shift keeps i == j finite (the r r^T
-            // term then multiplies r . lambda = 0)
-            const float inv_d = __builtin_amdgcn_rsqf(d2 + 1e-30f);
-            const float d = d2 * inv_d;
-            const float t = a * inv_d;
-            const float t2 = t * t;
-            const float iso_far = t * fmaf(0.5f, t2, 0.75f);
-            const float rr_far = t * fmaf(-1.5f, t2, 0.75f) * (inv_d * inv_d);
-            const float iso_near = fmaf(-kiso, d, 1.0f);
-            const float rr_near = krr * inv_d;
-            const bool near = d2 <= four_a2;
-            const float ciso = near ? iso_near : iso_far;
-            const float crr = near ? rr_near : rr_far;
-            const float pxy = fmaf(rx, s.fx, ry * s.fy);
-            const float sr = crr * fmaf(rz, s.fz, pxy);
-            ax = fmaf(ciso, s.fx, fmaf(sr, rx, ax));
-            ay = fmaf(ciso, s.fy, fmaf(sr, ry, ay));
-            az = fmaf(ciso, s.fz, fmaf(sr, rz, az));
-            if (WALL) {
-                const float Rz = fmaf(2.0f, s.zf, rz);  // z_i + z_j
-                const float L2 = fmaf(Rz, Rz, rxy2);
-                const float invL = __builtin_amdgcn_rsqf(L2);
-                const float xw = a * invL, hh = s.zf * invL, ez = Rz * invL;
-                const float xw2 = xw * xw, xw4 = xw2 * xw2, ez2 = ez * ez;
-                const float hh2 = hh * hh, ezh = ez * hh;
-                const float T = hh2 - ezh;
-                const float xq = 0.25f * xw;
-                // c1 = xi/4 [-3 + 6 T + xi^2 (6 ez^2 - 2) + xi^4 (2 - 10 ez^2)], T = hh^2 - ez hh
-                const float c1 = xq * fmaf(xw4, fmaf(-10.f, ez2, 2.f),
-                                           fmaf(xw2, fmaf(6.f, ez2, -2.f), fmaf(6.f, T, -3.f)));
-                // c2 = xi/4 [-3 - 18 T + xi^2 (6 - 30 ez^2) + xi^4 (70 ez^2 - 10)]
-                const float c2 = xq * fmaf(xw4, fmaf(70.f, ez2, -10.f),
-                                           fmaf(xw2, fmaf(-30.f, ez2, 6.f), fmaf(-18.f, T, -3.f)));
-                // c3 = xi [3/2 hh (1 - 6 ez^2 + 6 ez hh) + ez (xi^2 (15 ez^2 - 3) + xi^4 (10 - 35 ez^2))]
-                const float hh15 = 1.5f * hh;
-                const float m3 = hh15 * fmaf(-6.f, ez2, fmaf(6.f, ezh, 1.f));
-                const float e3 = fmaf(xw2, fmaf(15.f, ez2, -3.f), xw4 * fmaf(-35.f, ez2, 10.f));
-                const float c3 = xw * fmaf(ez, e3, m3);
-                // c4 = xi [3/2 hh - 5 ez xi^4]
-                const float c4 = xw * fmaf(-5.f * ez, xw4, hh15);
-                // c5 = xi [-3 (hh^2 + ez^2 xi^2) + xi^4 (15 ez^2 - 2)]
-                const float c5 = xw * fmaf(xw4, fmaf(15.f, ez2, -2.f), -3.f * fmaf(ez2, xw2, hh2));
-                const float ef = fmaf(Rz, s.fz, pxy) * invL;  // e . f
-                const float g = fmaf(c2, ef, c3 * s.fz) * invL;
-                const float kz = fmaf(c4, ef, c5 * s.fz);
-                ax = fmaf(c1, s.fx, fmaf(g, rx, ax));
-                ay = fmaf(c1, s.fy, fmaf(g, ry, ay));
-                az = fmaf(c1, s.fz, fmaf(g, Rz, az)) + kz;
-            }
-        }
-        vx += (double)ax;
-        vy += (double)ay;
-        vz += (double)az;
-    }
-    if (active) {
-        const gmem<double> out = as_global(J.partial + ((int64_t)split * J.nb + i) * 3);
-        out[0] = vx;
-        out[1] = vy;
-        out[2] = vz;
-    }
-}
-
-template <bool WALL>
 __global__ __launch_bounds__(kPairBlock) void pair_f64_kernel(const PairJob *__restrict__ jobs,
                                                              int32_t n_jobs) {
     const int64_t w = blockIdx.x;
@@ -389,10 +296,7 @@ hipError_t launch_pair_tiles(int precision, bool wall, const PairJob *jobs, int3
     if (n_tiles <= 0) return hipSuccess;
     dim3 g((unsigned)n_tiles), b(kPairBlock);
     if (precision == RMB_PREC_FP32_PAIRS) {
-        if (wall)
-            hipLaunchKernelGGL(pair_f32_kernel<true>, g, b, 0, s, jobs, n_jobs);
-        else
-            hipLaunchKernelGGL(pair_f32_kernel<false>, g, b, 0, s, jobs, n_jobs);
+        return launch_pair_lds_f32(wall, jobs, n_jobs, n_tiles, s);
     } else {
         if (wall)
             hipLaunchKernelGGL(pair_f64_kernel<true>, g, b, 0, s, jobs, n_jobs);

@@ -471,6 +471,100 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     }
 }
 
+// One-sided FP32 product (targets and sources may differ: small systems and
+// the flow field).  A workgroup of 256 lanes owns 256 targets and one chunk of
+// sources; the sources are staged in LDS 256 at a time, as two-float
+// positions, and every wave then visits them one by one with the same
+// address on all lanes (LDS broadcast), so the pair arithmetic runs on
+// registers in VOP3 form.  Sums are FP32 over aligned blocks of 64 sources
+// and FP64 across blocks, as in the symmetric product.
+struct SrcStage {
+    float2 xy[kPairBlock], zx[kPairBlock], yz[kPairBlock], fxy[kPairBlock], fz[kPairBlock];
+};
+
+template <bool WALL>
+__global__ __launch_bounds__(kPairBlock) void pair_lds_f32_kernel(const PairJob *__restrict__ jobs, int32_t n_jobs) {
+    using P = VOp<float>;
+    __shared__ SrcStage st;
+    const int64_t w = blockIdx.x;
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].tile_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const PairJob &J = jobs[lo];
+    const int64_t lt = w - J.tile_begin;
+    const int32_t split = (int32_t)(lt / J.n_tblock);
+    const int64_t t0 = (lt % J.n_tblock) * kPairBlock;
+    const int64_t s0 = split * J.chunk;
+    const int64_t s1 = min(s0 + J.chunk, J.ns);
+    const int tid = threadIdx.x;
+    const int64_t i = t0 + tid;
+    const bool active = i < J.nb;
+    const int64_t ii = active ? i : t0;  // idle lanes shadow a valid target
+    const gmem<const double> tpos = as_global(J.tpos);
+    Pos2 tp;
+    tp.set(tpos[3 * ii], tpos[3 * ii + 1], tpos[3 * ii + 2]);
+    const gmem<const SrcF32> src = as_global((const SrcF32 *)J.src);
+    const float a = J.a_f, four_a2 = J.four_a2_f, kiso = J.k_near_iso_f, krr = J.k_near_rr_f, tiny = 1e-30f;
+    double vx = 0.0, vy = 0.0, vz = 0.0;
+
+    for (int64_t jb = s0; jb < s1; jb += kPairBlock) {
+        const int64_t j = jb + tid;
+        const int64_t js = j < s1 ? j : jb;
+        const gmem<const SrcF32> r = src + js;
+        Pos2 q;
+        q.set(r->x, r->y, r->z);
+        const float fx = j < s1 ? r->fx : 0.f, fy = j < s1 ? r->fy : 0.f, gz = j < s1 ? r->fz : 0.f;
+        __syncthreads();  // the previous block's reads are done
+        st.xy[tid] = make_float2(q.xh, q.yh);
+        st.zx[tid] = make_float2(q.zh, q.xl);
+        st.yz[tid] = make_float2(q.yl, q.zl);
+        st.fxy[tid] = make_float2(fx, fy);
+        st.fz[tid] = make_float2(gz, 0.f);
+        __syncthreads();
+        const int ne = (int)min((int64_t)kPairBlock, s1 - jb);
+        for (int g = 0; g < ne; g += kAccBlock) {
+            const int ge = min(kAccBlock, ne - g);
+            float ax = 0.f, ay = 0.f, az = 0.f;
+            for (int k = 0; k < ge; ++k) {
+                const int e = g + k;
+                const float2 xy = st.xy[e], zx = st.zx[e], yz = st.yz[e], f = st.fxy[e], fzz = st.fz[e];
+                const float rx = P::add(P::sub(tp.xh, xy.x), P::sub(tp.xl, zx.y));
+                const float ry = P::add(P::sub(tp.yh, xy.y), P::sub(tp.yl, yz.x));
+                const float rz = P::add(P::sub(tp.zh, zx.x), P::sub(tp.zl, yz.y));
+                const float rxy2 = P::fma(ry, ry, P::mul(rx, rx));
+                const float d2 = P::fma(rz, rz, rxy2);
+                PairCoef<float, WALL> pc;
+                if (__ballot(d2 <= four_a2) != 0)
+                    pc.template eval_d2<true>(rxy2, d2, rz, zx.x, a, four_a2, kiso, krr, tiny);
+                else
+                    pc.template eval_d2<false>(rxy2, d2, rz, zx.x, a, four_a2, kiso, krr, tiny);
+                pc.template apply<false>(rx, ry, rz, f.x, f.y, fzz.x, ax, ay, az);
+            }
+            vx += (double)ax;
+            vy += (double)ay;
+            vz += (double)az;
+        }
+    }
+    if (active) {
+        const gmem<double> out = as_global(J.partial + ((int64_t)split * J.nb + i) * 3);
+        out[0] = vx;
+        out[1] = vy;
+        out[2] = vz;
+    }
+}
+
+hipError_t launch_pair_lds_f32(bool wall, const PairJob *jobs, int32_t n_jobs, int64_t n_tiles, hipStream_t s) {
+    if (n_tiles <= 0) return hipSuccess;
+    dim3 g((unsigned)n_tiles), b(kPairBlock);
+    if (wall)
+        hipLaunchKernelGGL(pair_lds_f32_kernel<true>, g, b, 0, s, jobs, n_jobs);
+    else
+        hipLaunchKernelGGL(pair_lds_f32_kernel<false>, g, b, 0, s, jobs, n_jobs);
+    return hipGetLastError();
+}
+
 // v[k] = pref * (sum_{J >= K} vpart[tile(K,J)][kk] + sum_{I < K} upart[tile(I,K)][kk]).
 // A workgroup covers 16 blobs with 16 threads each: thread (q, b) sums the
 // contributions q, q+16, q+32, ... of blob b (in the order listed above), and
