@@ -440,6 +440,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-factor", action="store_true")
     ap.add_argument("--no-flow", action="store_true")
+    ap.add_argument("--prewarm", type=int, default=300, help="untimed products before anything is timed")
     ap.add_argument("--serve-precision", default="relaxed", choices=["fp32", "relaxed"])
     ap.add_argument("--serve-budget-gib", type=int, default=0, help="server context budget (0: 16 GiB)")
     ap.add_argument("--no-cpu", action="store_true")
@@ -467,7 +468,7 @@ def main():
     # products of a fresh process run up to 15% slower (about 0.1 s here)
     lam_w = torch.ones((nb, 3), dtype=torch.float64, device="cuda")
     vel_w = torch.empty_like(lam_w)
-    for _ in range(300):
+    for _ in range(args.prewarm):
         rmb.mobility_matvec(ctx, sysd, lam_w, "fp32", vel_w)
     torch.cuda.synchronize()
     del lam_w, vel_w

@@ -590,12 +590,14 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
         auto tile = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i); };
         const int32_t nv = T - K;  // vpart contributions, then K upart ones
         if (J.f32) {
+#pragma unroll 4
             for (int32_t c = q; c < T; c += kRedParts) {
                 const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + (tile(K, K + c) * B + kk) * 3
                                                              : (const float *)J.upart + (tile(c - nv, K) * B + kk) * 3);
                 s[0] += (double)p[0], s[1] += (double)p[1], s[2] += (double)p[2];
             }
         } else {
+#pragma unroll 4
             for (int32_t c = q; c < T; c += kRedParts) {
                 const gmem<const double> p = as_global(c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
                                                               : J.upart + (tile(c - nv, K) * B + kk) * 3);
