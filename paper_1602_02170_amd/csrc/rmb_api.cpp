@@ -70,6 +70,39 @@ rmb_status pinned(rmb_ctx ctx, size_t bytes, void **out) {
     return RMB_OK;
 }
 
+void *pinned_lease(rmb_ctx ctx, size_t bytes, size_t *got) {
+    auto &c = ctx->pinned_cache;
+    size_t best = c.size();
+    for (size_t i = 0; i < c.size(); ++i)
+        if (c[i].second >= bytes && (best == c.size() || c[i].second < c[best].second)) best = i;
+    if (best < c.size()) {
+        void *p = c[best].first;
+        *got = c[best].second;
+        c.erase(c.begin() + best);
+        return p;
+    }
+    void *p = nullptr;
+    if (hipHostMalloc(&p, bytes, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    *got = bytes;
+    return p;
+}
+
+void pinned_give(rmb_ctx ctx, void *p, size_t bytes) {
+    if (!p) return;
+    auto &c = ctx->pinned_cache;
+    c.emplace_back(p, bytes);
+    if (c.size() > 8) {  // keep the largest few
+        size_t small = 0;
+        for (size_t i = 1; i < c.size(); ++i)
+            if (c[i].second < c[small].second) small = i;
+        (void)hipHostFree(c[small].first);
+        c.erase(c.begin() + small);
+    }
+}
+
 rmb_status check_system(rmb_ctx ctx, const rmb_system *sys, bool need_bodies) {
     if (!sys) return fail(ctx, RMB_EINVAL, "system is NULL");
     if (sys->n_blobs < 1) return fail(ctx, RMB_EINVAL, "n_blobs must be >= 1 (got %lld)", (long long)sys->n_blobs);
@@ -247,6 +280,7 @@ void rmb_ctx_destroy(rmb_ctx ctx) {
     resolve_timing(ctx, true);
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    for (auto &b : ctx->pinned_cache) (void)hipHostFree(b.first);
     delete ctx->arena;
     delete ctx;
 }

@@ -17,6 +17,9 @@ struct rmb_ctx_s {
     // Pinned host staging for small uploads/downloads.
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
+    // Pinned host buffers given back by finished solve engines, lent to the
+    // next ones: pinning host memory costs more than several solve steps.
+    std::vector<std::pair<void *, size_t>> pinned_cache;
     hipStream_t last_stream = nullptr;
     bool any_stream = false;
     // kernel timing (diagnostics)
@@ -63,6 +66,11 @@ rmb_status enter(rmb_ctx ctx, hipStream_t s);
 rmb_status scratch(rmb_ctx ctx, size_t bytes, void **out);
 // Grow-only pinned host staging of at least `bytes`.
 rmb_status pinned(rmb_ctx ctx, size_t bytes, void **out);
+// A pinned host buffer of at least `bytes` from the context's cache (or a
+// new one); NULL if pinning fails.  *got receives its size.  Give it back
+// with pinned_give once no work uses it.
+void *pinned_lease(rmb_ctx ctx, size_t bytes, size_t *got);
+void pinned_give(rmb_ctx ctx, void *p, size_t bytes);
 
 // Host-side checks of a system description.  need_bodies: body_off and q
 // must describe n_bodies bodies covering all blobs.

@@ -48,15 +48,15 @@ static double now_s() {
 
 static size_t al(size_t x) { return (x + 255) / 256 * 256; }
 
-// Waits for the stream by polling for up to 2 ms, then blocking: one GMRES
+// Waits for an event by polling for up to 2 ms, then blocking: one GMRES
 // step takes well under that, and polling avoids the blocking wait's
 // wake-up latency on every step.
-static hipError_t wait_stream(hipStream_t s) {
+static hipError_t wait_event(hipEvent_t e) {
     const double t0 = now_s();
     for (;;) {
-        const hipError_t e = hipStreamQuery(s);
-        if (e != hipErrorNotReady) return e;
-        if (now_s() - t0 > 2e-3) return hipStreamSynchronize(s);
+        const hipError_t r = hipEventQuery(e);
+        if (r != hipErrorNotReady) return r;
+        if (now_s() - t0 > 2e-3) return hipEventSynchronize(e);
     }
 }
 
@@ -214,6 +214,7 @@ struct Job {
     double bnorm = 0, rel = 1, target = 0;
     bool cycle_fp32 = false;
     bool step_fp32 = false;  // relaxed precision: the next product in FP32
+    double est = 0, est_prev = 0;  // the cycle's last two residual estimates
     std::vector<double> R, cs, sn, g, y;
     rmb_status status = RMB_OK;
     std::string msg;
@@ -289,11 +290,23 @@ struct Engine {
     std::deque<Job *> done;
     // mailbox: per slot, [flag word][hcol: restart + 2 doubles]
     static constexpr int kSlot = 260;
-    double *mbox_d = nullptr, *mbox_h = nullptr;
+    double *mbox_d = nullptr, *mbox_h = nullptr;  // mbox_h: the host copy being read
+    double *mbox_hp[2] = {nullptr, nullptr};     // host copies, one per tick buffer
+    size_t mbox_hbytes[2] = {0, 0}, stage_hbytes[2] = {0, 0};  // sizes of the leased host buffers
+    hipEvent_t tick_ev[2] = {nullptr, nullptr};  // end of the tick using buffer 0 / 1
     std::vector<int> free_slots;
     // staging
     Staging st;
-    char *stage_h = nullptr, *stage_d = nullptr;
+    char *stage_hp[2] = {nullptr, nullptr}, *stage_d = nullptr;  // host staging, one per tick buffer
+    // A lone job in the Arnoldi phase runs one step ahead: the next step is
+    // enqueued before the current one's results are read, so the GPU does
+    // not wait for the host.  If the current step ends the cycle, the
+    // speculative one is ignored (its products are not counted); stream
+    // order keeps the work that follows correct.
+    bool spec_live = false;
+    Job *spec_job = nullptr;
+    int spec_k = -1, spec_par = 0, last_par = 1;
+    int32_t spec_mv32 = 0, spec_mv64 = 0;
     size_t stage_cap = 0;
 
     Engine(rmb_ctx c, hipStream_t st_, int maxa) : ctx(c), s(st_), max_active(maxa) {}
@@ -303,15 +316,23 @@ struct Engine {
         for (Job *j : queue) delete j;
         for (Job *j : done) delete j;
         if (mbox_d) ctx->arena->free(mbox_d);
-        if (mbox_h) (void)hipHostFree(mbox_h);
+        for (int b = 0; b < 2; ++b) {
+            pinned_give(ctx, mbox_hp[b], mbox_hbytes[b]);
+            pinned_give(ctx, stage_hp[b], stage_hbytes[b]);
+            if (tick_ev[b]) (void)hipEventDestroy(tick_ev[b]);
+        }
         if (stage_d) ctx->arena->free(stage_d);
-        if (stage_h) (void)hipHostFree(stage_h);
     }
 
     rmb_status init() {
         mbox_d = (double *)ctx->arena->alloc((size_t)max_active * kSlot * 8);
         if (!mbox_d) return fail(ctx, RMB_ENOMEM, "server mailbox does not fit the budget");
-        RMB_HIP(ctx, hipHostMalloc(&mbox_h, (size_t)max_active * kSlot * 8, hipHostMallocDefault));
+        for (int b = 0; b < 2; ++b) {
+            mbox_hp[b] = (double *)pinned_lease(ctx, (size_t)max_active * kSlot * 8, &mbox_hbytes[b]);
+            if (!mbox_hp[b]) return fail(ctx, RMB_EDEVICE, "pinned host mailbox allocation failed");
+            RMB_HIP(ctx, hipEventCreateWithFlags(&tick_ev[b], hipEventDisableTiming));
+        }
+        mbox_h = mbox_hp[0];
         for (int i = max_active - 1; i >= 0; --i) free_slots.push_back(i);
         return RMB_OK;
     }
@@ -439,14 +460,22 @@ struct Engine {
             d = (char *)ctx->arena->alloc(want);
         }
         if (!d) return false;
-        char *h = nullptr;
-        if (hipHostMalloc(&h, want, hipHostMallocDefault) != hipSuccess) {
-            ctx->arena->free(d);
-            return false;
-        }
+        char *h[2] = {nullptr, nullptr};
+        size_t hb[2] = {0, 0};
+        for (int b = 0; b < 2; ++b)
+            if (!(h[b] = (char *)pinned_lease(ctx, want, &hb[b]))) {
+                if (h[0]) pinned_give(ctx, h[0], hb[0]);
+                ctx->arena->free(d);
+                return false;
+            }
+        (void)hipStreamSynchronize(s);  // a tick in flight may still read the old buffers
         if (stage_d) ctx->arena->free(stage_d);
-        if (stage_h) (void)hipHostFree(stage_h);
-        stage_d = d, stage_h = h, stage_cap = want;
+        for (int b = 0; b < 2; ++b) {
+            pinned_give(ctx, stage_hp[b], stage_hbytes[b]);
+            stage_hp[b] = h[b];
+            stage_hbytes[b] = hb[b];
+        }
+        stage_d = d, stage_cap = want;
         return true;
     }
     rmb_status ensure_stage(size_t bytes) {
@@ -470,6 +499,7 @@ struct Engine {
         J->cycle_fp32 = J->prec == RMB_PREC_FP32_PAIRS;
         J->target = J->cycle_fp32 ? std::max(J->inner_tol * beta, 0.5 * J->tol * J->bnorm) : J->tol * J->bnorm;
         J->step_fp32 = relaxed_fp32(J, beta);
+        J->est = beta, J->est_prev = 0;
         J->R.assign((size_t)J->m * J->m, 0.0);
         J->cs.assign(J->m, 0.0);
         J->sn.assign(J->m, 0.0);
@@ -493,17 +523,73 @@ struct Engine {
     }
 
     // ---------------------------------------------------------------------
+    // Speculation pays only if the step in flight is unlikely to end the
+    // cycle: the residual estimate falls roughly geometrically, so the step
+    // is skipped when the last reduction ratio predicts the target within a
+    // factor 1.5.
+    static bool can_speculate(const Job *J) {
+        if (!(J->phase == ITER && J->k + 1 < J->m && J->iters + 1 < J->max_iters &&
+              (J->prec != RMB_PREC_RELAXED || J->step_fp32)))
+            return false;
+        const double rho = J->est_prev > 0 ? J->est / J->est_prev : 1.0;
+        return J->est * rho > 1.5 * J->target;
+    }
+
     rmb_status step() {
+        if (spec_live) {
+            Job *J = spec_job;
+            const bool valid = J->phase == ITER && J->k == spec_k;
+            if (valid && !(active.size() == 1 && queue.empty())) {
+                // other work arrived: finish the step already in flight on its own
+                spec_live = false;
+                J->mv32 += spec_mv32, J->mv64 += spec_mv64;
+                std::vector<Job *> none, it{J};
+                RMB_TRY(complete(none, none, it, spec_par));
+                return finalize_done();
+            }
+            if (!valid) spec_live = false;  // ignored; later work is stream-ordered after it
+        }
         admit();
         if (active.empty()) return RMB_OK;
-        st.reset();
-
-        std::vector<Job *> setup, finish, iter, resid;
+        std::vector<Job *> setup, finish, iter;
         for (Job *J : active) {
             if (J->phase == SETUP) setup.push_back(J);
             else if (J->phase == FINISH) finish.push_back(J);
             else if (J->phase == ITER) iter.push_back(J);
         }
+        // this tick: the speculative step already in flight, or a new launch
+        int par;
+        if (spec_live) {
+            par = spec_par;
+            spec_live = false;
+            spec_job->mv32 += spec_mv32, spec_job->mv64 += spec_mv64;
+        } else {
+            par = 1 - last_par;
+            RMB_TRY(launch(setup, finish, iter, par, 0));
+            last_par = par;
+        }
+        // a lone Arnoldi job: enqueue its next step before reading this one
+        if (active.size() == 1 && queue.empty() && iter.size() == 1 && can_speculate(iter[0])) {
+            std::vector<Job *> none, it{iter[0]};
+            spec_mv32 = spec_mv64 = 0;
+            RMB_TRY(launch(none, none, it, 1 - par, 1));
+            last_par = 1 - par;
+            spec_live = true, spec_job = iter[0], spec_k = iter[0]->k + 1, spec_par = 1 - par;
+        }
+        RMB_TRY(complete(setup, finish, iter, par));
+        if (spec_live && !(spec_job->phase == ITER && spec_job->k == spec_k)) spec_live = false;
+        return finalize_done();
+    }
+
+    // Enqueues one tick for the given jobs: descriptor tables (through host
+    // staging buffer `par`), every launch, and the copy of the mailbox into
+    // host buffer `par`, followed by tick_ev[par].  koff = 1 builds the
+    // Arnoldi jobs' step for index k + 1 (a speculative step; its products
+    // are counted apart until it is accepted).
+    rmb_status launch(std::vector<Job *> &setup, std::vector<Job *> &finish, std::vector<Job *> &iter, int par,
+                      int koff) {
+        st.reset();
+
 
         // --- descriptor tables ------------------------------------------
         // precond build items (setup jobs without external factors)
@@ -560,7 +646,7 @@ struct Engine {
             }
         };
         for (Job *J : finish) add_app(J, J->z, J->w);
-        for (Job *J : iter) add_app(J, J->V + (size_t)J->k * J->ldv, J->z);
+        for (Job *J : iter) add_app(J, J->V + (size_t)(J->k + koff) * J->ldv, J->z);
 
         // matvec operands: iter (z, its cycle precision), finish/resid (x, FP64)
         std::vector<Job *> mv = iter;
@@ -642,7 +728,8 @@ struct Engine {
             sd.push_back(sj);
             wg_sd_blob += J->sym ? 0 : (J->nb + 255) / 256;  // symmetric: rows written by the reduction
             wg_sd_body += J->resist ? 0 : J->N;
-            if (f32) J->mv32++; else J->mv64++;
+            if (koff) (f32 ? spec_mv32 : spec_mv64)++;
+            else if (f32) J->mv32++; else J->mv64++;
         }
 
         // orthogonalisation / normalisation: iter (kk = k+1), finish->resid
@@ -668,7 +755,8 @@ struct Engine {
             wg += J->nseg;
             return K;
         };
-        for (Job *J : iter) orth.push_back(kj(J, J->w, J->k + 1, J->V + (size_t)(J->k + 1) * J->ldv, wg_orth));
+        for (Job *J : iter)
+            orth.push_back(kj(J, J->w, J->k + koff + 1, J->V + (size_t)(J->k + koff + 1) * J->ldv, wg_orth));
         for (Job *J : finish) orth.push_back(kj(J, J->w, 0, J->V, wg_orth));
         for (Job *J : setup) orth.push_back(kj(J, J->b, 0, J->V, wg_orth));
         // finish: combine then axpy tables
@@ -712,8 +800,8 @@ struct Engine {
         if (!comb.empty()) o_comb = st.put(comb.data(), comb.size() * sizeof(KrylovJob));
         if (!sred.empty()) o_sred = st.put(sred.data(), sred.size() * sizeof(SymJob));
         RMB_TRY(ensure_stage(st.used));
-        memcpy(stage_h, st.host.data(), st.used);
-        RMB_HIP(ctx, hipMemcpyAsync(stage_d, stage_h, st.used, hipMemcpyHostToDevice, s));
+        memcpy(stage_hp[par], st.host.data(), st.used);
+        RMB_HIP(ctx, hipMemcpyAsync(stage_d, stage_hp[par], st.used, hipMemcpyHostToDevice, s));
         auto D = [&](size_t o) { return (void *)(stage_d + o); };
 
         // --- launches -------------------------------------------------------
@@ -774,8 +862,16 @@ struct Engine {
             RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));
         if (!orth.empty())
             RMB_HIP(ctx, launch_orthogonalise((const KrylovJob *)D(o_orth), (int32_t)orth.size(), wg_orth, s));
-        RMB_HIP(ctx, hipMemcpyAsync(mbox_h, mbox_d, (size_t)max_slot * kSlot * 8, hipMemcpyDeviceToHost, s));
-        RMB_HIP(ctx, wait_stream(s));
+        RMB_HIP(ctx, hipMemcpyAsync(mbox_hp[par], mbox_d, (size_t)max_slot * kSlot * 8, hipMemcpyDeviceToHost, s));
+        RMB_HIP(ctx, hipEventRecord(tick_ev[par], s));
+        return RMB_OK;
+    }
+
+    // Waits for the tick that used buffer `par` and applies its results on
+    // the host (Givens rotations, convergence tests, next phases).
+    rmb_status complete(std::vector<Job *> &setup, std::vector<Job *> &finish, std::vector<Job *> &iter, int par) {
+        RMB_HIP(ctx, wait_event(tick_ev[par]));
+        mbox_h = mbox_hp[par];
         if (ctx->timing) resolve_timing(ctx, false);
 
         // --- host updates -------------------------------------------------
@@ -824,6 +920,7 @@ struct Engine {
             J->k = k + 1;
             J->iters++;
             J->step_fp32 = relaxed_fp32(J, std::fabs(J->g[J->k]));
+            J->est_prev = J->est, J->est = std::fabs(J->g[J->k]);
             const bool lucky = !(h[k + 1] > 1e-300 * std::max(1.0, J->bnorm));
             if (breakdown || lucky || std::fabs(J->g[J->k]) <= J->target || J->k >= J->m || J->iters >= J->max_iters) {
                 // y = R^-1 g over the first kk columns (drop a singular last column)
@@ -839,7 +936,12 @@ struct Engine {
             }
         }
 
-        // --- completion ------------------------------------------------------
+        return RMB_OK;
+    }
+
+    // Hands finished jobs back: outputs copied, stream drained (a
+    // speculative step may still be running), buffers released.
+    rmb_status finalize_done() {
         std::vector<Job *> fin;
         for (Job *J : active)
             if (J->phase == DONE) fin.push_back(J);
