@@ -333,7 +333,7 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
         *hJ = J;
         RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(SymJob), hipMemcpyHostToDevice, s));
         RMB_TRY(sym_launch(ctx, precision, wall, J.B, (const SymJob *)(base + off_job), 1, tiles, s));
-        RMB_HIP(ctx, launch_sym_reduce((const SymJob *)(base + off_job), 1, sym_reduce_groups(nb), s));
+        RMB_HIP(ctx, launch_sym_reduce((const SymJob *)(base + off_job), 1, sym_reduce_groups(nb), nullptr, 0, 0, s));
         RMB_HIP(ctx, launch_add_shift(sys->blob_shift, lambda, nb, vel, s));
         return RMB_OK;
     }

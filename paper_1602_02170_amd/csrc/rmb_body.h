@@ -108,6 +108,43 @@ __device__ __forceinline__ void saddle_blob_row(const SaddleJob &J, int64_t i, c
     }
 }
 
+// Body rows of the saddle-point operator for body w of the job list (its
+// global index over all jobs' bodies), one 64-lane wave: -K^T x, or
+// b_body + K^T x with a right-hand side.  `lane` is the wave lane 0..63.
+__device__ __forceinline__ void saddle_body_rows(const SaddleJob *__restrict__ jobs, int32_t n_jobs, int64_t w,
+                                                 int lane) {
+    int lo = 0, hi = n_jobs - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].body_begin <= w) lo = mid; else hi = mid - 1;
+    }
+    const SaddleJob &J = jobs[lo];
+    const int64_t p = w - J.body_begin;
+    const int64_t b0 = as_global(J.body_off)[p], b1 = as_global(J.body_off)[p + 1];
+    const gmem<const double> q = as_global(J.q + 3 * p);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t i = b0 + lane; i < b1; i += 64) {
+        const double l[3] = {as_global(J.x)[3 * i], as_global(J.x)[3 * i + 1], as_global(J.x)[3 * i + 2]};
+        const double d[3] = {as_global(J.pos)[3 * i] - q[0], as_global(J.pos)[3 * i + 1] - q[1],
+                             as_global(J.pos)[3 * i + 2] - q[2]};
+        acc[0] += l[0];
+        acc[1] += l[1];
+        acc[2] += l[2];
+        acc[3] += d[1] * l[2] - d[2] * l[1];
+        acc[4] += d[2] * l[0] - d[0] * l[2];
+        acc[5] += d[0] * l[1] - d[1] * l[0];
+    }
+    for (int k = 0; k < 6; ++k) {
+        double v = acc[k];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        acc[k] = v;
+    }
+    if (lane == 0) {
+        const int64_t o = 3 * J.nb + 6 * p;
+        for (int k = 0; k < 6; ++k) as_global(J.y)[o + k] = J.b ? as_global(J.b)[o + k] + acc[k] : -acc[k];
+    }
+}
+
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s);
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s);

@@ -118,7 +118,11 @@ constexpr int64_t kSymMinBlobs = 1024;
 inline bool use_sym(int64_t nb) { return nb >= kSymMinBlobs; }
 hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs, int64_t n_tiles,
                            hipStream_t s);
-hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+// n_wg reduction workgroups, then (n_body + 3) / 4 more for the saddle body
+// rows of `sd` (none when sd is null).
+struct SaddleJob;
+hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, const SaddleJob *sd, int32_t n_sd,
+                             int64_t n_body, hipStream_t s);
 
 // Packing of source records for several systems in one launch.
 struct PackJob {

@@ -856,7 +856,13 @@ struct Engine {
                             RMB_TRY(sym_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0, Bs[c],
                                                (const SymJob *)D(o_sym[a][b][c]), (int32_t)syms[a][b][c].size(),
                                                stiles[a][b][c], s));
-            if (!sred.empty()) RMB_HIP(ctx, launch_sym_reduce((const SymJob *)D(o_sred), (int32_t)sred.size(), wg_sred, s));
+            // the saddle body rows ride on the reduction launch when there is one
+            if (!sred.empty()) {
+                RMB_HIP(ctx, launch_sym_reduce((const SymJob *)D(o_sred), (int32_t)sred.size(), wg_sred,
+                                               sd.empty() ? nullptr : (const SaddleJob *)D(o_sd), (int32_t)sd.size(),
+                                               wg_sd_body, s));
+                wg_sd_body = 0;
+            }
         }
         if (!sd.empty())
             RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));

@@ -571,9 +571,19 @@ hipError_t launch_pair_lds_f32(bool wall, const PairJob *jobs, int32_t n_jobs, i
 // the 16 partial sums are added in the order q = 0..15.
 constexpr int kRedBlobs = 16, kRedParts = 16;
 
-__global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs) {
+// Workgroups past n_red carry the saddle body rows of a solve step (four
+// bodies per workgroup, a wave each): they read only the Krylov vector, so
+// they share the launch with the reduction instead of taking one of their own.
+__global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs,
+                                                         int64_t n_red, const SaddleJob *__restrict__ sd,
+                                                         int32_t n_sd, int64_t n_body) {
     __shared__ double part[kRedParts][kRedBlobs][3];
     const int64_t w = blockIdx.x;
+    if (w >= n_red) {
+        const int64_t body = (w - n_red) * 4 + threadIdx.x / 64;
+        if (body < n_body) saddle_body_rows(sd, n_sd, body, threadIdx.x % 64);
+        return;
+    }
     int lo = 0, hi = n_jobs - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -667,9 +677,13 @@ hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, 
     return hipGetLastError();
 }
 
-hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s) {
-    if (n_wg <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)n_wg), dim3(256), 0, s, jobs, n_jobs);
+hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, const SaddleJob *sd, int32_t n_sd,
+                             int64_t n_body, hipStream_t s) {
+    if (!sd || n_sd <= 0) n_body = 0;
+    const int64_t total = n_wg + (n_body + 3) / 4;
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, n_jobs, n_wg, sd, n_sd,
+                       n_body);
     return hipGetLastError();
 }
 
