@@ -43,6 +43,13 @@ def _cases():
     out.append(("wall 203 boomerangs", s2, np.random.default_rng(12).standard_normal((s2.n_blobs, 3))))
     s3, l3 = S.icosahedra_monolayer(n_bodies=1100)  # 13200 blobs
     out.append(("wall monolayer 1100 icosahedra", s3, l3))
+    # 11655 blobs: 183 blocks of 64, the last one holding 7; and a
+    # free-space system of 12000 blobs (both over 16,000 tiles)
+    s4 = S.boomerangs_wall(n_bodies=777, lateral=np.sqrt(40 * 777), seed=21)
+    out.append(("wall 777 boomerangs ragged", s4, np.random.default_rng(22).standard_normal((s4.n_blobs, 3))))
+    s5 = S.boomerangs_wall(n_bodies=800, lateral=np.sqrt(40 * 800), seed=23)
+    s5.wall = False
+    out.append(("free 800 boomerangs", s5, np.random.default_rng(24).standard_normal((s5.n_blobs, 3))))
     return out
 
 
