@@ -168,12 +168,16 @@ struct VOp<double> {
 // Coefficients of one pair block, shared by both contractions:
 //   M_ij f   = A f + Bv (r . f) r + W f,   W f = c1 f + (c2 (e.f) + c3 f_z) e + (c4 (e.f) + c5 f_z) z
 //   M_ij^T f = A f + Bv (r . f) r + c1 f + (c2 (e.f) + c4 f_z) e + (c3 (e.f) + c5 f_z) z
+// with e = R / L.  The contractions take R . f unnormalised, so the stored
+// image coefficients are c2 / L^2, c3 / L and c4 / L; and since R = r + 2 z_j z,
+// the e-term shares the direction r with the RPY term in x and y, the z row
+// taking the rest as g 2 z_j.
 template <typename R, bool WALL>
 struct PairCoef {
     using P = VOp<R>;
-    R iso, crr;                  // ciso + c1 (ciso alone in free space), and crr: ciso I + crr r r^T
-    R c2, c3, c4, c5, invL;      // wall image (R = (rx, ry, Rz), e = R invL)
-    R Rz;
+    R iso, crr;              // ciso + c1 (ciso alone in free space), and crr: ciso I + crr r r^T
+    R c2L, c3L, c4L, c5;     // wall image: c2 / L^2, c3 / L, c4 / L, c5
+    R Rz, zj2;               // R_z = r_z + 2 z_j, and 2 z_j
 
     // NEAR_POSSIBLE = false: the caller knows r > 2a (far branch only).
     template <bool NEAR_POSSIBLE = true>
@@ -184,7 +188,9 @@ struct PairCoef {
     }
     template <bool NEAR_POSSIBLE>
     __device__ __forceinline__ void eval_d2(R rxy2, R d2, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
-        const R inv_d = rsqrt_r(d2 + tiny);
+        // r = 0 (a blob with itself) only on the near branch; the far one has
+        // d2 > 4 a^2
+        const R inv_d = rsqrt_r(NEAR_POSSIBLE ? d2 + tiny : d2);
         const R t = P::mul(a, inv_d);
         const R t2 = P::mul(t, t);
         const R iso_far = P::mul(t, (R)0.5 * t2 + (R)0.75);
@@ -200,23 +206,26 @@ struct PairCoef {
             crr = near ? rr_near : rr_far;
         }
         if (WALL) {
-            Rz = (R)2 * zj + rz;
+            zj2 = zj + zj;
+            Rz = zj2 + rz;
             const R L2 = P::fma(Rz, Rz, rxy2);
-            invL = rsqrt_r(L2);
+            const R invL = rsqrt_r(L2);
             const R xw = P::mul(a, invL), hh = P::mul(zj, invL), ez = P::mul(Rz, invL);
             const R xw2 = P::mul(xw, xw), xw4 = P::mul(xw2, xw2), ez2 = P::mul(ez, ez);
             const R hh2 = P::mul(hh, hh), ezh = P::mul(ez, hh);
             const R T = P::sub(hh2, ezh);
-            const R xq = (R)0.25 * xw;
-            const R c1 = P::mul(xq, P::fma(xw4, (R)-10 * ez2 + (R)2, P::fma(xw2, (R)6 * ez2 - (R)2, (R)6 * T - (R)3)));
-            c2 = P::mul(xq, P::fma(xw4, (R)70 * ez2 - (R)10, P::fma(xw2, (R)-30 * ez2 + (R)6, (R)-18 * T - (R)3)));
+            const R xwL = P::mul(xw, invL), xwLL = P::mul(xwL, invL);
+            // c1 and c2 carry xi / 4, folded into their polynomials
+            iso = P::fma(xw, P::fma(xw4, (R)-2.5 * ez2 + (R)0.5, P::fma(xw2, (R)1.5 * ez2 - (R)0.5, (R)1.5 * T - (R)0.75)),
+                         ciso);
+            c2L = P::mul(xwLL,
+                         P::fma(xw4, (R)17.5 * ez2 - (R)2.5, P::fma(xw2, (R)-7.5 * ez2 + (R)1.5, (R)-4.5 * T - (R)0.75)));
             const R hh15 = (R)1.5 * hh;
             const R m3 = P::mul(hh15, (R)-6 * ez2 + ((R)6 * ezh + (R)1));
             const R e3 = P::fma(xw4, (R)-35 * ez2 + (R)10, P::mul(xw2, (R)15 * ez2 - (R)3));
-            c3 = P::mul(xw, P::fma(ez, e3, m3));
-            c4 = P::mul(xw, P::fma((R)-5 * ez, xw4, hh15));
+            c3L = P::mul(xwL, P::fma(ez, e3, m3));
+            c4L = P::mul(xwL, P::fma((R)-5 * ez, xw4, hh15));
             c5 = P::mul(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)));
-            iso = P::add(ciso, c1);
         } else {
             iso = ciso;
         }
@@ -225,20 +234,20 @@ struct PairCoef {
     template <bool TRANSPOSE>
     __device__ __forceinline__ void apply(R rx, R ry, R rz, R fx, R fy, R fz, R &ox, R &oy, R &oz) const {
         const R pxy = P::fma(ry, fy, P::mul(rx, fx));
-        const R sr = P::mul(crr, P::fma(rz, fz, pxy));
+        const R rf = P::fma(rz, fz, pxy);
         if (!WALL) {
+            const R sr = P::mul(crr, rf);
             ox = P::fma(iso, fx, P::fma(sr, rx, ox));
             oy = P::fma(iso, fy, P::fma(sr, ry, oy));
             oz = P::fma(iso, fz, P::fma(sr, rz, oz));
         } else {
-            const R ef = P::mul(P::fma(Rz, fz, pxy), invL);
-            const R ce = TRANSPOSE ? c4 : c3, cz = TRANSPOSE ? c3 : c4;
-            const R g = P::mul(P::fma(c2, ef, P::mul(ce, fz)), invL);
-            const R kz = P::fma(cz, ef, P::mul(c5, fz));
-            const R gr = P::add(sr, g);
+            const R Rf = P::fma(Rz, fz, pxy);
+            const R ce = TRANSPOSE ? c4L : c3L, cz = TRANSPOSE ? c3L : c4L;
+            const R g = P::fma(c2L, Rf, P::mul(ce, fz));
+            const R gr = P::fma(crr, rf, g);
             ox = P::fma(iso, fx, P::fma(gr, rx, ox));
             oy = P::fma(iso, fy, P::fma(gr, ry, oy));
-            oz = P::fma(iso, fz, P::fma(sr, rz, P::fma(g, Rz, P::add(oz, kz))));
+            oz = P::fma(iso, fz, P::fma(gr, rz, P::fma(g, zj2, P::fma(cz, Rf, P::fma(c5, fz, oz)))));
         }
     }
 };
