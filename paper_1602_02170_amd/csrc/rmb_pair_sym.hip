@@ -118,6 +118,14 @@ __device__ __forceinline__ float rsqrt_r(float x) {
 }
 __device__ __forceinline__ double rsqrt_r(double x) { return rsqrt64(x); }
 
+// x + y, not moved out of the branch it is written in.
+__device__ __forceinline__ float add_in_place(float x, float y) {
+    float d;
+    asm volatile("v_add_f32_e64 %0, %1, %2" : "=v"(d) : "v"(x), "v"(y));
+    return d;
+}
+__device__ __forceinline__ double add_in_place(double x, double y) { return x + y; }
+
 // Arithmetic between two or three register operands.  On gfx950 the
 // two-VGPR-source VOP2 encodings of v_mul/v_add/v_sub/v_fmac_f32 issue at
 // about 21 lanes per clock per SIMD, while the same operations in VOP3
@@ -176,7 +184,7 @@ template <typename R, bool WALL>
 struct PairCoef {
     using P = VOp<R>;
     R iso, crr;              // ciso + c1 (ciso alone in free space), and crr: ciso I + crr r r^T
-    R c2L, c3L, c4L, c5;     // wall image: c2 / L^2, c3 / L, c4 / L, c5
+    R c2L, c3L, c4L, isoz;   // wall image: c2 / L^2, c3 / L, c4 / L; isoz = iso + c5 (the z-z diagonal)
     R Rz, zj2;               // R_z = r_z + 2 z_j, and 2 z_j
 
     // NEAR_POSSIBLE = false: the caller knows r > 2a (far branch only).
@@ -189,8 +197,9 @@ struct PairCoef {
     template <bool NEAR_POSSIBLE>
     __device__ __forceinline__ void eval_d2(R rxy2, R d2, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
         // r = 0 (a blob with itself) only on the near branch; the far one has
-        // d2 > 4 a^2
-        const R inv_d = rsqrt_r(NEAR_POSSIBLE ? d2 + tiny : d2);
+        // d2 > 4 a^2.  The guard is added in a form the compiler keeps inside
+        // the near branch (hoisted, it would cost the far steps too).
+        const R inv_d = rsqrt_r(NEAR_POSSIBLE ? add_in_place(d2, tiny) : d2);
         const R t = P::mul(a, inv_d);
         const R t2 = P::mul(t, t);
         const R iso_far = P::mul(t, (R)0.5 * t2 + (R)0.75);
@@ -225,7 +234,7 @@ struct PairCoef {
             const R e3 = P::fma(xw4, (R)-35 * ez2 + (R)10, P::mul(xw2, (R)15 * ez2 - (R)3));
             c3L = P::mul(xwL, P::fma(ez, e3, m3));
             c4L = P::mul(xwL, P::fma((R)-5 * ez, xw4, hh15));
-            c5 = P::mul(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)));
+            isoz = P::fma(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)), iso);
         } else {
             iso = ciso;
         }
@@ -247,7 +256,7 @@ struct PairCoef {
             const R gr = P::fma(crr, rf, g);
             ox = P::fma(iso, fx, P::fma(gr, rx, ox));
             oy = P::fma(iso, fy, P::fma(gr, ry, oy));
-            oz = P::fma(iso, fz, P::fma(gr, rz, P::fma(g, zj2, P::fma(cz, Rf, P::fma(c5, fz, oz)))));
+            oz = P::fma(isoz, fz, P::fma(gr, rz, P::fma(g, zj2, P::fma(cz, Rf, oz))));
         }
     }
 };
