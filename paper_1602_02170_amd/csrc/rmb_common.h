@@ -91,8 +91,8 @@ hipError_t launch_pack_sub_sources(int precision, const double *pos, const doubl
 struct SymJob {
     const double *tpos;  // [nb][3] positions
     const double *lam;   // [nb][3] operand (the target's own force for M^T lambda)
-    double *vpart;       // [tiles][B][3] target-side sums (FP32 pairs: floats at the same base)
-    double *upart;       // [tiles][B][3] source-side sums (likewise)
+    double *vpart;       // [tiles][3][B] target-side sums (FP32 pairs: floats at the same base)
+    double *upart;       // [tiles][3][B] source-side sums (likewise)
     double *vel;         // [nb][3] result, prefactor applied (unused with epi)
     const void *epi;     // NULL, or the system's saddle-operator rows (a SaddleJob): the
                          // reduction then writes the blob rows of A x (or b - A x) instead of vel
@@ -118,8 +118,9 @@ constexpr int64_t kSymMinBlobs = 1024;
 inline bool use_sym(int64_t nb) { return nb >= kSymMinBlobs; }
 hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs, int64_t n_tiles,
                            hipStream_t s);
-// n_wg reduction workgroups, then (n_body + 3) / 4 more for the saddle body
-// rows of `sd` (none when sd is null).
+// n_wg reduction workgroups (sym_reduce_groups per job), then
+// (n_body + 15) / 16 more for the saddle body rows of `sd` (none when sd is
+// null).
 struct SaddleJob;
 hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, const SaddleJob *sd, int32_t n_sd,
                              int64_t n_body, hipStream_t s);

@@ -469,10 +469,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
             vz += (double)az;
         }
         if (active) {
-            const gmem<R> o = vout + (sub * 64 + lane) * 3;
-            o[0] = (R)vx;
-            o[1] = (R)vy;
-            o[2] = (R)vz;
+            const int e = sub * 64 + lane;
+            vout[e] = (R)vx;
+            vout[B + e] = (R)vy;
+            vout[2 * B + e] = (R)vz;
         }
     }
     if (!diag) {
@@ -480,10 +480,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         for (int g = 0; g < G; ++g) {
             const int64_t j = s0 + 64 * g + lane;
             if (j < s1) {
-                const gmem<R> o = uout + (64 * g + lane) * 3;
-                o[0] = (R)u64[g][0];
-                o[1] = (R)u64[g][1];
-                o[2] = (R)u64[g][2];
+                const int e = 64 * g + lane;
+                uout[e] = (R)u64[g][0];
+                uout[B + e] = (R)u64[g][1];
+                uout[2 * B + e] = (R)u64[g][2];
             }
         }
     }
@@ -587,19 +587,24 @@ hipError_t launch_pair_lds_f32(bool wall, const PairJob *jobs, int32_t n_jobs, i
 // A workgroup covers 16 blobs with 16 threads each: thread (q, b) sums the
 // contributions q, q+16, q+32, ... of blob b (in the order listed above), and
 // the 16 partial sums are added in the order q = 0..15.
-constexpr int kRedBlobs = 16, kRedParts = 16;
+constexpr int kRedWaves = 16;
 
-// Workgroups past n_red carry the saddle body rows of a solve step (four
-// bodies per workgroup, a wave each): they read only the Krylov vector, so
-// they share the launch with the reduction instead of taking one of their own.
-__global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs,
-                                                         int64_t n_red, const SaddleJob *__restrict__ sd,
-                                                         int32_t n_sd, int64_t n_body) {
-    __shared__ double part[kRedParts][kRedBlobs][3];
+// One workgroup of 16 waves per 64 blobs of a block: wave q adds the blobs'
+// contributions q, q + 16, ... (row tiles, then column tiles), each read as
+// one row of 64 consecutive values per component of the [tile][3][B]
+// partials; the waves' sums are then added in a fixed order.  Workgroups
+// past n_red carry the saddle body rows of a solve step (16 bodies per
+// workgroup, a wave each): they read only the Krylov vector, so they share
+// the launch with the reduction instead of taking one of their own.
+__global__ __launch_bounds__(1024) void sym_reduce_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs,
+                                                          int64_t n_red, const SaddleJob *__restrict__ sd,
+                                                          int32_t n_sd, int64_t n_body) {
+    __shared__ double part[kRedWaves][3][64];
     const int64_t w = blockIdx.x;
+    const int q = threadIdx.x / 64, lane = threadIdx.x % 64;
     if (w >= n_red) {
-        const int64_t body = (w - n_red) * 4 + threadIdx.x / 64;
-        if (body < n_body) saddle_body_rows(sd, n_sd, body, threadIdx.x % 64);
+        const int64_t body = (w - n_red) * kRedWaves + q;
+        if (body < n_body) saddle_body_rows(sd, n_sd, body, lane);
         return;
     }
     int lo = 0, hi = n_jobs - 1;
@@ -608,36 +613,36 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
         if (jobs[mid].red_begin <= w) lo = mid; else hi = mid - 1;
     }
     const SymJob &J = jobs[lo];
-    const int b = threadIdx.x % kRedBlobs, q = threadIdx.x / kRedBlobs;
-    const int64_t k = (w - J.red_begin) * kRedBlobs + b;
+    const int32_t B = J.B, T = J.n_blk;
+    const int64_t k0 = (w - J.red_begin) * 64;  // groups of 64 never straddle a block (B is a multiple of 64)
+    const int64_t k = k0 + lane;
+    const int32_t K = (int32_t)(k0 / B);
+    const int64_t kk = k0 % B + lane;
     double s[3] = {0.0, 0.0, 0.0};
     if (k < J.nb) {
-        const int32_t B = J.B, T = J.n_blk;
-        const int32_t K = (int32_t)(k / B);
-        const int64_t kk = k % B;
         auto tile = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i); };
         const int32_t nv = T - K;  // vpart contributions, then K upart ones
         if (J.f32) {
 #pragma unroll 4
-            for (int32_t c = q; c < T; c += kRedParts) {
-                const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + (tile(K, K + c) * B + kk) * 3
-                                                             : (const float *)J.upart + (tile(c - nv, K) * B + kk) * 3);
-                s[0] += (double)p[0], s[1] += (double)p[1], s[2] += (double)p[2];
+            for (int32_t c = q; c < T; c += kRedWaves) {
+                const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + tile(K, K + c) * B * 3 + kk
+                                                             : (const float *)J.upart + tile(c - nv, K) * B * 3 + kk);
+                s[0] += (double)p[0], s[1] += (double)p[B], s[2] += (double)p[2 * B];
             }
         } else {
 #pragma unroll 4
-            for (int32_t c = q; c < T; c += kRedParts) {
-                const gmem<const double> p = as_global(c < nv ? J.vpart + (tile(K, K + c) * B + kk) * 3
-                                                              : J.upart + (tile(c - nv, K) * B + kk) * 3);
-                s[0] += p[0], s[1] += p[1], s[2] += p[2];
+            for (int32_t c = q; c < T; c += kRedWaves) {
+                const gmem<const double> p = as_global(c < nv ? J.vpart + tile(K, K + c) * B * 3 + kk
+                                                              : J.upart + tile(c - nv, K) * B * 3 + kk);
+                s[0] += p[0], s[1] += p[B], s[2] += p[2 * B];
             }
         }
     }
-    part[q][b][0] = s[0], part[q][b][1] = s[1], part[q][b][2] = s[2];
+    part[q][0][lane] = s[0], part[q][1][lane] = s[1], part[q][2][lane] = s[2];
     __syncthreads();
     if (q == 0 && k < J.nb) {
         double t[3] = {0.0, 0.0, 0.0};
-        for (int r = 0; r < kRedParts; ++r) t[0] += part[r][b][0], t[1] += part[r][b][1], t[2] += part[r][b][2];
+        for (int r = 0; r < kRedWaves; ++r) t[0] += part[r][0][lane], t[1] += part[r][1][lane], t[2] += part[r][2][lane];
         const double v[3] = {J.pref * t[0], J.pref * t[1], J.pref * t[2]};
         if (J.epi) {
             // inside a solve: the blob rows of the saddle-point operator
@@ -651,7 +656,7 @@ __global__ __launch_bounds__(256) void sym_reduce_kernel(const SymJob *__restric
     }
 }
 
-int64_t sym_reduce_groups(int64_t nb) { return (nb + kRedBlobs - 1) / kRedBlobs; }
+int64_t sym_reduce_groups(int64_t nb) { return (nb + 63) / 64; }
 
 void sym_plan(int64_t nb, int32_t *B, int32_t *n_blk) {
     int32_t b = nb <= 16384 ? 64 : nb <= 65536 ? 128 : nb <= 262144 ? 256 : 512;
@@ -698,10 +703,10 @@ hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, 
 hipError_t launch_sym_reduce(const SymJob *jobs, int32_t n_jobs, int64_t n_wg, const SaddleJob *sd, int32_t n_sd,
                              int64_t n_body, hipStream_t s) {
     if (!sd || n_sd <= 0) n_body = 0;
-    const int64_t total = n_wg + (n_body + 3) / 4;
+    const int64_t total = n_wg + (n_body + kRedWaves - 1) / kRedWaves;
     if (total <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)total), dim3(256), 0, s, jobs, n_jobs, n_wg, sd, n_sd,
-                       n_body);
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)total), dim3(64 * kRedWaves), 0, s, jobs, n_jobs, n_wg, sd,
+                       n_sd, n_body);
     return hipGetLastError();
 }
 
