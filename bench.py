@@ -429,6 +429,35 @@ def cpu_baseline(S, sus):
                       f"{calls[0]} products of {sus.n_blobs}^2 pairs, {dt:.1f} s"}
 
 
+def cpu_samples(S):
+    """The oracle on bounded samples of the other workloads, beside the GPU
+    figures: the product over a 24,576-blob prefix of the 196,608-blob
+    monolayer, and a few small requests of the serving stream solved one at
+    a time (FP64 GMRES to 1e-8)."""
+    import oracle
+    mono, lam = S.icosahedra_monolayer()
+    n = 24576  # a prefix of the monolayer, one of the GPU sweep's sizes
+    t = time.perf_counter()
+    oracle.matvec(mono.pos[:n], lam[:n], mono.a, mono.eta, mono.wall)
+    dtm = time.perf_counter() - t
+    ids = [0, 1, 8, 9]
+    reqs = [S.mixed_wall_request(i) for i in ids]
+    t = time.perf_counter()
+    for r in reqs:
+        oracle.solve_mobility(r, r.FT, tol=1e-8)
+    dts = time.perf_counter() - t
+    nb = [r.n_blobs for r in reqs]
+    return {
+        "c3_matvec": {"value": n * n / dtm, "unit": "blob-pair interactions/s",
+                      "cores": oracle.num_threads(), "kind": "oracle",
+                      "sample": f"the full FP64 wall product over the first {n} blobs of the {mono.n_blobs}-blob "
+                                f"monolayer, {dtm:.2f} s"},
+        "c5_serial": {"value": len(reqs) / dts, "unit": "solves/s", "cores": oracle.num_threads(), "kind": "oracle",
+                      "sample": f"requests {ids} of the serving stream ({min(nb)}-{max(nb)} blobs) solved one at a "
+                                f"time, {dts:.2f} s"},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -550,6 +579,9 @@ def main():
         if not args.no_cpu:
             line["cpu_baseline"] = cpu_baseline(S, sus)
             log(f"  cpu oracle: {line['cpu_baseline']['value']:.3e} pairs/s on {line['cpu_baseline']['cores']} threads")
+            line["cpu_samples"] = cpu_samples(S)
+            log(f"  cpu oracle samples: monolayer rows {line['cpu_samples']['c3_matvec']['value']:.3e} pairs/s; "
+                f"small requests {line['cpu_samples']['c5_serial']['value']:.2f} solves/s")
     ctx.close()
     print(json.dumps(line), flush=True)
 
