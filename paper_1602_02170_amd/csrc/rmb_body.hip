@@ -30,6 +30,8 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     double *A = lds;              // m x m, row-major
     double *Y = A + m * m;        // m x 6
     double *S = Y + 6 * m;        // 6 x 6
+    double *Ld = S + 36;          // L's diagonal (m)
+    double *Dq = Ld + m;          // r_i - q_p per blob (m)
     __shared__ int bad;
     if (tid == 0) bad = 0;
 
@@ -68,31 +70,39 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
         __syncthreads();
     }
 
-    // 3. Li = L^-1: L goes to the factor storage, then lane c forms column c
-    //    of Li in LDS (A is overwritten; each column belongs to one lane, so
-    //    no barrier is needed inside the loop).
+    // 3. Li = L^-1, column-major in A.  Lane c forms column c below the
+    //    diagonal into A's upper triangle (A[c m + r], r > c), reading L from
+    //    the lower triangle, which no lane writes; the diagonal and the
+    //    clearing of the lower triangle follow once every column is done.
     gmem<double> out = as_global(it.factor);
-    for (int e = tid; e < m * m; e += blockDim.x) out[e] = A[e];  // row-major L (lower part)
+    const gmem<const double> q = as_global(it.q);
+    for (int c = tid; c < m; c += blockDim.x) {
+        Ld[c] = A[c * m + c];
+        Dq[c] = as_global(it.pos)[3 * (int64_t)it.blob0 + c] - q[c % 3];
+    }
     __syncthreads();
     for (int c = tid; c < m; c += blockDim.x) {
-        for (int r = 0; r < c; ++r) A[c * m + r] = 0.0;
-        A[c * m + c] = 1.0 / out[c * m + c];
+        const double lcc = 1.0 / Ld[c];
         for (int r = c + 1; r < m; ++r) {
-            double acc = 0.0;
-            for (int k = c; k < r; ++k) acc += out[r * m + k] * A[c * m + k];
-            A[c * m + r] = -acc / out[r * m + r];
+            double acc = A[r * m + c] * lcc;
+            for (int k = c + 1; k < r; ++k) acc += A[r * m + k] * A[c * m + k];
+            A[c * m + r] = -acc / Ld[r];
         }
     }
     __syncthreads();
+    for (int e = tid; e < m * m; e += blockDim.x) {
+        const int c = e / m, r = e % m;
+        if (r < c) A[e] = 0.0;
+        else if (r == c) A[e] = 1.0 / Ld[c];
+    }
+    __syncthreads();
     // 4. Y = Li K_p, S = Y^T Y
-    const gmem<const double> q = as_global(it.q);
     for (int e = tid; e < 6 * m; e += blockDim.x) {
         const int row = e / 6, k = e % 6;
         double acc = 0.0;
         for (int c = 0; c <= row; ++c) {
             const int i = c / 3, cc = c % 3;
-            const gmem<const double> ri = as_global(it.pos + 3 * (int64_t)(it.blob0 + i));
-            const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
+            const double d[3] = {Dq[3 * i], Dq[3 * i + 1], Dq[3 * i + 2]};
             acc += A[c * m + row] * K_entry(d, cc, k);
         }
         Y[row * 6 + k] = acc;
@@ -410,7 +420,7 @@ __global__ void saddle_body_kernel(const SaddleJob *__restrict__ jobs, int32_t n
 
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    size_t lds = ((size_t)max_m * max_m + 6 * (size_t)max_m + 36) * sizeof(double);
+    size_t lds = ((size_t)max_m * max_m + 8 * (size_t)max_m + 36) * sizeof(double);
     hipLaunchKernelGGL(precond_build_small_kernel, dim3(n_items), dim3(64), lds, s, items, n_items);
     return hipGetLastError();
 }
