@@ -170,6 +170,14 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // the RPY tensor and K are rotation-covariant, M_pp = R~ M_ref R~^T and
 // K_p = R~ K_ref diag(R, R)^T.
 constexpr int kApplyThreads = 256;  // four waves: more factor loads in flight per body
+constexpr int kRowLanes = 4;        // lanes per row in the triangular products
+
+// Sum over the kRowLanes adjacent lanes of a row (all lanes take part).
+__device__ __forceinline__ double sum_row_lanes(double v) {
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    return v;
+}
 
 // With `resist` (resistance problem) only lambda = M_pp^-1 s is formed:
 // bot_in and U_out are not touched.
@@ -205,23 +213,35 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         for (int e = tid; e < m; e += kApplyThreads) sv[e] = s_in[e];
     }
     __syncthreads();
+    // The triangular products give each row's sum to kRowLanes adjacent
+    // lanes (every lane runs the same iterations, so the shuffles that
+    // combine a row's parts see all of its lanes).
+    const int part = tid % kRowLanes;
     // t = Li s
-    for (int r = tid; r < m; r += kApplyThreads) {
+    for (int base = 0; base < m; base += kApplyThreads / kRowLanes) {
+        const int r = base + tid / kRowLanes;
         double acc = 0.0;
-        for (int c = 0; c <= r; ++c) acc += Li[c * m + r] * sv[c];
-        t[r] = acc;
+        if (r < m)
+            for (int c = part; c <= r; c += kRowLanes) acc += Li[c * m + r] * sv[c];
+        acc = sum_row_lanes(acc);
+        if (r < m && part == 0) t[r] = acc;
     }
     __syncthreads();
-    // g = F - Y^T t, F = -bottom
-    if (tid < 6 && !resist) {
+    // g = F - Y^T t, F = -bottom: 32 lanes per component
+    if (!resist) {
+        const int k = tid / 32, p32 = tid % 32;
         double acc = 0.0;
-        for (int l = 0; l < m; ++l) acc += Y[l * 6 + tid] * t[l];
-        double bot = bot_in[tid];
-        if (it.rot) {
-            const int b = tid - tid % 3, c = tid % 3;
-            bot = R[c] * bot_in[b] + R[3 + c] * bot_in[b + 1] + R[6 + c] * bot_in[b + 2];
+        if (k < 6)
+            for (int l = p32; l < m; l += 32) acc += Y[l * 6 + k] * t[l];
+        for (int off = 16; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if (k < 6 && p32 == 0) {
+            double bot = bot_in[k];
+            if (it.rot) {
+                const int b = k - k % 3, c = k % 3;
+                bot = R[c] * bot_in[b] + R[3 + c] * bot_in[b + 1] + R[6 + c] * bot_in[b + 2];
+            }
+            g[k] = -bot - acc;
         }
-        g[tid] = -bot - acc;
     }
     __syncthreads();
     // U = S^-1 g (U = 0 for the resistance problem)
@@ -239,19 +259,21 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         sv[r] = acc;
     }
     __syncthreads();
-    if (!it.rot) {
-        for (int r = tid; r < m; r += kApplyThreads) {
-            double acc = 0.0;
-            for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
-            lam_out[r] = acc;
+    // lambda = Li^T w (into t when it still has to be rotated)
+    for (int base = 0; base < m; base += kApplyThreads / kRowLanes) {
+        const int r = base + tid / kRowLanes;
+        double acc = 0.0;
+        if (r < m)
+            for (int c = r + part; c < m; c += kRowLanes) acc += Li[r * m + c] * sv[c];
+        acc = sum_row_lanes(acc);
+        if (r < m && part == 0) {
+            if (it.rot) t[r] = acc;
+            else lam_out[r] = acc;
         }
+    }
+    if (!it.rot) {
         if (tid < 6 && !resist) U_out[tid] = g[6 + tid];
         return;
-    }
-    for (int r = tid; r < m; r += kApplyThreads) {
-        double acc = 0.0;
-        for (int c = r; c < m; ++c) acc += Li[r * m + c] * sv[c];
-        t[r] = acc;
     }
     __syncthreads();
     for (int e = tid; e < m; e += kApplyThreads) {
