@@ -38,13 +38,16 @@ struct BigBody {
 inline bool is_large_body(int64_t n_blobs) { return 3 * n_blobs > kSmallBodyMaxM; }
 inline int64_t padded_dim(int64_t n_blobs) { return (3 * n_blobs + 31) / 32 * 32; }
 
-// Factor storage of one body (doubles).  Small bodies: L^-1 (m x m), Y
-// (m x 6), S^-1 (6 x 6).  Large bodies, padded dimension Mp: L (Mp x Mp),
-// Y (Mp x 6), inverses of L's diagonal blocks (Mp x 32), Sc (6 x 6).
+// Factor storage of one body (doubles).  Small bodies: L^-1 (lower
+// triangle, packed by columns: column c holds rows c..m-1 from
+// packed_col(m, c)), Y (m x 6), S^-1 (6 x 6).  Large bodies, padded
+// dimension Mp: L (Mp x Mp), Y (Mp x 6), inverses of L's diagonal blocks
+// (Mp x 32), Sc (6 x 6).
+__host__ __device__ inline int64_t packed_col(int64_t m, int64_t c) { return c * m - c * (c - 1) / 2; }
 inline int64_t factor_doubles(int64_t n_blobs) {
     if (!is_large_body(n_blobs)) {
         const int64_t m = 3 * n_blobs;
-        return m * m + 6 * m + 36;
+        return m * (m + 1) / 2 + 6 * m + 36;
     }
     const int64_t Mp = padded_dim(n_blobs);
     return Mp * Mp + 6 * Mp + 32 * Mp + 36;

@@ -150,10 +150,14 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     }
     __syncthreads();
 
-    // 6. store Li (column-major), Y, S^-1
-    for (int e = tid; e < m * m; e += blockDim.x) out[e] = A[e];
-    for (int e = tid; e < 6 * m; e += blockDim.x) out[m * m + e] = Y[e];
-    for (int e = tid; e < 36; e += blockDim.x) out[m * m + 6 * m + e] = S[e];
+    // 6. store Li (lower triangle packed by columns), Y, S^-1
+    const int np = m * (m + 1) / 2;
+    for (int e = tid; e < m * m; e += blockDim.x) {
+        const int c = e / m, r = e - c * m;
+        if (r >= c) out[packed_col(m, c) + r - c] = A[e];
+    }
+    for (int e = tid; e < 6 * m; e += blockDim.x) out[np + e] = Y[e];
+    for (int e = tid; e < 36; e += blockDim.x) out[np + 6 * m + e] = S[e];
     // bit 4: M_pp not positive definite; bit 8: K_p^T M_pp^-1 K_p singular
     if (tid == 0 && bad) atomicOr(it.flag, ((bad & 1) ? 4 : 0) | ((bad & 2) ? 8 : 0));
 }
@@ -187,9 +191,9 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
     const int m = 3 * it.n_blobs, tid = threadIdx.x;
     // the whole factor [Li | Y | S^-1] is staged in LDS, eight loads in
     // flight per thread, followed by the right-hand side
-    const int nf = m * m + 6 * m + 36;
+    const int np = m * (m + 1) / 2, nf = np + 6 * m + 36;
     double *F = lds, *sv = lds + nf, *t = sv + m;
-    const double *Li = F, *Y = F + m * m, *Si = F + m * m + 6 * m;
+    const double *Li = F, *Y = F + np, *Si = F + np + 6 * m;  // Li packed by columns
     for (int e0 = tid; e0 < nf; e0 += 8 * kApplyThreads) {
         double v[8];
 #pragma unroll
@@ -222,7 +226,7 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         const int r = base + tid / kRowLanes;
         double acc = 0.0;
         if (r < m)
-            for (int c = part; c <= r; c += kRowLanes) acc += Li[c * m + r] * sv[c];
+            for (int c = part; c <= r; c += kRowLanes) acc += Li[packed_col(m, c) + r - c] * sv[c];
         acc = sum_row_lanes(acc);
         if (r < m && part == 0) t[r] = acc;
     }
@@ -264,7 +268,7 @@ __device__ __forceinline__ void precond_body_apply(const BodyWork &it, const gme
         const int r = base + tid / kRowLanes;
         double acc = 0.0;
         if (r < m)
-            for (int c = r + part; c < m; c += kRowLanes) acc += Li[r * m + c] * sv[c];
+            for (int c = r + part; c < m; c += kRowLanes) acc += Li[packed_col(m, r) + c - r] * sv[c];
         acc = sum_row_lanes(acc);
         if (r < m && part == 0) {
             if (it.rot) t[r] = acc;
