@@ -32,6 +32,7 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     double *S = Y + 6 * m;        // 6 x 6
     double *Ld = S + 36;          // L's diagonal (m)
     double *Dq = Ld + m;          // r_i - q_p per blob (m)
+    double *Kp = Dq + m;          // K_p (m x 6, row-major)
     __shared__ int bad;
     if (tid == 0) bad = 0;
 
@@ -59,13 +60,25 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
             A[j * m + j] = sqrt(dj > 0.0 ? dj : 1.0);
         }
         __syncthreads();
-        const double ljj = A[j * m + j];
-        for (int i = j + 1 + tid; i < m; i += blockDim.x) A[i * m + j] /= ljj;
+        const double inv_ljj = 1.0 / A[j * m + j];
+        for (int i = j + 1 + tid; i < m; i += blockDim.x) A[i * m + j] *= inv_ljj;
         __syncthreads();
         const int r = m - j - 1;  // trailing size
-        for (int e = tid; e < r * r; e += blockDim.x) {
-            const int i = j + 1 + e / r, k = j + 1 + e % r;
-            if (k <= i) A[i * m + k] -= A[i * m + j] * A[k * m + j];
+        // four independent elements per lane and pass, loads before stores,
+        // so that one LDS round trip serves four updates
+        for (int e0 = tid; e0 < r * r; e0 += 4 * 64) {
+            int at[4];
+            double v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 64 * u;
+                const int i = j + 1 + e / r, k = j + 1 + e % r;
+                at[u] = (e < r * r && k <= i) ? i * m + k : -1;
+                v[u] = at[u] >= 0 ? A[at[u]] - A[i * m + j] * A[k * m + j] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (at[u] >= 0) A[at[u]] = v[u];
         }
         __syncthreads();
     }
@@ -84,9 +97,16 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     for (int c = tid; c < m; c += blockDim.x) {
         const double lcc = 1.0 / Ld[c];
         for (int r = c + 1; r < m; ++r) {
-            double acc = A[r * m + c] * lcc;
-            for (int k = c + 1; k < r; ++k) acc += A[r * m + k] * A[c * m + k];
-            A[c * m + r] = -acc / Ld[r];
+            // four independent partial sums: the loads and FMAs of a row
+            // overlap instead of forming one dependent chain
+            double p[4] = {A[r * m + c] * lcc, 0.0, 0.0, 0.0};
+            int k = c + 1;
+            for (; k + 3 < r; k += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) p[u] += A[r * m + k + u] * A[c * m + k + u];
+            }
+            for (; k < r; ++k) p[0] += A[r * m + k] * A[c * m + k];
+            A[c * m + r] = -((p[0] + p[1]) + (p[2] + p[3])) / Ld[r];
         }
     }
     __syncthreads();
@@ -96,16 +116,23 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
         else if (r == c) A[e] = 1.0 / Ld[c];
     }
     __syncthreads();
-    // 4. Y = Li K_p, S = Y^T Y
+    // 4. Y = Li K_p (K_p staged first), S = Y^T Y
+    for (int e = tid; e < 6 * m; e += blockDim.x) {
+        const int c = e / 6, k = e % 6, i = c / 3;
+        const double d[3] = {Dq[3 * i], Dq[3 * i + 1], Dq[3 * i + 2]};
+        Kp[e] = K_entry(d, c % 3, k);
+    }
+    __syncthreads();
     for (int e = tid; e < 6 * m; e += blockDim.x) {
         const int row = e / 6, k = e % 6;
-        double acc = 0.0;
-        for (int c = 0; c <= row; ++c) {
-            const int i = c / 3, cc = c % 3;
-            const double d[3] = {Dq[3 * i], Dq[3 * i + 1], Dq[3 * i + 2]};
-            acc += A[c * m + row] * K_entry(d, cc, k);
+        double p[4] = {0.0, 0.0, 0.0, 0.0};
+        int c = 0;
+        for (; c + 3 <= row; c += 4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) p[u] += A[(c + u) * m + row] * Kp[(c + u) * 6 + k];
         }
-        Y[row * 6 + k] = acc;
+        for (; c <= row; ++c) p[0] += A[c * m + row] * Kp[c * 6 + k];
+        Y[row * 6 + k] = (p[0] + p[1]) + (p[2] + p[3]);
     }
     __syncthreads();
     if (tid < 36) {
@@ -446,7 +473,7 @@ __global__ void saddle_body_kernel(const SaddleJob *__restrict__ jobs, int32_t n
 
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    size_t lds = ((size_t)max_m * max_m + 8 * (size_t)max_m + 36) * sizeof(double);
+    size_t lds = ((size_t)max_m * max_m + 14 * (size_t)max_m + 36) * sizeof(double);
     hipLaunchKernelGGL(precond_build_small_kernel, dim3(n_items), dim3(64), lds, s, items, n_items);
     return hipGetLastError();
 }
