@@ -52,36 +52,50 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     }
     __syncthreads();
 
-    // 2. right-looking Cholesky, lower triangle, in place
+    // 2. right-looking Cholesky, lower triangle, in place, one barrier per
+    //    column: the trailing update takes column j unscaled with the pivot
+    //    d_jj (a_ik -= a_ij a_kj / d_jj), since no later column reads it,
+    //    and all columns are scaled by 1/sqrt(d_jj) in one pass at the end
+    //    (Ld holds the pivots meanwhile).
     for (int j = 0; j < m; ++j) {
+        const double dj0 = A[j * m + j];
+        const double dj = dj0 > 0.0 ? dj0 : 1.0;
         if (tid == 0) {
-            const double dj = A[j * m + j];
-            if (!(dj > 0.0)) bad = 1;
-            A[j * m + j] = sqrt(dj > 0.0 ? dj : 1.0);
+            if (!(dj0 > 0.0)) bad = 1;
+            Ld[j] = dj;
         }
-        __syncthreads();
-        const double inv_ljj = 1.0 / A[j * m + j];
-        for (int i = j + 1 + tid; i < m; i += blockDim.x) A[i * m + j] *= inv_ljj;
-        __syncthreads();
-        const int r = m - j - 1;  // trailing size
-        // four independent elements per lane and pass, loads before stores,
-        // so that one LDS round trip serves four updates
-        for (int e0 = tid; e0 < r * r; e0 += 4 * 64) {
-            int at[4];
-            double v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + 64 * u;
-                const int i = j + 1 + e / r, k = j + 1 + e % r;
-                at[u] = (e < r * r && k <= i) ? i * m + k : -1;
-                v[u] = at[u] >= 0 ? A[at[u]] - A[i * m + j] * A[k * m + j] : 0.0;
+        const double inv_d = 1.0 / dj;
+        // lanes as an 8 x 8 grid over the trailing lower triangle (no index
+        // division): lane (a, b) takes row I0 + a and columns K0 + b and
+        // K0 + 8 + b, loads before stores
+        const int a = tid >> 3, b = tid & 7;
+        for (int I0 = j + 1; I0 < m; I0 += 8) {
+            const int i = I0 + a;
+            const bool iv = i < m;
+            const double aij = iv ? A[i * m + j] * inv_d : 0.0;
+            for (int K0 = j + 1; K0 <= I0; K0 += 16) {
+                const int k0 = K0 + b, k1 = K0 + 8 + b;
+                const bool u0 = iv && k0 <= i, u1 = iv && k1 <= i;
+                const double x0 = u0 ? A[i * m + k0] - aij * A[k0 * m + j] : 0.0;
+                const double x1 = u1 ? A[i * m + k1] - aij * A[k1 * m + j] : 0.0;
+                if (u0) A[i * m + k0] = x0;
+                if (u1) A[i * m + k1] = x1;
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (at[u] >= 0) A[at[u]] = v[u];
         }
         __syncthreads();
     }
+    for (int c = tid; c < m; c += blockDim.x) {
+        const double l = sqrt(Ld[c]);
+        Ld[c] = l;
+        Y[c] = 1.0 / l;  // Y is free until step 4
+    }
+    __syncthreads();
+    for (int e = tid; e < m * m; e += blockDim.x) {
+        const int i = e / m, c = e - i * m;  // row-major A[i][c]
+        if (c < i) A[e] *= Y[c];
+        else if (c == i) A[e] = Ld[c];
+    }
+    __syncthreads();
 
     // 3. Li = L^-1, column-major in A.  Lane c forms column c below the
     //    diagonal into A's upper triangle (A[c m + r], r > c), reading L from
