@@ -6,7 +6,7 @@
 namespace rmb {
 
 // Largest 3n x 3n block handled by the LDS-resident per-body path.
-constexpr int kSmallBodyMaxM = 84;  // 28 blobs: build workspace (m^2 + 6m + 36 doubles) stays under 64 KiB of LDS
+constexpr int kSmallBodyMaxM = 84;  // 28 blobs: build workspace (m^2 + 13m + 36 doubles) stays under 64 KiB of LDS
 
 // One body of one system, for preconditioner build and apply.
 struct BodyWork {

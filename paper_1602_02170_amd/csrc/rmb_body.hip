@@ -31,8 +31,7 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     double *Y = A + m * m;        // m x 6
     double *S = Y + 6 * m;        // 6 x 6
     double *Ld = S + 36;          // L's diagonal (m)
-    double *Dq = Ld + m;          // r_i - q_p per blob (m)
-    double *Kp = Dq + m;          // K_p (m x 6, row-major)
+    double *Kp = Ld + m;          // K_p (m x 6, row-major)
     __shared__ int bad;
     if (tid == 0) bad = 0;
 
@@ -103,10 +102,7 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     //    clearing of the lower triangle follow once every column is done.
     gmem<double> out = as_global(it.factor);
     const gmem<const double> q = as_global(it.q);
-    for (int c = tid; c < m; c += blockDim.x) {
-        Ld[c] = A[c * m + c];
-        Dq[c] = as_global(it.pos)[3 * (int64_t)it.blob0 + c] - q[c % 3];
-    }
+    for (int c = tid; c < m; c += blockDim.x) Ld[c] = A[c * m + c];
     __syncthreads();
     for (int c = tid; c < m; c += blockDim.x) {
         const double lcc = 1.0 / Ld[c];
@@ -133,7 +129,8 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
     // 4. Y = Li K_p (K_p staged first), S = Y^T Y
     for (int e = tid; e < 6 * m; e += blockDim.x) {
         const int c = e / 6, k = e % 6, i = c / 3;
-        const double d[3] = {Dq[3 * i], Dq[3 * i + 1], Dq[3 * i + 2]};
+        const gmem<const double> ri = as_global(it.pos + 3 * (int64_t)(it.blob0 + i));
+        const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
         Kp[e] = K_entry(d, c % 3, k);
     }
     __syncthreads();
@@ -487,7 +484,8 @@ __global__ void saddle_body_kernel(const SaddleJob *__restrict__ jobs, int32_t n
 
 hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, int max_m, hipStream_t s) {
     if (n_items <= 0) return hipSuccess;
-    size_t lds = ((size_t)max_m * max_m + 14 * (size_t)max_m + 36) * sizeof(double);
+    // m^2 + 13m + 36 doubles: 65,472 bytes at the largest small body (m = 84)
+    size_t lds = ((size_t)max_m * max_m + 13 * (size_t)max_m + 36) * sizeof(double);
     hipLaunchKernelGGL(precond_build_small_kernel, dim3(n_items), dim3(64), lds, s, items, n_items);
     return hipGetLastError();
 }
@@ -495,7 +493,7 @@ hipError_t launch_precond_build_small(const BodyWork *items, int32_t n_items, in
 hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg,
                                       int32_t max_rhs, int max_m, hipStream_t s) {
     if (n_wg <= 0 || max_rhs <= 0) return hipSuccess;
-    size_t lds = ((size_t)max_m * max_m + 8 * max_m + 36) * sizeof(double);
+    size_t lds = ((size_t)max_m * (max_m + 1) / 2 + 8 * max_m + 36) * sizeof(double);  // packed L^-1, Y, S^-1, 2m
     hipLaunchKernelGGL(precond_apply_small_kernel, dim3((unsigned)n_wg, max_rhs), dim3(kApplyThreads), lds, s, jobs,
                        n_jobs);
     return hipGetLastError();

@@ -189,6 +189,37 @@ def test_server_results_equal_alone(env):
         assert res <= 1.05e-8
 
 
+def test_largest_small_bodies(env):
+    """Bodies of 28 blobs (m = 84, the largest on the small-body path): the
+    factor build and apply against the oracle's preconditioner, and a solve
+    against the dense solution."""
+    rmb, torch, ctx, O = env
+    lattice = np.array([[x, y, z] for x in range(3) for y in range(3) for z in range(3)], float)
+    shp = np.vstack([lattice, [[1.0, 1.0, 3.0]]])
+    rng = np.random.default_rng(31)
+    n = 6
+    centres = np.column_stack([rng.uniform(0, 20, n), rng.uniform(0, 20, n), rng.uniform(4.0, 6.0, n)])
+    quats = rng.standard_normal((n, 4))
+    quats /= np.linalg.norm(quats, axis=1, keepdims=True)
+    pos, off = S.assemble([shp] * n, centres, quats)
+    sus = S.Suspension(pos, off, centres, 0.4, 1.0, True)
+    sus.FT = rng.standard_normal((n, 6))
+    assert np.all(np.diff(off) == 28) and pos[:, 2].min() > 0.4
+    sysd = rmb.System.from_suspension(sus)
+    rhs = rng.standard_normal((3, 3 * sus.n_blobs + 6 * n))
+    P = O.BlockPreconditioner(sus)
+    ref = np.stack([P.apply(r) for r in rhs])
+    pc = rmb.Precond(ctx, sysd)
+    err = _rel(pc.apply(_dev(torch, rhs)).cpu().numpy(), ref)
+    print(f"[gpu] 28-blob bodies: precond apply rel err {err:.2e}", flush=True)
+    assert err <= 1e-10
+    pc.close()
+    Ud, _ = O.dense_solve(sus, sus.FT)
+    U, lam, info = _solve(env, sus, tol=1e-10, precision="fp64")
+    print(f"    solve {info}  U err {_rel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0 and _rel(U, Ud) <= 1e-8
+
+
 def test_solve_error_paths(env):
     rmb, torch, ctx, O = env
     # a layer of blobs overlapping the wall: the body's block is not SPD
