@@ -8,8 +8,9 @@
 //   M_pp = L L^T,  Y = L^-1 K_p (m x 6),  S = Y^T Y = K_p^T M_pp^-1 K_p
 // and for a right-hand side (s_p, bottom_p) with F_p = -bottom_p:
 //   t = L^-1 s,  U = S^-1 (F - Y^T t),  lambda = L^-T (t + Y U).
-// Bodies on the LDS path store Li = L^-1 (column-major), Y (row-major) and
-// S^-1, so that an apply is two triangular matrix-vector products.
+// Bodies on the LDS path store Li = L^-1 (lower triangle packed by columns),
+// Y (row-major) and S^-1, so that an apply is two triangular matrix-vector
+// products.
 #include <cmath>
 
 #include "rmb_blocks.h"
@@ -98,8 +99,8 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 
     // 3. Li = L^-1, column-major in A.  Lane c forms column c below the
     //    diagonal into A's upper triangle (A[c m + r], r > c), reading L from
-    //    the lower triangle, which no lane writes; the diagonal and the
-    //    clearing of the lower triangle follow once every column is done.
+    //    the lower triangle, which no lane writes; the diagonal follows once
+    //    every column is done (entries above Li's diagonal are never read).
     gmem<double> out = as_global(it.factor);
     const gmem<const double> q = as_global(it.q);
     for (int c = tid; c < m; c += blockDim.x) Ld[c] = A[c * m + c];
@@ -120,11 +121,7 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
         }
     }
     __syncthreads();
-    for (int e = tid; e < m * m; e += blockDim.x) {
-        const int c = e / m, r = e % m;
-        if (r < c) A[e] = 0.0;
-        else if (r == c) A[e] = 1.0 / Ld[c];
-    }
+    for (int c = tid; c < m; c += blockDim.x) A[c * m + c] = 1.0 / Ld[c];
     __syncthreads();
     // 4. Y = Li K_p (K_p staged first), S = Y^T Y
     for (int e = tid; e < 6 * m; e += blockDim.x) {
@@ -205,8 +202,8 @@ __global__ __launch_bounds__(64) void precond_build_small_kernel(const BodyWork 
 // ---------------------------------------------------------------------------
 
 // Solves one body's [M_pp -K_p; -K_p^T 0][lambda; U] = [s; bottom] with the
-// body's factor staged in LDS (lds: m*m + 6m + 36 doubles of the factor,
-// then 2m doubles).  With a rotation R (shared reference-shape factor), the
+// body's factor staged in LDS (lds: m(m+1)/2 + 6m + 36 doubles of the
+// factor, then 2m doubles).  With a rotation R (shared reference-shape factor), the
 // inputs are taken into the body frame (R^T on every 3-vector: blob
 // velocities, force, torque) and the results back (R on lambda, u, omega):
 // the RPY tensor and K are rotation-covariant, M_pp = R~ M_ref R~^T and
