@@ -216,10 +216,12 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
             const double s = sqrt(dcc > 0.0 ? dcc : 1.0), inv = 1.0 / s, inv2 = inv * inv;
             if (tid < NB) Lc[c * NB + tid] = tid > c ? D[c * NB + tid] * inv : (tid == c ? s : 0.0);
             if (tid == 0) Li[c] = inv;
-            const int rem = NB - c - 1;
-            for (int e = tid; e < rem * rem; e += 256) {
-                const int r = c + 1 + e % rem, cc = c + 1 + e / rem;
-                if (r >= cc) D[cc * NB + r] -= D[c * NB + r] * D[c * NB + cc] * inv2;
+            // lane (r, first column): rows by lane % NB, columns by lane / NB
+            // in rounds of 256 / NB (no division by a run-time count)
+            {
+                const int r = tid % NB;
+                for (int cc = c + 1 + tid / NB; cc < NB; cc += 256 / NB)
+                    if (r >= cc) D[cc * NB + r] -= D[c * NB + r] * D[c * NB + cc] * inv2;
             }
             __syncthreads();
         }
@@ -278,10 +280,8 @@ __global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restri
             }
         }
         // 5. zero the panel's columns above the diagonal block
-        for (int e = tid; e < j * NB; e += 256) {
-            const int r = e % j, c = e / j;
-            L[(int64_t)(j + c) * Mp + r] = 0.0;
-        }
+        for (int c = 0; c < NB; ++c)
+            for (int r = tid; r < j; r += 256) L[(int64_t)(j + c) * Mp + r] = 0.0;
         __syncthreads();
     }
     if (tid == 0 && bad) atomicOr(it.w.flag, 4);
