@@ -478,8 +478,8 @@ def main():
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how the "
-              "mobility product would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the mobility product would shard "
+              "by target rows with one all-gather of lambda per product); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
