@@ -426,15 +426,15 @@ def cpu_baseline(S, sus):
     return {"value": pairs / dt, "unit": "blob-pair interactions/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": f"the oracle's full FP64 solve of the same 1000-boomerang system to 1e-8: {it} iterations, "
-                      f"{calls[0]} products of {sus.n_blobs}^2 pairs, {dt:.1f} s"}
+                      f"{calls[0]} products of {sus.n_blobs}^2 pairs, {dt:.1f} s",
+            "other_workloads": _cpu_other_workloads(S, oracle)}
 
 
-def cpu_samples(S):
-    """The oracle on bounded samples of the other workloads, beside the GPU
-    figures: the product over a 24,576-blob prefix of the 196,608-blob
-    monolayer, and a few small requests of the serving stream solved one at
-    a time (FP64 GMRES to 1e-8)."""
-    import oracle
+def _cpu_other_workloads(S, oracle):
+    """Part of the CPU-baseline leg: the oracle on bounded samples of the
+    other workloads, beside the GPU figures: the product over a 24,576-blob
+    prefix of the 196,608-blob monolayer, and a few small requests of the
+    serving stream solved one at a time (FP64 GMRES to 1e-8)."""
     mono, lam = S.icosahedra_monolayer()
     n = 24576  # a prefix of the monolayer, one of the GPU sweep's sizes
     t = time.perf_counter()
@@ -579,9 +579,9 @@ def main():
         if not args.no_cpu:
             line["cpu_baseline"] = cpu_baseline(S, sus)
             log(f"  cpu oracle: {line['cpu_baseline']['value']:.3e} pairs/s on {line['cpu_baseline']['cores']} threads")
-            line["cpu_samples"] = cpu_samples(S)
-            log(f"  cpu oracle samples: monolayer rows {line['cpu_samples']['c3_matvec']['value']:.3e} pairs/s; "
-                f"small requests {line['cpu_samples']['c5_serial']['value']:.2f} solves/s")
+            ow = line["cpu_baseline"]["other_workloads"]
+            log(f"  cpu oracle, other workloads: monolayer prefix {ow['c3_matvec']['value']:.3e} pairs/s; "
+                f"small requests {ow['c5_serial']['value']:.2f} solves/s")
     ctx.close()
     print(json.dumps(line), flush=True)
 
