@@ -292,6 +292,20 @@ typedef struct {
     int32_t pad;
     double inner_tol;    /* refinement: residual reduction asked of each inner cycle;
                             0 -> 1e-5 */
+    double u_tol;        /* mobility solves only: bound on the forward error of the body
+                            velocities, ||U - U_exact|| / ||U_exact||, in addition to
+                            `tol`; 0 -> off.  A relative residual r leaves a velocity
+                            error of about gamma r, with gamma depending on the
+                            system's conditioning (3-5 for the wall boomerangs).  The
+                            solver measures gamma from its own refinement cycles: a
+                            cycle started from the iterate x_c with residual r_c
+                            computes the correction d ~ x_exact - x_c, so
+                            gamma ~ (||d_U|| / ||x_U||) / r_c.  It then stops only
+                            when r <= min(tol, u_tol / gamma), reported as
+                            tol_internal.  A solve whose first cycle already meets
+                            `tol` runs one short verification cycle (residual reduced
+                            tenfold) to measure gamma.  RMB_EINVAL for resistance
+                            solves. */
 } rmb_solve_opts;
 
 typedef struct {
@@ -303,6 +317,12 @@ typedef struct {
     int32_t pad;
     double rel_residual;   /* final ||b - A x|| / ||b|| with the FP64 operator */
     double seconds;        /* host wall time from admission to completion */
+    double tol_internal;   /* residual target the solve ended with: tol, or
+                              min(tol, u_tol / gamma) under velocity-error control */
+    double u_err_est;      /* estimated ||U - U_exact|| / ||U_exact|| of the result
+                              (gamma * rel_residual), or -1 when u_tol is off or no
+                              refinement cycle has measured gamma */
+    double gamma;          /* measured velocity-error amplification (see u_tol), or -1 */
 } rmb_solve_info;
 
 /* Mobility problem: given F (device [N][6], force then torque about q_p) and

@@ -57,7 +57,8 @@ class rmb_shapes(ctypes.Structure):
 
 class rmb_solve_opts(ctypes.Structure):
     _fields_ = [("tol", ctypes.c_double), ("precision", ctypes.c_int32), ("restart", ctypes.c_int32),
-                ("max_iters", ctypes.c_int32), ("pad", ctypes.c_int32), ("inner_tol", ctypes.c_double)]
+                ("max_iters", ctypes.c_int32), ("pad", ctypes.c_int32), ("inner_tol", ctypes.c_double),
+                ("u_tol", ctypes.c_double)]
 
 
 class rmb_tune_record(ctypes.Structure):
@@ -69,7 +70,8 @@ class rmb_tune_record(ctypes.Structure):
 class rmb_solve_info(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("cycles", ctypes.c_int32),
                 ("matvecs_fp64", ctypes.c_int32), ("matvecs_fp32", ctypes.c_int32), ("pad", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("tol_internal", ctypes.c_double), ("u_err_est", ctypes.c_double), ("gamma", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -287,8 +289,11 @@ def flow_field(ctx: Context, system: System, lam: torch.Tensor, sub_offsets, tra
     return out
 
 
-def solve_opts(tol=1e-8, precision="fp64", restart=100, max_iters=1000, inner_tol=1e-5):
-    return rmb_solve_opts(float(tol), _prec(precision), int(restart), int(max_iters), 0, float(inner_tol))
+def solve_opts(tol=1e-8, precision="fp64", restart=100, max_iters=1000, inner_tol=1e-5, u_tol=0.0):
+    """u_tol > 0 bounds the forward error of the body velocities as well
+    (see rmb_solve_opts in include/rmb.h)."""
+    return rmb_solve_opts(float(tol), _prec(precision), int(restart), int(max_iters), 0, float(inner_tol),
+                          float(u_tol))
 
 
 def _vec(t, name, n):
@@ -438,6 +443,11 @@ class Server:
         ctx._adopt(self)
 
     def submit(self, tag: int, system: System, FT: torch.Tensor, slip: torch.Tensor = None, **opts):
+        """Queues one request.  Tags must be unique among requests not yet
+        polled: the output tensors of a request are kept alive under its tag
+        until poll() returns it."""
+        if int(tag) in self.live:
+            raise ValueError(f"tag {int(tag)} is already in flight")
         nb, N = system.n_blobs, system.n_bodies
         U = torch.empty((N, 6), dtype=torch.float64, device=FT.device)
         lam = torch.empty((nb, 3), dtype=torch.float64, device=FT.device)

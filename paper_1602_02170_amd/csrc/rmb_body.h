@@ -210,6 +210,7 @@ struct KrylovJob {
     int32_t n_seg;      // workgroups of this system
     int32_t n_chunk;    // 512-element chunks per workgroup
     int32_t kk;
+    int64_t u0;         // velocity norms: first element of the body part of x and t
 };
 
 // CGS2 orthogonalisation of w against V[0..kk-1] and normalisation into
@@ -219,6 +220,9 @@ hipError_t launch_orthogonalise(const KrylovJob *jobs, int32_t n_jobs, int64_t n
 hipError_t launch_combine(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
 // x += t
 hipError_t launch_axpy(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipStream_t s);
+// One workgroup per job (wg_begin = its index): hcol[1] = sum of t[e]^2 and
+// hcol[2] = sum of x[e]^2 over e in [u0, n), summed in a fixed order.
+hipError_t launch_unorm(const KrylovJob *jobs, int32_t n_jobs, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // misc per-system kernels

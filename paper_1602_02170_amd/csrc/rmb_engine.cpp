@@ -182,6 +182,9 @@ struct Job {
     double *U_out = nullptr, *lam_out = nullptr;
     bool resist = false;
     double tol = 1e-8, inner_tol = 1e-5;
+    // velocity-error control: u_tol bounds ||U - U_exact|| / ||U_exact||;
+    // gamma is the measured ratio of that error to the relative residual
+    double u_tol = 0.0, gamma = -1.0, tol_eff = 1e-8, rel_start = 1.0;
     int prec = RMB_PREC_FP64, m = 100, max_iters = 1000;
     rmb_precond pc = nullptr;  // external factors (not owned) or null
     // sizes
@@ -365,8 +368,12 @@ struct Engine {
         J->sys.body_off = J->off.data();
         J->FT = FT, J->slip = slip, J->U_out = U, J->lam_out = lam;
         if (o) {
-            if (o->tol < 0 || o->inner_tol < 0 || o->restart < 0 || o->restart > 255 || o->max_iters < 0)
+            if (o->tol < 0 || o->inner_tol < 0 || o->restart < 0 || o->restart > 255 || o->max_iters < 0 ||
+                !(o->u_tol >= 0.0))
                 return fail(ctx, RMB_EINVAL, "bad solve options");
+            if (o->u_tol > 0 && resist)
+                return fail(ctx, RMB_EINVAL, "u_tol applies to mobility solves only");
+            J->u_tol = o->u_tol;
             if (o->precision != RMB_PREC_FP64 && o->precision != RMB_PREC_FP32_PAIRS &&
                 o->precision != RMB_PREC_RELAXED)
                 return fail(ctx, RMB_EINVAL, "unknown precision %d", o->precision);
@@ -382,6 +389,7 @@ struct Engine {
             J->pc = pc;
         }
         J->resist = resist;
+        J->tol_eff = J->tol;
         J->nb = sys->n_blobs, J->N = sys->n_bodies;
         J->n = resist ? 3 * J->nb : 3 * J->nb + 6 * J->N;
         J->ldv = (J->n + 31) / 32 * 32;
@@ -493,11 +501,19 @@ struct Engine {
     static constexpr size_t kStageFixed = 32768;  // alignment of the shared tables
     size_t stage_reserved = kStageFixed;
 
+    // Residual target of the next cycle.  Under velocity-error control the
+    // solve's tolerance is min(tol, u_tol / gamma) once a refinement cycle
+    // has measured gamma; a solve that meets `tol` before any such cycle runs
+    // a verification cycle that reduces the residual tenfold.
     void begin_cycle(Job *J, double beta) {
         J->k = 0;
         J->cycles++;
+        J->rel_start = beta / J->bnorm;
         J->cycle_fp32 = J->prec == RMB_PREC_FP32_PAIRS;
-        J->target = J->cycle_fp32 ? std::max(J->inner_tol * beta, 0.5 * J->tol * J->bnorm) : J->tol * J->bnorm;
+        J->tol_eff = J->u_tol > 0 && J->gamma > 0 ? std::min(J->tol, J->u_tol / J->gamma) : J->tol;
+        double t = J->tol_eff * J->bnorm;
+        if (J->u_tol > 0 && !(J->gamma > 0) && beta <= J->tol * J->bnorm) t = 0.1 * beta;
+        J->target = J->cycle_fp32 ? std::max(J->inner_tol * beta, 0.5 * t) : t;
         J->step_fp32 = relaxed_fp32(J, beta);
         J->est = beta, J->est_prev = 0;
         J->R.assign((size_t)J->m * J->m, 0.0);
@@ -513,7 +529,7 @@ struct Engine {
     // that error, ||r_k|| being the current residual (estimate).
     static constexpr double kFp32ProductError = 1e-7;
     static bool relaxed_fp32(const Job *J, double rnorm) {
-        return J->prec == RMB_PREC_RELAXED && rnorm * kFp32ProductError <= J->tol * J->bnorm;
+        return J->prec == RMB_PREC_RELAXED && rnorm * kFp32ProductError <= J->tol_eff * J->bnorm;
     }
 
     void finish_job(Job *J, rmb_status st, const char *msg) {
@@ -758,6 +774,18 @@ struct Engine {
         for (Job *J : iter)
             orth.push_back(kj(J, J->w, J->k + koff + 1, J->V + (size_t)(J->k + koff + 1) * J->ldv, wg_orth));
         for (Job *J : finish) orth.push_back(kj(J, J->w, 0, J->V, wg_orth));
+        // velocity norms of the correction and the updated iterate (after the axpy)
+        std::vector<KrylovJob> un;
+        for (Job *J : finish)
+            if (J->u_tol > 0) {
+                int64_t unused = 0;
+                KrylovJob U = kj(J, nullptr, 0, nullptr, unused);
+                U.wg_begin = (int64_t)un.size();  // one workgroup per job
+                U.x = J->x;
+                U.t = J->w;
+                U.u0 = 3 * J->nb;
+                un.push_back(U);
+            }
         for (Job *J : setup) orth.push_back(kj(J, J->b, 0, J->V, wg_orth));
         // finish: combine then axpy tables
         std::vector<KrylovJob> axp;
@@ -791,6 +819,7 @@ struct Engine {
         size_t o_sd = sd.empty() ? 0 : st.put(sd.data(), sd.size() * sizeof(SaddleJob));
         size_t o_orth = orth.empty() ? 0 : st.put(orth.data(), orth.size() * sizeof(KrylovJob));
         size_t o_axp = axp.empty() ? 0 : st.put(axp.data(), axp.size() * sizeof(KrylovJob));
+        size_t o_un = un.empty() ? 0 : st.put(un.data(), un.size() * sizeof(KrylovJob));
         // the combine and reduction tables hold device addresses inside the
         // staging buffer (coefficients, saddle rows): patched once it is sized
         size_t o_comb = 0, o_sred = 0;
@@ -841,6 +870,7 @@ struct Engine {
                 RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)D(o_appL[v]), (int32_t)appL[v].size(),
                                                         wg_appL[v], 1, appL_max_Mp[v], v ? 32 : 16, s));
         if (!axp.empty()) RMB_HIP(ctx, launch_axpy((const KrylovJob *)D(o_axp), (int32_t)axp.size(), wg_axp, s));
+        if (!un.empty()) RMB_HIP(ctx, launch_unorm((const KrylovJob *)D(o_un), (int32_t)un.size(), s));
         if (!pk.empty()) RMB_HIP(ctx, launch_pack_table((const PackJob *)D(o_pk), (int32_t)pk.size(), wg_pk, s));
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
@@ -900,7 +930,15 @@ struct Engine {
         for (Job *J : finish) {
             const double beta = hcol_h(J)[0];
             J->rel = beta / J->bnorm;
-            if (J->rel <= J->tol) finish_job(J, RMB_OK, nullptr);
+            bool ok = J->rel <= J->tol;
+            if (J->u_tol > 0) {
+                // the cycle's correction d estimates the error of the iterate it
+                // started from, whose relative residual was rel_start
+                const double du = std::sqrt(hcol_h(J)[1]), xu = std::sqrt(hcol_h(J)[2]);
+                if (J->cycles >= 2 && J->rel_start > 0 && xu > 0) J->gamma = du / xu / J->rel_start;
+                ok = ok && J->gamma > 0 && J->gamma * J->rel <= J->u_tol;
+            }
+            if (ok) finish_job(J, RMB_OK, nullptr);
             else if (J->iters >= J->max_iters) finish_job(J, RMB_ENOCONV, "iteration limit reached");
             else begin_cycle(J, beta);
         }
@@ -985,6 +1023,9 @@ struct Engine {
         info->pad = 0;
         info->rel_residual = J->rel;
         info->seconds = J->t_done - J->t_admit;
+        info->tol_internal = J->tol_eff;
+        info->gamma = J->gamma > 0 ? J->gamma : -1.0;
+        info->u_err_est = J->u_tol > 0 && J->gamma > 0 ? J->gamma * J->rel : -1.0;
     }
 };
 

@@ -301,6 +301,38 @@ hipError_t launch_axpy(const KrylovJob *jobs, int32_t n_jobs, int64_t n_wg, hipS
     return hipGetLastError();
 }
 
+// Squared norms of the body part of the last correction (t) and of the
+// updated iterate (x), for the velocity-error estimate of a solve: one
+// workgroup per job, each thread summing a strided range, then the
+// workgroup's fixed-order reduction.
+__global__ __launch_bounds__(kThreads) void unorm_kernel(const KrylovJob *__restrict__ jobs, int32_t n_jobs) {
+    __shared__ double red[kThreads];
+    const KrylovJob &J = jobs[blockIdx.x];
+    double st = 0.0, sx = 0.0;
+    for (int64_t e = J.u0 + threadIdx.x; e < J.n; e += kThreads) {
+        const double t = as_global(J.t)[e], x = as_global(J.x)[e];
+        st = fma(t, t, st);
+        sx = fma(x, x, sx);
+    }
+    stash_wave_sum(st, 0, red);
+    __syncthreads();
+    const double tt = block_sum(red, 0);
+    __syncthreads();
+    stash_wave_sum(sx, 0, red);
+    __syncthreads();
+    const double xx = block_sum(red, 0);
+    if (threadIdx.x == 0) {
+        as_global(J.hcol)[1] = tt;
+        as_global(J.hcol)[2] = xx;
+    }
+}
+
+hipError_t launch_unorm(const KrylovJob *jobs, int32_t n_jobs, hipStream_t s) {
+    if (n_jobs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(unorm_kernel, dim3((unsigned)n_jobs), dim3(kThreads), 0, s, jobs, n_jobs);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 
 __global__ void build_rhs_kernel(const double *__restrict__ FT, const double *__restrict__ slip, int64_t nb3,

@@ -4,6 +4,7 @@ oracle's per-body dense solves (eq:saddle_M_precon)."""
 import numpy as np
 import pytest
 
+import parity
 import suspensions as S
 
 pytestmark = pytest.mark.gpu
@@ -22,8 +23,8 @@ def _dev(torch, a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+_rel = parity.err  # 2-norm and per-row bound (tests/parity.py)
+_srel = parity.solve_err  # the same for solve results
 
 
 def _sub(sus, bodies):
@@ -87,8 +88,8 @@ def test_mixed_small_and_large_bodies(env):
     U, lam, info = rmb.solve_mobility(ctx, rmb.System.from_suspension(s), _dev(torch, s.FT), tol=1e-11,
                                       precision="fp32")
     U = U.cpu().numpy()
-    print(f"[gpu] mixed solve info {info} U err {_rel(U, Ud):.2e}", flush=True)
-    assert info["status"] == 0 and _rel(U, Ud) <= 1e-8
+    print(f"[gpu] mixed solve info {info} U err {_srel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0 and _srel(U, Ud) <= 1e-8
 
 
 def test_free_space_42_blob_shells_solve(env):
@@ -101,7 +102,7 @@ def test_free_space_42_blob_shells_solve(env):
     s = S.Suspension(pos, off, centres, 0.5 * S.min_spacing(shp), 1.0, False, rng.standard_normal((4, 6)))
     Ud, _ = O.dense_solve(s, s.FT)
     U, lam, info = rmb.solve_mobility(ctx, rmb.System.from_suspension(s), _dev(torch, s.FT), tol=1e-11)
-    assert info["status"] == 0 and _rel(U.cpu().numpy(), Ud) <= 1e-8
+    assert info["status"] == 0 and _srel(U.cpu().numpy(), Ud) <= 1e-8
 
 
 def test_shell_batch_512x162_factor_and_apply_sampled(env):

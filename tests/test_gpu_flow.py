@@ -9,6 +9,7 @@ pairs with FP64 accumulation, as for the square product.
 import numpy as np
 import pytest
 
+import parity
 import suspensions as S
 
 pytestmark = pytest.mark.gpu
@@ -40,8 +41,7 @@ def _run(env, sus, lam, offs, ta, targets, prec):
     return v.cpu().numpy()
 
 
-def _rel(v, ref):
-    return np.linalg.norm(v - ref) / np.linalg.norm(ref)
+_rel = parity.err  # 2-norm and per-row bound (tests/parity.py)
 
 
 def _plane(z, nx=40, ny=30, half=25.0):

@@ -1,11 +1,15 @@
 """Parity of the HIP blob mobility product with the CPU FP64 oracle.
 
-Bar: relative 2-norm error over the whole (Nb, 3) result <= 1e-12 for FP64
-pairs and <= 1e-5 for FP32 pairs with FP64 accumulation.
+Bar: relative 2-norm error over the whole (Nb, 3) result, and the largest
+error of any one blob relative to the rms blob velocity, both <= 1e-12 for
+FP64 pairs and <= 1e-5 for FP32 pairs with FP64 accumulation.  Every block
+size of the symmetric product (64, 128, 256, 512 blobs) and the one-sided
+kernel are covered.
 """
 import numpy as np
 import pytest
 
+import parity
 import suspensions as S
 
 pytestmark = pytest.mark.gpu
@@ -31,8 +35,7 @@ def _run(env, sus, lam, prec):
     return v.cpu().numpy()
 
 
-def _rel(v, ref):
-    return np.linalg.norm(v - ref) / np.linalg.norm(ref)
+_rel = parity.err  # 2-norm and per-row bound (tests/parity.py)
 
 
 def _cases():
@@ -80,6 +83,52 @@ def test_matvec_full_monolayer_sampled_rows(env, prec):
     ref = env[3].matvec_rows(sus.pos, lam, rows, sus.a, sus.eta, sus.wall)
     err = _rel(v[rows], ref)
     print(f"    sampled rel err {err:.3e}", flush=True)
+    assert err <= TOL[prec]
+    assert np.all(np.isfinite(v))
+
+
+_B128 = {}
+
+
+def _b128_case(env):
+    """4096 icosahedra of the monolayer (49,152 blobs): the symmetric product
+    with 128-blob blocks (384 blocks); the oracle's full product is computed
+    once for both precisions."""
+    if not _B128:
+        sus, lam = S.icosahedra_monolayer(n_bodies=4096)
+        _B128["sus"], _B128["lam"] = sus, lam
+        _B128["ref"] = env[3].matvec(sus.pos, lam, sus.a, sus.eta, sus.wall)
+    return _B128["sus"], _B128["lam"], _B128["ref"]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_matvec_block128_full_parity(env, prec):
+    rmb = env[0]
+    sus, lam, ref = _b128_case(env)
+    assert rmb.pair_plan(sus.n_blobs) == (True, 128)
+    print(f"[gpu] 128-blob blocks {prec} nb={sus.n_blobs}", flush=True)
+    v = _run(env, sus, lam, prec)
+    err = _rel(v, ref)
+    print(f"    rel err {parity.rel2(v, ref):.3e}, worst blob {parity.rowmax(v, ref):.3e}", flush=True)
+    assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_matvec_block512_sampled_rows(env, prec):
+    """A 160 x 160 monolayer lattice (25,600 icosahedra, 307,200 blobs): the
+    symmetric product with 512-blob blocks; sampled rows (the first and last
+    blob among them) against the oracle's per-row sums."""
+    rmb = env[0]
+    sus, lam = S.icosahedra_monolayer(n_side=160)
+    assert rmb.pair_plan(sus.n_blobs) == (True, 512)
+    print(f"[gpu] 512-blob blocks {prec} nb={sus.n_blobs}", flush=True)
+    v = _run(env, sus, lam, prec)
+    rows = np.random.default_rng(17).choice(sus.n_blobs, 126, replace=False)
+    rows = np.concatenate([rows, [0, sus.n_blobs - 1]])
+    ref = env[3].matvec_rows(sus.pos, lam, rows, sus.a, sus.eta, sus.wall)
+    err = _rel(v[rows], ref)
+    print(f"    sampled rel err {parity.rel2(v[rows], ref):.3e}, worst blob {parity.rowmax(v[rows], ref):.3e}",
+          flush=True)
     assert err <= TOL[prec]
     assert np.all(np.isfinite(v))
 

@@ -8,6 +8,7 @@ against the dense solve."""
 import numpy as np
 import pytest
 
+import parity
 import suspensions as S
 
 pytestmark = pytest.mark.gpu
@@ -26,8 +27,8 @@ def _dev(torch, a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+_rel = parity.err  # 2-norm and per-row bound (tests/parity.py)
+_srel = parity.solve_err  # the same for solve results
 
 
 def _permeable(sus, seed, lo=0.1, hi=2.0):
@@ -79,10 +80,10 @@ def test_permeable_solve(env, prec):
     rigid = S.boomerangs_wall(n_bodies=60, lateral=50.0, seed=303)
     _, _, ir = rmb.solve_mobility(ctx, rmb.System.from_suspension(rigid), _dev(torch, rigid.FT), tol=1e-10,
                                   precision=prec)
-    print(f"[gpu] permeable solve {prec}: {info} residual {res:.2e} U err {_rel(U, Ud):.2e}; "
+    print(f"[gpu] permeable solve {prec}: {info} residual {res:.2e} U err {_srel(U, Ud):.2e}; "
           f"rigid iterations {ir['iterations']}", flush=True)
     assert info["status"] == 0 and res <= 1.05e-10
-    assert _rel(U, Ud) <= 1e-8
+    assert _srel(U, Ud) <= 1e-8
     assert info["iterations"] <= ir["iterations"]
 
 
@@ -94,8 +95,8 @@ def test_permeable_large_bodies_solve(env):
     Ud, _ = O.dense_solve(sus, sus.FT)
     U, lam, info = rmb.solve_mobility(ctx, rmb.System.from_suspension(sus), _dev(torch, sus.FT), tol=1e-10)
     U = U.cpu().numpy()
-    print(f"[gpu] permeable shells solve: {info} U err {_rel(U, Ud):.2e}", flush=True)
-    assert info["status"] == 0 and _rel(U, Ud) <= 1e-8
+    print(f"[gpu] permeable shells solve: {info} U err {_srel(U, Ud):.2e}", flush=True)
+    assert info["status"] == 0 and _srel(U, Ud) <= 1e-8
 
 
 def test_permeable_with_shared_blocks(env):
@@ -109,7 +110,7 @@ def test_permeable_with_shared_blocks(env):
                                  _dev(torch, sus.quat))
     Ud, _ = O.dense_solve(sus, sus.FT)
     U, lam, info = rmb.solve_mobility(ctx, sysd, _dev(torch, sus.FT), precond=pc, tol=1e-10)
-    assert info["status"] == 0 and _rel(U.cpu().numpy(), Ud) <= 1e-8
+    assert info["status"] == 0 and _srel(U.cpu().numpy(), Ud) <= 1e-8
     pc.close()
 
 

@@ -10,6 +10,7 @@ takes to bring its residual to tol / 1e-7; at most one extra cycle."""
 import numpy as np
 import pytest
 
+import parity
 import suspensions as S
 
 pytestmark = pytest.mark.gpu
@@ -30,8 +31,7 @@ def _dev(torch, a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+_rel = parity.solve_err  # 2-norm and per-row bound (tests/parity.py)
 
 
 @pytest.mark.parametrize("tol", [1e-8, 1e-10])

@@ -9,6 +9,7 @@ the oracle's GMRES with the same preconditioner."""
 import numpy as np
 import pytest
 
+import parity
 import suspensions as S
 
 pytestmark = pytest.mark.gpu
@@ -27,8 +28,7 @@ def _dev(torch, a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
 
 
-def _rel(a, b):
-    return np.linalg.norm(a - b) / np.linalg.norm(b)
+_rel = parity.solve_err  # 2-norm and per-row bound (tests/parity.py)
 
 
 def _residual(O, sus, U, slip, lam):
