@@ -287,79 +287,102 @@ void rmb_ctx_destroy(rmb_ctx ctx) {
 
 const char *rmb_last_error(rmb_ctx ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
-                               double *vel, rmb_stream stream) {
-    if (!ctx) return RMB_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    RMB_TRY(enter(ctx, s));
-    RMB_TRY(check_system(ctx, sys, false));
-    if (precision != RMB_PREC_FP64 && precision != RMB_PREC_FP32_PAIRS)
-        return fail(ctx, RMB_EINVAL, "unknown precision %d", precision);
-    if (!lambda || !vel) return fail(ctx, RMB_EINVAL, "lambda and vel are required");
-    if ((const void *)lambda == (const void *)vel) return fail(ctx, RMB_EINVAL, "vel must not alias lambda");
-
-    const int64_t nb = sys->n_blobs;
+// Workspace of one standalone product, from its base (device, 256-byte
+// aligned): [flag | job records, 256 bytes each | partials (symmetric:
+// vpart then upart of the largest band) or packed sources then per-split
+// partials (one-sided)].
+static size_t product_work_bytes(int64_t nb, int32_t precision, size_t band_bytes) {
+    if (use_sym(nb)) {
+        const size_t jobs = sym_bands(nb, band_bytes).size();
+        return 256 + 256 * jobs + sym_band_partial_doubles(nb, band_bytes) * sizeof(double);
+    }
     const size_t rec = precision == RMB_PREC_FP32_PAIRS ? sizeof(SrcF32) : sizeof(SrcF64);
+    int32_t S, Tb;
+    int64_t chunk;
+    split_plan(nb, &S, &chunk, &Tb);
+    return 512 + (nb * rec + 255) / 256 * 256 + (size_t)S * nb * 3 * sizeof(double);
+}
+
+// Enqueues vel = M lambda on `s` with the workspace at `work` (positions
+// already validated).  Job records are written by kernels, so nothing here
+// allocates or stages host memory.  `timed`: bracket the pair launches with
+// the context's timing events when timing is on.
+static rmb_status product_enqueue(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                                  double *vel, char *work, size_t band_bytes, bool timed, hipStream_t s) {
+    const int64_t nb = sys->n_blobs;
     const bool wall = sys->geometry == RMB_GEOM_WALL;
     const double pref = mobility_prefactor(sys->a, sys->eta);
     if (use_sym(nb)) {
-        // scratch layout: [flag | job | vpart, upart]; the symmetric kernel
-        // reads positions and forces directly
+        // the symmetric kernel reads positions and forces directly; the
+        // output doubles as the accumulator of the bands
+        const std::vector<SymBand> bands = sym_bands(nb, band_bytes);
         SymJob J{};
         sym_plan(nb, &J.B, &J.n_blk);
-        const int64_t tiles = sym_tiles(nb);
-        size_t off_job = 256;
-        size_t off_part = off_job + 256;
-        size_t total = off_part + sym_partial_doubles(nb) * sizeof(double);
-        char *base = nullptr;
-        RMB_TRY(scratch(ctx, total, (void **)&base));
-        RMB_TRY(check_positions(ctx, sys, (int *)base, s));
+        double *part = (double *)(work + 256 + 256 * bands.size());
         J.tpos = sys->pos;
         J.lam = lambda;
-        J.vpart = (double *)(base + off_part);
-        J.upart = J.vpart + (size_t)tiles * J.B * 3;
+        J.vpart = part;
+        J.upart = part + sym_band_partial_doubles(nb, band_bytes) / 2;
         J.vel = vel;
+        J.acc = vel;
         J.nb = nb;
-        J.wg_begin = 0;
-        J.red_begin = 0;
         J.a = sys->a;
         J.four_a2 = 4.0 * sys->a * sys->a;
         J.k_near_iso = 9.0 / (32.0 * sys->a);
         J.k_near_rr = 3.0 / (32.0 * sys->a);
         J.pref = pref;
         J.f32 = precision == RMB_PREC_FP32_PAIRS;
-        SymJob *hJ = nullptr;
-        RMB_TRY(pinned(ctx, sizeof(SymJob), (void **)&hJ));
-        *hJ = J;
-        RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(SymJob), hipMemcpyHostToDevice, s));
-        RMB_TRY(sym_launch(ctx, precision, wall, J.B, (const SymJob *)(base + off_job), 1, tiles, s));
-        RMB_HIP(ctx, launch_sym_reduce((const SymJob *)(base + off_job), 1, sym_reduce_groups(nb), nullptr, 0, 0, s));
+        for (size_t b = 0; b < bands.size(); ++b) {
+            SymJob Jb = J;
+            Jb.t0 = bands[b].t0;
+            Jb.I0 = bands[b].I0, Jb.I1 = bands[b].I1;
+            Jb.first = b == 0, Jb.last = b + 1 == bands.size();
+            SymJob *d = (SymJob *)(work + 256 + 256 * b);
+            RMB_HIP(ctx, launch_store_sym_job(Jb, d, s));
+            if (timed) RMB_TRY(sym_launch(ctx, precision, wall, J.B, d, 1, bands[b].tiles, s));
+            else RMB_HIP(ctx, launch_pair_sym(precision, wall, J.B, d, 1, bands[b].tiles, s));
+            RMB_HIP(ctx, launch_sym_reduce(d, 1, sym_reduce_groups_band(nb, J.B, bands[b], Jb.last), nullptr, 0, 0, s));
+        }
         RMB_HIP(ctx, launch_add_shift(sys->blob_shift, lambda, nb, vel, s));
         return RMB_OK;
     }
+    const size_t rec = precision == RMB_PREC_FP32_PAIRS ? sizeof(SrcF32) : sizeof(SrcF64);
     PairJob J;
     pair_job_init(&J, sys->pos, nullptr, nullptr, nb, sys->a);
-    // scratch layout: [flag | job | sources | partials]
-    size_t off_job = 256, off_src = off_job + 256;
-    size_t off_part = off_src + (nb * rec + 255) / 256 * 256;
-    size_t total = off_part + (size_t)J.n_split * nb * 3 * sizeof(double);
-    char *base = nullptr;
-    RMB_TRY(scratch(ctx, total, (void **)&base));
-    RMB_TRY(check_positions(ctx, sys, (int *)base, s));
-
-    J.src = base + off_src;
-    J.partial = (double *)(base + off_part);
+    const size_t off_src = 512, off_part = off_src + (nb * rec + 255) / 256 * 256;
+    J.src = work + off_src;
+    J.partial = (double *)(work + off_part);
     J.tile_begin = 0;
-    PairJob *hJ = nullptr;
-    RMB_TRY(pinned(ctx, sizeof(PairJob), (void **)&hJ));
-    *hJ = J;
-    RMB_HIP(ctx, hipMemcpyAsync(base + off_job, hJ, sizeof(PairJob), hipMemcpyHostToDevice, s));
-    RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, base + off_src, s));
-    RMB_TRY(pair_launch(ctx, precision, wall, (const PairJob *)(base + off_job), 1,
-                        (int64_t)J.n_tblock * J.n_split, s));
+    PairJob *d = (PairJob *)(work + 256);
+    RMB_HIP(ctx, launch_store_pair_job(J, d, s));
+    RMB_HIP(ctx, launch_pack_sources(precision, sys->pos, lambda, nb, work + off_src, s));
+    if (timed) RMB_TRY(pair_launch(ctx, precision, wall, d, 1, (int64_t)J.n_tblock * J.n_split, s));
+    else RMB_HIP(ctx, launch_pair_tiles(precision, wall, d, 1, (int64_t)J.n_tblock * J.n_split, s));
     RMB_HIP(ctx, launch_reduce_partials(J.partial, J.n_split, nb, pref, vel, s));
     RMB_HIP(ctx, launch_add_shift(sys->blob_shift, lambda, nb, vel, s));
     return RMB_OK;
+}
+
+static rmb_status check_product_args(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                                     const double *vel) {
+    RMB_TRY(check_system(ctx, sys, false));
+    if (precision != RMB_PREC_FP64 && precision != RMB_PREC_FP32_PAIRS)
+        return fail(ctx, RMB_EINVAL, "unknown precision %d", precision);
+    if (!lambda || !vel) return fail(ctx, RMB_EINVAL, "lambda and vel are required");
+    if ((const void *)lambda == (const void *)vel) return fail(ctx, RMB_EINVAL, "vel must not alias lambda");
+    return RMB_OK;
+}
+
+rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                               double *vel, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_product_args(ctx, sys, precision, lambda, vel));
+    char *base = nullptr;
+    RMB_TRY(scratch(ctx, product_work_bytes(sys->n_blobs, precision, kSymBandBytes), (void **)&base));
+    RMB_TRY(check_positions(ctx, sys, (int *)base, s));
+    return product_enqueue(ctx, sys, precision, lambda, vel, base, kSymBandBytes, true, s);
 }
 
 rmb_status rmb_flow_field(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,

@@ -63,6 +63,8 @@ struct PairJob {
     float a_f, four_a2_f, k_near_iso_f, k_near_rr_f;
 };
 
+hipError_t launch_store_pair_job(const PairJob &j, PairJob *dst, hipStream_t s);
+
 // Number of source splits and the split length for a system of nb blobs.
 // A function of nb only, so that a system's arithmetic does not depend on
 // what else shares the launch.
@@ -84,23 +86,31 @@ hipError_t launch_pack_sub_sources(int precision, const double *pos, const doubl
                                    int32_t n_sub, double a, int wall, void *src, int *flag, hipStream_t s);
 
 // One system's share of a launch of the pair kernel that evaluates each pair
-// block once (pair_sym_kernel): workgroups [wg_begin, wg_begin + T(T+1)/2)
-// are the block pairs (I <= J) of its T = ceil(nb / B) blocks; reduction
-// workgroups [red_begin, red_begin + sym_reduce_groups(nb)) add the partials
-// into vel.
+// block once (pair_sym_kernel).  The T(T+1)/2 block pairs (I <= J) of its
+// T = ceil(nb / B) blocks are numbered row by row; they are evaluated in
+// bands of whole rows [I0, I1) (tiles [t0, t0 + band tiles)), so that the
+// partial sums of one band at a time are stored: workgroups [wg_begin,
+// wg_begin + band tiles) are the band's tiles, and reduction workgroups
+// [red_begin, red_begin + sym_reduce_groups_band(...)) add the band's
+// partials of every blob they touch into an FP64 accumulator (first band:
+// stored; later bands: added), the last band writing the result.
 struct SymJob {
     const double *tpos;  // [nb][3] positions
     const double *lam;   // [nb][3] operand (the target's own force for M^T lambda)
-    double *vpart;       // [tiles][3][B] target-side sums (FP32 pairs: floats at the same base)
-    double *upart;       // [tiles][3][B] source-side sums (likewise)
+    double *vpart;       // [band tiles][3][B] target-side sums (FP32 pairs: floats at the same base)
+    double *upart;       // [band tiles][3][B] source-side sums (likewise)
     double *vel;         // [nb][3] result, prefactor applied (unused with epi)
+    double *acc;         // [nb][3] FP64 sums of the bands so far (several bands only; may be vel)
     const void *epi;     // NULL, or the system's saddle-operator rows (a SaddleJob): the
                          // reduction then writes the blob rows of A x (or b - A x) instead of vel
     int64_t nb;
     int64_t wg_begin;
     int64_t red_begin;
+    int64_t t0;          // first tile of the band
     int32_t n_blk;
     int32_t B;
+    int32_t I0, I1;      // block rows of the band
+    int32_t first, last; // the band is the system's first / last
     int32_t f32;         // partials are floats (FP32 pairs: each tile's sums are FP32 values)
     int32_t pad;
     double a, four_a2, k_near_iso, k_near_rr;
@@ -108,17 +118,33 @@ struct SymJob {
 };
 
 // Block size and block count of the symmetric product for nb blobs (a
-// function of nb only); tiles and partial storage it needs.
+// function of nb only); tiles it evaluates.
 void sym_plan(int64_t nb, int32_t *B, int32_t *n_blk);
 int64_t sym_tiles(int64_t nb);
-int64_t sym_reduce_groups(int64_t nb);
-size_t sym_partial_doubles(int64_t nb);
+// Bands: consecutive block rows whose tiles' partials (counted in FP64,
+// whatever the pair precision, so that the partition depends on nb alone)
+// fit `band_bytes`; a single row always forms a band of its own.
+struct SymBand {
+    int32_t I0, I1;
+    int64_t t0, tiles;
+};
+// Default partial storage of one band: 4 GiB, so that every product up to
+// about 210,000 blobs runs in one band and larger ones in a few.
+constexpr size_t kSymBandBytes = size_t(4) << 30;
+std::vector<SymBand> sym_bands(int64_t nb, size_t band_bytes);
+// Doubles of partial storage for the largest band (vpart + upart).
+size_t sym_band_partial_doubles(int64_t nb, size_t band_bytes);
+// Reduction workgroups of one band: blobs of blocks [I0, T), or all blobs
+// for the last band (which writes every blob's result).
+int64_t sym_reduce_groups_band(int64_t nb, int32_t B, const SymBand &b, bool last);
+// One job record written to device memory by a kernel (from its argument).
+hipError_t launch_store_sym_job(const SymJob &j, SymJob *dst, hipStream_t s);
 // Systems of at least this many blobs use the symmetric product.
 constexpr int64_t kSymMinBlobs = 1024;
 inline bool use_sym(int64_t nb) { return nb >= kSymMinBlobs; }
 hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs, int64_t n_tiles,
                            hipStream_t s);
-// n_wg reduction workgroups (sym_reduce_groups per job), then
+// n_wg reduction workgroups (sym_reduce_groups_band per job), then
 // (n_body + 15) / 16 more for the saddle body rows of `sd` (none when sd is
 // null).
 struct SaddleJob;

@@ -202,6 +202,7 @@ struct Job {
     double *vel = nullptr;  // reduced product of the symmetric kernel
     bool sym = false;
     int32_t symB = 0, symT = 0;
+    std::vector<SymBand> bands;  // symmetric product: bands of tile rows
     BodyWork *items_d = nullptr;
     double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *V = nullptr;
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
@@ -227,7 +228,7 @@ struct Job {
 static size_t job_bytes(Job &J) {
     const int64_t nb = J.nb, N = J.N, n = J.n;
     size_t t = 0;
-    const size_t part = J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24;
+    const size_t part = J.sym ? sym_band_partial_doubles(nb, kSymBandBytes) * 8 : (size_t)J.pj.n_split * nb * 24;
     t += al((N + 1) * 8) + al(nb * 4) + al(J.sym ? 0 : nb * sizeof(SrcF64)) + al(part) + al(nb * 24);
     t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
     t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8) + al(256 * 8);
@@ -246,7 +247,7 @@ static void job_carve(Job &J) {
     J.off_d = (int64_t *)take((N + 1) * 8);
     J.blob_body = (int32_t *)take(nb * 4);
     J.src = J.sym ? nullptr : take(nb * sizeof(SrcF64));  // packed sources: one-sided kernel only
-    J.partial = (double *)take(J.sym ? sym_partial_doubles(nb) * 8 : (size_t)J.pj.n_split * nb * 24);
+    J.partial = (double *)take(J.sym ? sym_band_partial_doubles(nb, kSymBandBytes) * 8 : (size_t)J.pj.n_split * nb * 24);
     J.vel = (double *)take(nb * 24);
     J.x = (double *)take(n * 8);
     J.b = (double *)take(n * 8);
@@ -400,7 +401,10 @@ struct Engine {
         }
         pair_job_init(&J->pj, sys->pos, nullptr, nullptr, J->nb, sys->a);
         J->sym = use_sym(J->nb);
-        if (J->sym) sym_plan(J->nb, &J->symB, &J->symT);
+        if (J->sym) {
+            sym_plan(J->nb, &J->symB, &J->symT);
+            J->bands = sym_bands(J->nb, kSymBandBytes);
+        }
         J->bytes = job_bytes(*J);
         if (J->bytes > ctx->arena->budget())
             return fail(ctx, RMB_ENOMEM, "request needs %zu bytes of device memory, budget is %zu", J->bytes,
@@ -496,7 +500,7 @@ struct Engine {
     // never needs staging that the budget cannot provide.
     static size_t stage_need(const Job &J) {
         return 2 * al(J.N * sizeof(BodyWork)) + al(J.N * sizeof(BigBody)) + al((J.N + 1) * 8) +
-               al((size_t)(J.m + 1) * 8) + 8192;
+               al((size_t)(J.m + 1) * 8) + 8192 + 2 * J.bands.size() * sizeof(SymJob);
     }
     static constexpr size_t kStageFixed = 32768;  // alignment of the shared tables
     size_t stage_reserved = kStageFixed;
@@ -671,12 +675,18 @@ struct Engine {
         int64_t wg_pk = 0;
         std::vector<PairJob> pairs[2][2];  // [fp32][wall]
         int64_t tiles[2][2] = {{0, 0}, {0, 0}};
-        // symmetric product: [fp32][wall][block size 64/128/256/512]
-        std::vector<SymJob> syms[2][2][4];
-        int64_t stiles[2][2][4] = {};
-        std::vector<SymJob> sred;  // reduction table (all symmetric jobs)
-        int64_t wg_sred = 0;
-        auto bidx = [](int B) { return B == 64 ? 0 : B == 128 ? 1 : B == 256 ? 2 : 3; };
+        // symmetric product, per band index: tile tables [fp32][wall][block
+        // size 64/128/256] and the reduction table of the systems with that band
+        struct BandTables {
+            std::vector<SymJob> syms[2][2][3];
+            int64_t stiles[2][2][3] = {};
+            size_t o_sym[2][2][3] = {};
+            std::vector<SymJob> sred;
+            int64_t wg_sred = 0;
+            size_t o_sred = 0;
+        };
+        std::vector<BandTables> bt;
+        auto bidx = [](int B) { return B == 64 ? 0 : B == 128 ? 1 : 2; };
         std::vector<SaddleJob> sd;
         int64_t wg_sd_blob = 0, wg_sd_body = 0;
         for (Job *J : mv) {
@@ -700,8 +710,9 @@ struct Engine {
                 y.tpos = J->sys.pos;
                 y.lam = xin;
                 y.vpart = J->partial;
-                y.upart = J->partial + (size_t)sym_tiles(J->nb) * J->symB * 3;
+                y.upart = J->partial + sym_band_partial_doubles(J->nb, kSymBandBytes) / 2;
                 y.vel = J->vel;
+                y.acc = J->vel;  // unused by the product otherwise (the reduction writes the saddle rows)
                 y.nb = J->nb;
                 y.n_blk = J->symT;
                 y.B = J->symB;
@@ -712,13 +723,22 @@ struct Engine {
                 y.pref = mobility_prefactor(J->sys.a, J->sys.eta);
                 y.f32 = f32 ? 1 : 0;
                 const int bi = bidx(J->symB);
-                y.wg_begin = stiles[f32][wl][bi];
-                y.red_begin = wg_sred;
-                stiles[f32][wl][bi] += sym_tiles(J->nb);
-                wg_sred += sym_reduce_groups(J->nb);
-                syms[f32][wl][bi].push_back(y);
                 y.epi = (const void *)(uintptr_t)sd.size();  // index of its saddle rows; patched below
-                sred.push_back(y);
+                const int nband = (int)J->bands.size();
+                if ((int)bt.size() < nband) bt.resize(nband);
+                for (int b = 0; b < nband; ++b) {
+                    const SymBand &band = J->bands[b];
+                    BandTables &T = bt[b];
+                    y.t0 = band.t0;
+                    y.I0 = band.I0, y.I1 = band.I1;
+                    y.first = b == 0, y.last = b == nband - 1;
+                    y.wg_begin = T.stiles[f32][wl][bi];
+                    y.red_begin = T.wg_sred;
+                    T.stiles[f32][wl][bi] += band.tiles;
+                    T.wg_sred += sym_reduce_groups_band(J->nb, J->symB, band, y.last);
+                    T.syms[f32][wl][bi].push_back(y);
+                    T.sred.push_back(y);
+                }
             } else {
                 PairJob pj = J->pj;
                 pj.tile_begin = tiles[f32][wl];
@@ -810,24 +830,30 @@ struct Engine {
         for (int a = 0; a < 2; ++a)
             for (int b = 0; b < 2; ++b)
                 o_pair[a][b] = pairs[a][b].empty() ? 0 : st.put(pairs[a][b].data(), pairs[a][b].size() * sizeof(PairJob));
-        size_t o_sym[2][2][4] = {};
-        for (int a = 0; a < 2; ++a)
-            for (int b = 0; b < 2; ++b)
-                for (int c = 0; c < 4; ++c)
-                    if (!syms[a][b][c].empty())
-                        o_sym[a][b][c] = st.put(syms[a][b][c].data(), syms[a][b][c].size() * sizeof(SymJob));
+        size_t n_sred = 0;
+        for (BandTables &T : bt) {
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    for (int c = 0; c < 3; ++c)
+                        if (!T.syms[a][b][c].empty())
+                            T.o_sym[a][b][c] = st.put(T.syms[a][b][c].data(), T.syms[a][b][c].size() * sizeof(SymJob));
+            n_sred += T.sred.size();
+        }
         size_t o_sd = sd.empty() ? 0 : st.put(sd.data(), sd.size() * sizeof(SaddleJob));
         size_t o_orth = orth.empty() ? 0 : st.put(orth.data(), orth.size() * sizeof(KrylovJob));
         size_t o_axp = axp.empty() ? 0 : st.put(axp.data(), axp.size() * sizeof(KrylovJob));
         size_t o_un = un.empty() ? 0 : st.put(un.data(), un.size() * sizeof(KrylovJob));
         // the combine and reduction tables hold device addresses inside the
         // staging buffer (coefficients, saddle rows): patched once it is sized
-        size_t o_comb = 0, o_sred = 0;
-        RMB_TRY(ensure_stage(st.used + comb.size() * sizeof(KrylovJob) + sred.size() * sizeof(SymJob) + 8192));
+        size_t o_comb = 0;
+        RMB_TRY(ensure_stage(st.used + comb.size() * sizeof(KrylovJob) + n_sred * sizeof(SymJob) + 8192 +
+                             256 * bt.size()));
         for (auto &K : comb) K.coef = (const double *)(stage_d + (size_t)(uintptr_t)K.coef);
-        for (auto &y : sred) y.epi = stage_d + o_sd + (size_t)(uintptr_t)y.epi * sizeof(SaddleJob);
         if (!comb.empty()) o_comb = st.put(comb.data(), comb.size() * sizeof(KrylovJob));
-        if (!sred.empty()) o_sred = st.put(sred.data(), sred.size() * sizeof(SymJob));
+        for (BandTables &T : bt) {
+            for (auto &y : T.sred) y.epi = stage_d + o_sd + (size_t)(uintptr_t)y.epi * sizeof(SaddleJob);
+            if (!T.sred.empty()) T.o_sred = st.put(T.sred.data(), T.sred.size() * sizeof(SymJob));
+        }
         RMB_TRY(ensure_stage(st.used));
         memcpy(stage_hp[par], st.host.data(), st.used);
         RMB_HIP(ctx, hipMemcpyAsync(stage_d, stage_hp[par], st.used, hipMemcpyHostToDevice, s));
@@ -878,21 +904,22 @@ struct Engine {
                     RMB_TRY(pair_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0,
                                         (const PairJob *)D(o_pair[a][b]), (int32_t)pairs[a][b].size(), tiles[a][b], s));
         {
-            const int Bs[4] = {64, 128, 256, 512};
-            for (int a = 0; a < 2; ++a)
-                for (int b = 0; b < 2; ++b)
-                    for (int c = 0; c < 4; ++c)
-                        if (!syms[a][b][c].empty())
-                            RMB_TRY(sym_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0, Bs[c],
-                                               (const SymJob *)D(o_sym[a][b][c]), (int32_t)syms[a][b][c].size(),
-                                               stiles[a][b][c], s));
-            // the saddle body rows ride on the reduction launch when there is one
-            if (!sred.empty()) {
-                RMB_HIP(ctx, launch_sym_reduce((const SymJob *)D(o_sred), (int32_t)sred.size(), wg_sred,
-                                               sd.empty() ? nullptr : (const SaddleJob *)D(o_sd), (int32_t)sd.size(),
-                                               wg_sd_body, s));
-                wg_sd_body = 0;
+            const int Bs[3] = {64, 128, 256};
+            for (size_t band = 0; band < bt.size(); ++band) {
+                BandTables &T = bt[band];
+                for (int a = 0; a < 2; ++a)
+                    for (int b = 0; b < 2; ++b)
+                        for (int c = 0; c < 3; ++c)
+                            if (!T.syms[a][b][c].empty())
+                                RMB_TRY(sym_launch(ctx, a ? RMB_PREC_FP32_PAIRS : RMB_PREC_FP64, b != 0, Bs[c],
+                                                   (const SymJob *)D(T.o_sym[a][b][c]),
+                                                   (int32_t)T.syms[a][b][c].size(), T.stiles[a][b][c], s));
+                // the saddle body rows ride on the first reduction launch
+                RMB_HIP(ctx, launch_sym_reduce((const SymJob *)D(T.o_sred), (int32_t)T.sred.size(), T.wg_sred,
+                                               band == 0 && !sd.empty() ? (const SaddleJob *)D(o_sd) : nullptr,
+                                               (int32_t)sd.size(), band == 0 ? wg_sd_body : 0, s));
             }
+            if (!bt.empty()) wg_sd_body = 0;
         }
         if (!sd.empty())
             RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));

@@ -377,9 +377,9 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         if (jobs[mid].wg_begin <= w) lo = mid; else hi = mid - 1;
     }
     const SymJob &J = jobs[lo];
-    const int64_t t = w - J.wg_begin;
+    const int64_t slot = w - J.wg_begin;  // the tile's partials within its band
     int32_t I, Jb;
-    tile_ij(t, J.n_blk, &I, &Jb);
+    tile_ij(J.t0 + slot, J.n_blk, &I, &Jb);
     const int64_t nb = J.nb;
     const int lane = threadIdx.x;
     // sources are read straight from the positions and forces (no packed
@@ -394,8 +394,8 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     // tile sums are stored in the pair precision: with FP32 pairs each one is
     // an FP32 sum over 64 sources (exact as a float for B = 64; for larger B
     // the FP64 sum over the tile's groups, rounded once)
-    const gmem<R> vout = as_global((R *)J.vpart + t * (int64_t)B * 3);
-    const gmem<R> uout = as_global((R *)J.upart + t * (int64_t)B * 3);
+    const gmem<R> vout = as_global((R *)J.vpart + slot * (int64_t)B * 3);
+    const gmem<R> uout = as_global((R *)J.upart + slot * (int64_t)B * 3);
 
     double u64[G][3];
 #pragma unroll
@@ -583,19 +583,22 @@ hipError_t launch_pair_lds_f32(bool wall, const PairJob *jobs, int32_t n_jobs, i
     return hipGetLastError();
 }
 
-// v[k] = pref * (sum_{J >= K} vpart[tile(K,J)][kk] + sum_{I < K} upart[tile(I,K)][kk]).
-// A workgroup covers 16 blobs with 16 threads each: thread (q, b) sums the
-// contributions q, q+16, q+32, ... of blob b (in the order listed above), and
-// the 16 partial sums are added in the order q = 0..15.
+// v[k] = pref * (sum_{J >= K} vpart[tile(K,J)][kk] + sum_{I < K} upart[tile(I,K)][kk]),
+// taken band by band.  Within a band the contributions of a blob of block K
+// are listed as its row tiles (K, J >= K) when K is one of the band's rows,
+// then its column tiles (I, K) for the band's rows I < K; the first band's
+// sum is stored in an FP64 accumulator, later bands add theirs to it, and
+// the last band writes pref times the total (one band: no accumulator, the
+// sum goes straight to the output).
 constexpr int kRedWaves = 16;
 
 // One workgroup of 16 waves per 64 blobs of a block: wave q adds the blobs'
-// contributions q, q + 16, ... (row tiles, then column tiles), each read as
-// one row of 64 consecutive values per component of the [tile][3][B]
-// partials; the waves' sums are then added in a fixed order.  Workgroups
-// past n_red carry the saddle body rows of a solve step (16 bodies per
-// workgroup, a wave each): they read only the Krylov vector, so they share
-// the launch with the reduction instead of taking one of their own.
+// contributions q, q + 16, ... in the order above, each read as one row of 64
+// consecutive values per component of the [tile][3][B] partials; the waves'
+// sums are then added in a fixed order.  Workgroups past n_red carry the
+// saddle body rows of a solve step (16 bodies per workgroup, a wave each):
+// they read only the Krylov vector, so they share the launch with the
+// reduction instead of taking one of their own.
 __global__ __launch_bounds__(1024) void sym_reduce_kernel(const SymJob *__restrict__ jobs, int32_t n_jobs,
                                                           int64_t n_red, const SaddleJob *__restrict__ sd,
                                                           int32_t n_sd, int64_t n_body) {
@@ -613,27 +616,30 @@ __global__ __launch_bounds__(1024) void sym_reduce_kernel(const SymJob *__restri
         if (jobs[mid].red_begin <= w) lo = mid; else hi = mid - 1;
     }
     const SymJob &J = jobs[lo];
-    const int32_t B = J.B, T = J.n_blk;
-    const int64_t k0 = (w - J.red_begin) * 64;  // groups of 64 never straddle a block (B is a multiple of 64)
+    const int32_t B = J.B, T = J.n_blk, I0 = J.I0, I1 = J.I1;
+    // groups of 64 never straddle a block (B is a multiple of 64); the last
+    // band covers every blob, the others the blobs of blocks >= I0
+    const int64_t k0 = (J.last ? 0 : (int64_t)I0 * B) + (w - J.red_begin) * 64;
     const int64_t k = k0 + lane;
     const int32_t K = (int32_t)(k0 / B);
     const int64_t kk = k0 % B + lane;
     double s[3] = {0.0, 0.0, 0.0};
-    if (k < J.nb) {
-        auto tile = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i); };
-        const int32_t nv = T - K;  // vpart contributions, then K upart ones
+    if (k < J.nb && K >= I0) {
+        auto slot = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i) - J.t0; };
+        const int32_t nv = K < I1 ? T - K : 0;            // row tiles (K, K + c)
+        const int32_t n = nv + (K < I1 ? K : I1) - I0;    // then column tiles (I0 + c - nv, K)
         if (J.f32) {
 #pragma unroll 4
-            for (int32_t c = q; c < T; c += kRedWaves) {
-                const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + tile(K, K + c) * B * 3 + kk
-                                                             : (const float *)J.upart + tile(c - nv, K) * B * 3 + kk);
+            for (int32_t c = q; c < n; c += kRedWaves) {
+                const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + slot(K, K + c) * B * 3 + kk
+                                                             : (const float *)J.upart + slot(I0 + c - nv, K) * B * 3 + kk);
                 s[0] += (double)p[0], s[1] += (double)p[B], s[2] += (double)p[2 * B];
             }
         } else {
 #pragma unroll 4
-            for (int32_t c = q; c < T; c += kRedWaves) {
-                const gmem<const double> p = as_global(c < nv ? J.vpart + tile(K, K + c) * B * 3 + kk
-                                                              : J.upart + tile(c - nv, K) * B * 3 + kk);
+            for (int32_t c = q; c < n; c += kRedWaves) {
+                const gmem<const double> p = as_global(c < nv ? J.vpart + slot(K, K + c) * B * 3 + kk
+                                                              : J.upart + slot(I0 + c - nv, K) * B * 3 + kk);
                 s[0] += p[0], s[1] += p[B], s[2] += p[2 * B];
             }
         }
@@ -642,7 +648,16 @@ __global__ __launch_bounds__(1024) void sym_reduce_kernel(const SymJob *__restri
     __syncthreads();
     if (q == 0 && k < J.nb) {
         double t[3] = {0.0, 0.0, 0.0};
+        if (!J.first) {
+            const gmem<const double> a = as_global((const double *)J.acc + 3 * k);
+            t[0] = a[0], t[1] = a[1], t[2] = a[2];
+        }
         for (int r = 0; r < kRedWaves; ++r) t[0] += part[r][0][lane], t[1] += part[r][1][lane], t[2] += part[r][2][lane];
+        if (!J.last) {
+            const gmem<double> a = as_global(J.acc + 3 * k);
+            a[0] = t[0], a[1] = t[1], a[2] = t[2];
+            return;
+        }
         const double v[3] = {J.pref * t[0], J.pref * t[1], J.pref * t[2]};
         if (J.epi) {
             // inside a solve: the blob rows of the saddle-point operator
@@ -656,10 +671,8 @@ __global__ __launch_bounds__(1024) void sym_reduce_kernel(const SymJob *__restri
     }
 }
 
-int64_t sym_reduce_groups(int64_t nb) { return (nb + 63) / 64; }
-
 void sym_plan(int64_t nb, int32_t *B, int32_t *n_blk) {
-    int32_t b = nb <= 16384 ? 64 : nb <= 65536 ? 128 : nb <= 262144 ? 256 : 512;
+    int32_t b = nb <= 16384 ? 64 : nb <= 65536 ? 128 : 256;
     *B = b;
     *n_blk = (int32_t)((nb + b - 1) / b);
 }
@@ -670,10 +683,34 @@ int64_t sym_tiles(int64_t nb) {
     return (int64_t)T * (T + 1) / 2;
 }
 
-size_t sym_partial_doubles(int64_t nb) {
+std::vector<SymBand> sym_bands(int64_t nb, size_t band_bytes) {
     int32_t B, T;
     sym_plan(nb, &B, &T);
-    return (size_t)sym_tiles(nb) * B * 3 * 2;  // vpart + upart
+    const int64_t cap = std::max<int64_t>(1, (int64_t)(band_bytes / ((size_t)B * 3 * 2 * sizeof(double))));
+    std::vector<SymBand> out;
+    int64_t t = 0;
+    int32_t I = 0;
+    while (I < T) {
+        SymBand b{I, I, t, 0};
+        while (b.I1 < T && (b.I1 == I || b.tiles + (T - b.I1) <= cap)) b.tiles += T - b.I1, ++b.I1;
+        t += b.tiles;
+        I = b.I1;
+        out.push_back(b);
+    }
+    return out;
+}
+
+size_t sym_band_partial_doubles(int64_t nb, size_t band_bytes) {
+    int32_t B, T;
+    sym_plan(nb, &B, &T);
+    int64_t most = 0;
+    for (const SymBand &b : sym_bands(nb, band_bytes)) most = std::max(most, b.tiles);
+    return (size_t)most * B * 3 * 2;  // vpart + upart
+}
+
+int64_t sym_reduce_groups_band(int64_t nb, int32_t B, const SymBand &b, bool last) {
+    const int64_t first = last ? 0 : (int64_t)b.I0 * B;
+    return (nb - first + 63) / 64;
 }
 
 template <typename SRC, bool WALL>
@@ -682,8 +719,7 @@ static void launch_sym_b(int B, const SymJob *jobs, int32_t n_jobs, int64_t n_ti
     switch (B) {
         case 64: hipLaunchKernelGGL((pair_sym_kernel<SRC, 64, WALL>), g, b, 0, s, jobs, n_jobs); break;
         case 128: hipLaunchKernelGGL((pair_sym_kernel<SRC, 128, WALL>), g, b, 0, s, jobs, n_jobs); break;
-        case 256: hipLaunchKernelGGL((pair_sym_kernel<SRC, 256, WALL>), g, b, 0, s, jobs, n_jobs); break;
-        default: hipLaunchKernelGGL((pair_sym_kernel<SRC, 512, WALL>), g, b, 0, s, jobs, n_jobs); break;
+        default: hipLaunchKernelGGL((pair_sym_kernel<SRC, 256, WALL>), g, b, 0, s, jobs, n_jobs); break;
     }
 }
 
@@ -697,6 +733,29 @@ hipError_t launch_pair_sym(int precision, bool wall, int B, const SymJob *jobs, 
         if (wall) launch_sym_b<SrcF64, true>(B, jobs, n_jobs, n_tiles, s);
         else launch_sym_b<SrcF64, false>(B, jobs, n_jobs, n_tiles, s);
     }
+    return hipGetLastError();
+}
+
+// Job records written by a one-thread kernel from its argument (no host
+// staging buffer): used where a caller's stream must not depend on host
+// memory the library would have to allocate.
+template <typename T>
+__device__ __forceinline__ void store_words(const T &j, T *dst) {
+    static_assert(sizeof(T) % 4 == 0, "job records are whole words");
+    const int *w = (const int *)&j;
+    const gmem<int> d = as_global((int *)dst);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(T) / 4); ++k) d[k] = w[k];
+}
+__global__ void store_sym_job_kernel(SymJob j, SymJob *dst) { store_words(j, dst); }
+__global__ void store_pair_job_kernel(PairJob j, PairJob *dst) { store_words(j, dst); }
+
+hipError_t launch_store_sym_job(const SymJob &j, SymJob *dst, hipStream_t s) {
+    hipLaunchKernelGGL(store_sym_job_kernel, dim3(1), dim3(1), 0, s, j, dst);
+    return hipGetLastError();
+}
+hipError_t launch_store_pair_job(const PairJob &j, PairJob *dst, hipStream_t s) {
+    hipLaunchKernelGGL(store_pair_job_kernel, dim3(1), dim3(1), 0, s, j, dst);
     return hipGetLastError();
 }
 

@@ -3,7 +3,8 @@
 Bar: relative 2-norm error over the whole (Nb, 3) result, and the largest
 error of any one blob relative to the rms blob velocity, both <= 1e-12 for
 FP64 pairs and <= 1e-5 for FP32 pairs with FP64 accumulation.  Every block
-size of the symmetric product (64, 128, 256, 512 blobs) and the one-sided
+size of the symmetric product (64, 128, 256 blobs), products taken in
+several bands of tile rows, and the one-sided
 kernel are covered.
 """
 import numpy as np
@@ -113,15 +114,22 @@ def test_matvec_block128_full_parity(env, prec):
     assert err <= TOL[prec]
 
 
+_MILLION = {}
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_matvec_block512_sampled_rows(env, prec):
-    """A 160 x 160 monolayer lattice (25,600 icosahedra, 307,200 blobs): the
-    symmetric product with 512-blob blocks; sampled rows (the first and last
-    blob among them) against the oracle's per-row sums."""
+def test_matvec_million_blobs_sampled_rows(env, prec):
+    """A 289 x 289 monolayer lattice (83,521 icosahedra, 1,002,252 blobs) in
+    the default 16 GiB budget: the symmetric product's partial sums (94 GB
+    for FP64 pairs in one pass) are taken in bands of tile rows, so its
+    workspace stays bounded; sampled rows (the first and last blob among
+    them) against the oracle's per-row sums."""
     rmb = env[0]
-    sus, lam = S.icosahedra_monolayer(n_side=160)
-    assert rmb.pair_plan(sus.n_blobs) == (True, 512)
-    print(f"[gpu] 512-blob blocks {prec} nb={sus.n_blobs}", flush=True)
+    if not _MILLION:
+        _MILLION["case"] = S.icosahedra_monolayer(n_side=289)
+    sus, lam = _MILLION["case"]
+    assert sus.n_blobs > 10 ** 6 and rmb.pair_plan(sus.n_blobs) == (True, 256)
+    print(f"[gpu] million-blob product {prec} nb={sus.n_blobs}", flush=True)
     v = _run(env, sus, lam, prec)
     rows = np.random.default_rng(17).choice(sus.n_blobs, 126, replace=False)
     rows = np.concatenate([rows, [0, sus.n_blobs - 1]])
