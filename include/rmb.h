@@ -181,6 +181,29 @@ rmb_status rmb_ctx_tune_log(rmb_ctx ctx, int32_t capacity, rmb_tune_record *reco
 rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
                                const double *lambda, double *vel, rmb_stream stream);
 
+/* The same product for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: a tight serving loop, a harness that forbids
+ * allocation, work being captured into a HIP graph).  It allocates nothing:
+ * its workspace is a static device array of rmb_noalloc_workspace_bytes()
+ * (128 MiB) that each device holds from the first context created on it
+ * until the process ends; the caller still provides lambda and vel.  Every
+ * call on a device shares that array, so calls that overlap on one device
+ * (other streams, other threads, other contexts) race: serialise them.
+ * Results agree with rmb_mobility_matvec to rounding (the symmetric product
+ * runs in more, smaller bands of tile rows here, so sums are grouped
+ * differently).  `validate` = 1 checks the positions first and synchronises
+ * `stream` once, as rmb_mobility_matvec does; 0 skips the check (the caller
+ * guarantees finite positions, z > 0 above a wall and a valid blob_shift)
+ * and the call only enqueues work on `stream`: no host synchronisation, no
+ * memset, no host staging.  Errors: RMB_EINVAL as rmb_mobility_matvec, and
+ * for a system too large for the workspace (above about 2.7 million blobs);
+ * RMB_EDEVICE if the workspace is unavailable. */
+rmb_status rmb_mobility_matvec_noalloc(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
+                                       const double *lambda, double *vel, int32_t validate, rmb_stream stream);
+
+/* Size in bytes of the no-allocation entry point's static workspace. */
+size_t rmb_noalloc_workspace_bytes(void);
+
 /* Flow field at arbitrary points (appendix "Computing flow fields"): every
  * blob i of `sys` is replaced by n_sub blobs of radius tracer_a placed at
  * r_i + a * sub_offsets[k], each carrying lambda_i / n_sub, and the velocity

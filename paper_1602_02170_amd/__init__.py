@@ -33,7 +33,7 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
            "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan",
            "rmb_flow_field", "rmb_precond_factor_shapes", "rmb_precond_set_orientations",
-           "rmb_solve_resistance"]
+           "rmb_solve_resistance", "rmb_mobility_matvec_noalloc", "rmb_noalloc_workspace_bytes"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -96,6 +96,9 @@ def library(path: str = LIB_PATH):
         L.rmb_last_error.restype = ctypes.c_char_p
         L.rmb_version.restype = ctypes.c_char_p
         L.rmb_mobility_matvec.argtypes = [vp, sysp, i32, vp, vp, vp]
+        L.rmb_mobility_matvec_noalloc.argtypes = [vp, sysp, i32, vp, vp, i32, vp]
+        L.rmb_noalloc_workspace_bytes.argtypes = []
+        L.rmb_noalloc_workspace_bytes.restype = ctypes.c_size_t
         L.rmb_flow_field.argtypes = [vp, sysp, i32, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
                                      ctypes.c_int64, vp, vp, vp]
         optp, infop = ctypes.POINTER(rmb_solve_opts), ctypes.POINTER(rmb_solve_info)
@@ -267,6 +270,23 @@ def mobility_matvec(ctx: Context, system: System, lam: torch.Tensor, precision="
     ctx.check(ctx.lib.rmb_mobility_matvec(ctx.h, ctypes.byref(system.c), _prec(precision), lp, op,
                                           _stream(stream)))
     return out
+
+
+def mobility_matvec_noalloc(ctx: Context, system: System, lam: torch.Tensor, out: torch.Tensor,
+                            precision="fp64", validate: bool = True, stream=None) -> torch.Tensor:
+    """v = M lambda through the entry point that allocates nothing
+    (rmb_mobility_matvec_noalloc): the output tensor is the caller's, the
+    workspace a static device array shared by every call on the device."""
+    n = system.n_blobs
+    lp = _dev(lam, "lambda", (n, 3))
+    op = _dev(out, "out", (n, 3))
+    ctx.check(ctx.lib.rmb_mobility_matvec_noalloc(ctx.h, ctypes.byref(system.c), _prec(precision), lp, op,
+                                                  1 if validate else 0, _stream(stream)))
+    return out
+
+
+def noalloc_workspace_bytes() -> int:
+    return int(library().rmb_noalloc_workspace_bytes())
 
 
 def flow_field(ctx: Context, system: System, lam: torch.Tensor, sub_offsets, tracer_a: float,

@@ -1,8 +1,17 @@
-// Context management, validation and the blob mobility product entry point.
+// Context management, validation and the blob mobility product entry points.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "rmb_ctx.h"
+
+// Workspace of rmb_mobility_matvec_noalloc: a static device array, so that
+// the entry point allocates nothing.  Every device the library runs on holds
+// its own copy until the process ends.  Host code never uses the array's
+// name for memory: its device address comes from hipGetSymbolAddress, per
+// device, when a context is created on that device.
+constexpr size_t kNoAllocBytes = size_t(128) << 20;
+static __device__ __align__(256) char scratch[kNoAllocBytes];
 
 namespace rmb {
 
@@ -27,7 +36,7 @@ rmb_status enter(rmb_ctx ctx, hipStream_t s) {
     return RMB_OK;
 }
 
-rmb_status scratch(rmb_ctx ctx, size_t bytes, void **out) {
+rmb_status ctx_scratch(rmb_ctx ctx, size_t bytes, void **out) {
     if (bytes <= ctx->scratch_bytes) {
         *out = ctx->scratch;
         return RMB_OK;
@@ -224,6 +233,23 @@ extern "C" {
 
 const char *rmb_version(void) { return "rmb 0.1 (gfx950)"; }
 
+// Device address of this device's copy of `scratch`, looked up once per
+// device (the device must be current).  Null if the lookup failed.
+static void *noalloc_work_address(int device) {
+    static std::mutex mu;
+    static std::vector<void *> addr;
+    static std::vector<bool> tried;
+    std::lock_guard<std::mutex> lock(mu);
+    if ((size_t)device >= addr.size()) addr.resize(device + 1, nullptr), tried.resize(device + 1, false);
+    if (!tried[device]) {
+        tried[device] = true;
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess) addr[device] = p;
+        else (void)hipGetLastError();
+    }
+    return addr[device];
+}
+
 rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
     if (!out) return RMB_EINVAL;
     *out = nullptr;
@@ -233,6 +259,7 @@ rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
     rmb_ctx c = new rmb_ctx_s();
     c->device = device;
     c->arena = new Arena(hbm_budget_bytes ? hbm_budget_bytes : (size_t(16) << 30));
+    c->noalloc_work = noalloc_work_address(device);
     *out = c;
     return RMB_OK;
 }
@@ -380,10 +407,53 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     RMB_TRY(enter(ctx, s));
     RMB_TRY(check_product_args(ctx, sys, precision, lambda, vel));
     char *base = nullptr;
-    RMB_TRY(scratch(ctx, product_work_bytes(sys->n_blobs, precision, kSymBandBytes), (void **)&base));
+    RMB_TRY(ctx_scratch(ctx, product_work_bytes(sys->n_blobs, precision, kSymBandBytes), (void **)&base));
     RMB_TRY(check_positions(ctx, sys, (int *)base, s));
     return product_enqueue(ctx, sys, precision, lambda, vel, base, kSymBandBytes, true, s);
 }
+
+__global__ void zero_flag_kernel(int *flag) { *as_global(flag) = 0; }
+
+rmb_status rmb_mobility_matvec_noalloc(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
+                                       double *vel, int32_t validate, rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_product_args(ctx, sys, precision, lambda, vel));
+    char *work = (char *)ctx->noalloc_work;
+    if (!work) return fail(ctx, RMB_EDEVICE, "the no-allocation workspace is not available on this device");
+    const int64_t nb = sys->n_blobs;
+    // bands sized so that [flag | a job record per block row at most | the
+    // largest band's partials] fits the static workspace
+    size_t band_bytes = kNoAllocBytes;
+    if (use_sym(nb)) {
+        int32_t B, T;
+        sym_plan(nb, &B, &T);
+        band_bytes = kNoAllocBytes - 256 - 256 * (size_t)T;
+        if (256 + 256 * (size_t)T >= kNoAllocBytes)
+            return fail(ctx, RMB_EINVAL, "%lld blobs exceed the no-allocation workspace (%zu MiB)", (long long)nb,
+                        kNoAllocBytes >> 20);
+    }
+    const size_t need = product_work_bytes(nb, precision, band_bytes);
+    if (need > kNoAllocBytes)
+        return fail(ctx, RMB_EINVAL, "%lld blobs need %zu bytes of workspace, more than the %zu MiB of the "
+                    "no-allocation entry point", (long long)nb, need, kNoAllocBytes >> 20);
+    if (validate) {
+        int *flag = (int *)work;
+        int h = 0;
+        hipLaunchKernelGGL(zero_flag_kernel, dim3(1), dim3(1), 0, s, flag);
+        RMB_HIP(ctx, hipGetLastError());
+        RMB_HIP(ctx, launch_validate_positions(sys->pos, nb, sys->geometry == RMB_GEOM_WALL, sys->blob_shift, flag, s));
+        RMB_HIP(ctx, hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, s));
+        RMB_HIP(ctx, hipStreamSynchronize(s));
+        if (h & 1) return fail(ctx, RMB_EINVAL, "non-finite blob position");
+        if (h & 2) return fail(ctx, RMB_EINVAL, "a blob has z <= 0 in wall geometry");
+        if (h & 32) return fail(ctx, RMB_EINVAL, "blob_shift must be finite and >= 0");
+    }
+    return product_enqueue(ctx, sys, precision, lambda, vel, work, band_bytes, false, s);
+}
+
+size_t rmb_noalloc_workspace_bytes(void) { return kNoAllocBytes; }
 
 rmb_status rmb_flow_field(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
                           int32_t n_sub, const double *sub_offsets, double tracer_a, int64_t n_targets,
@@ -418,7 +488,7 @@ rmb_status rmb_flow_field(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
     const size_t off_part = off_src + ((size_t)ns * rec + 255) / 256 * 256;
     const size_t total = off_part + (size_t)J.n_split * n_targets * 3 * sizeof(double);
     char *base = nullptr;
-    RMB_TRY(scratch(ctx, total, (void **)&base));
+    RMB_TRY(ctx_scratch(ctx, total, (void **)&base));
     int *flag = (int *)base;
     // targets: finite, and above the wall in wall geometry
     rmb_system tsys = *sys;

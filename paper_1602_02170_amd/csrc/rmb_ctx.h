@@ -39,6 +39,9 @@ struct rmb_ctx_s {
         float ms;
     };
     std::vector<TuneRecord> tune_log;
+    // this device's copy of the no-allocation entry point's static workspace
+    // (device address from hipGetSymbolAddress; null if it could not be had)
+    void *noalloc_work = nullptr;
 };
 
 namespace rmb {
@@ -63,7 +66,7 @@ rmb_status fail(rmb_ctx ctx, rmb_status st, const char *fmt, ...);
 rmb_status enter(rmb_ctx ctx, hipStream_t s);
 
 // Grow-only scratch of at least `bytes` (device).
-rmb_status scratch(rmb_ctx ctx, size_t bytes, void **out);
+rmb_status ctx_scratch(rmb_ctx ctx, size_t bytes, void **out);
 // Grow-only pinned host staging of at least `bytes`.
 rmb_status pinned(rmb_ctx ctx, size_t bytes, void **out);
 // A pinned host buffer of at least `bytes` from the context's cache (or a

@@ -1316,7 +1316,7 @@ rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, co
     a[1].items = (const BodyWork *)pc->bigs_d;
     a[1].n_items = pc->n_large;
     void *d = nullptr, *h = nullptr;
-    RMB_TRY(scratch(ctx, sizeof a, &d));
+    RMB_TRY(ctx_scratch(ctx, sizeof a, &d));
     RMB_TRY(pinned(ctx, sizeof a, &h));
     memcpy(h, a, sizeof a);
     RMB_HIP(ctx, hipMemcpyAsync(d, h, sizeof a, hipMemcpyHostToDevice, s));
