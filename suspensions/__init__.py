@@ -368,8 +368,11 @@ def sphere_lattice(n_side: int, n_blobs: int, phi: float, seed: Optional[int] = 
     fraction is phi = (4 pi / 3) R_h^3 / d^3 with d the centre-to-centre
     spacing and R_h the shell's hydrodynamic radius (the paper pairs a spacing
     of 4 R_g ~ 3.6 R_h with phi ~ 0.09).  Every shell has the reference
-    orientation.  Forces, torques and per-blob slips are N(0, 1) per
-    component.  The seed defaults to one per (n_blobs, phi index)."""
+    orientation.  Forces and torques are N(0, 1) per component; per-blob
+    slips are N(0, 1) per component in units of the velocity a unit force
+    gives an isolated shell, 1 / (6 pi eta R_h), so that the three random
+    loads move the bodies comparably.  The seed defaults to one per
+    (n_blobs, phi index)."""
     shp = sphere_shell(n_blobs, 1.0)
     a = 0.5 * min_spacing(shp)
     rh = SHELL_RH_HALF_SPACING[n_blobs]
@@ -384,6 +387,6 @@ def sphere_lattice(n_side: int, n_blobs: int, phi: float, seed: Optional[int] = 
     quats = np.tile(np.array([1.0, 0.0, 0.0, 0.0]), (n, 1))
     pos, off = assemble([shp] * n, centres, quats)
     FT = rng.standard_normal((n, 6))
-    slip = rng.standard_normal((pos.shape[0], 3))
+    slip = rng.standard_normal((pos.shape[0], 3)) / (6.0 * math.pi * rh)
     return Suspension(pos, off, centres.copy(), a, 1.0, False, FT, slip, tol, quats,
                       name=f"free-space {n_side}^3 lattice of {n_blobs}-blob shells, phi {phi:g}")
