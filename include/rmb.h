@@ -142,10 +142,35 @@ rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, in
  * (*block = number of source splits).  A function of nb only. */
 rmb_status rmb_pair_plan(int64_t nb, int32_t *symmetric, int32_t *block);
 
-/* Panel width (16 or 32) of the tile shape the autotuner chose for the
- * large-body factorisation of padded block size `padded_dim` on this context
- * (the first factorisation of that size times every candidate shape and
- * keeps the fastest), or 0 if no block of that size has been factorised yet. */
+/* Tile shapes of the large-body factorisation (bodies whose 3n x 3n block
+ * is too large for the LDS path; padded_dim = 3n rounded up to 32).  Which
+ * shape a batch uses:
+ *   - the shape forced with rmb_ctx_set_tile_shape for its padded size;
+ *   - else, for batches of fewer than 64 bodies, shape 0 (small batches are
+ *     never timed, and always get the same shape, so their factors do not
+ *     depend on what ran before);
+ *   - else the tuned shape: the first batch of a padded size times every
+ *     shape and keeps the fastest.  The choice is persisted (a line per
+ *     padded size in the file named by the environment variable
+ *     RMB_TUNE_CACHE, by default $XDG_CACHE_HOME/rmb/tune.txt or
+ *     $HOME/.cache/rmb/tune.txt; an empty value disables it) and every new
+ *     context reads it, so processes sharing the file factorise with the
+ *     same shape and give bitwise-identical results.
+ * Shapes change rounding only. */
+int32_t rmb_tile_shape_count(void);
+
+/* Panel width, 16-row tiles per wave and prefetched columns of `shape`
+ * (host outputs).  RMB_EINVAL for an unknown shape or a null pointer. */
+rmb_status rmb_tile_shape_info(int32_t shape, int32_t *panel, int32_t *row_tiles, int32_t *chunk);
+
+/* Forces `shape` for blocks of padded size `padded_dim` on this context
+ * (shape -1 returns the choice to the rules above).  RMB_EINVAL for a
+ * padded_dim that is not a positive multiple of 32 or an unknown shape. */
+rmb_status rmb_ctx_set_tile_shape(rmb_ctx ctx, int32_t padded_dim, int32_t shape);
+
+/* Panel width of the tuned shape for padded size `padded_dim` on this
+ * context (from this context's tuning or the persisted file), or 0 if
+ * there is none yet. */
 rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_width);
 
 /* One timing of the large-body factorisation autotuner. */
@@ -324,8 +349,9 @@ typedef struct {
                             cycle started from the iterate x_c with residual r_c
                             computes the correction d ~ x_exact - x_c, so
                             gamma ~ (||d_U|| / ||x_U||) / r_c.  It then stops only
-                            when r <= min(tol, u_tol / gamma), reported as
-                            tol_internal.  A solve whose first cycle already meets
+                            when r <= min(tol, u_tol / (2 gamma)), reported as
+                            tol_internal (half the bound absorbs the error of the
+                            estimate itself).  A solve whose first cycle already meets
                             `tol` runs one short verification cycle (residual reduced
                             tenfold) to measure gamma.  RMB_EINVAL for resistance
                             solves. */
@@ -341,7 +367,7 @@ typedef struct {
     double rel_residual;   /* final ||b - A x|| / ||b|| with the FP64 operator */
     double seconds;        /* host wall time from admission to completion */
     double tol_internal;   /* residual target the solve ended with: tol, or
-                              min(tol, u_tol / gamma) under velocity-error control */
+                              min(tol, u_tol / (2 gamma)) under velocity-error control */
     double u_err_est;      /* estimated ||U - U_exact|| / ||U_exact|| of the result
                               (gamma * rel_residual), or -1 when u_tol is off or no
                               refinement cycle has measured gamma */

@@ -33,7 +33,8 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_server_step", "rmb_server_poll", "rmb_server_destroy", "rmb_ctx_set_timing",
            "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan",
            "rmb_flow_field", "rmb_precond_factor_shapes", "rmb_precond_set_orientations",
-           "rmb_solve_resistance", "rmb_mobility_matvec_noalloc", "rmb_noalloc_workspace_bytes"]
+           "rmb_solve_resistance", "rmb_mobility_matvec_noalloc", "rmb_noalloc_workspace_bytes",
+           "rmb_tile_shape_count", "rmb_tile_shape_info", "rmb_ctx_set_tile_shape"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -122,10 +123,27 @@ def library(path: str = LIB_PATH):
         L.rmb_ctx_set_timing.argtypes = [vp, i32]
         L.rmb_ctx_kernel_time.argtypes = [vp, i32, ctypes.POINTER(dbl), ctypes.POINTER(i64)]
         L.rmb_ctx_tuned_panel.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.rmb_tile_shape_count.argtypes = []
+        L.rmb_tile_shape_count.restype = i32
+        L.rmb_tile_shape_info.argtypes = [i32, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.rmb_ctx_set_tile_shape.argtypes = [vp, i32, i32]
         L.rmb_ctx_tune_log.argtypes = [vp, i32, ctypes.POINTER(rmb_tune_record), ctypes.POINTER(i32)]
         L.rmb_pair_plan.argtypes = [i64, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         _LIB = L
     return _LIB
+
+
+def tile_shapes() -> list:
+    """Every tile shape of the large-body factorisation: dicts with panel,
+    row_tiles and chunk, indexed by shape number."""
+    L = library()
+    out = []
+    for k in range(L.rmb_tile_shape_count()):
+        p, g, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        if L.rmb_tile_shape_info(k, ctypes.byref(p), ctypes.byref(g), ctypes.byref(c)) != RMB_OK:
+            raise RmbError(RMB_EINVAL, f"rmb_tile_shape_info({k}) failed")
+        out.append({"panel": p.value, "row_tiles": g.value, "chunk": c.value})
+    return out
 
 
 def pair_plan(nb: int):
@@ -201,6 +219,11 @@ class Context:
         w = ctypes.c_int32()
         self.check(self.lib.rmb_ctx_tuned_panel(self.h, int(padded_dim), ctypes.byref(w)))
         return w.value
+
+    def set_tile_shape(self, padded_dim: int, shape: int):
+        """Force a tile shape of the large-body factorisation for one padded
+        size on this context (-1: back to the autotuner)."""
+        self.check(self.lib.rmb_ctx_set_tile_shape(self.h, int(padded_dim), int(shape)))
 
     def tune_log(self) -> list:
         """Every timing the large-body autotuner took on this context:

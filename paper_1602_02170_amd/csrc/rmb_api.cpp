@@ -260,6 +260,7 @@ rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
     c->device = device;
     c->arena = new Arena(hbm_budget_bytes ? hbm_budget_bytes : (size_t(16) << 30));
     c->noalloc_work = noalloc_work_address(device);
+    load_tune_cache(c);
     *out = c;
     return RMB_OK;
 }

@@ -2,8 +2,9 @@
 // too large for LDS (Sec. 2.2.2: the per-body factorisation of M_pp behind
 // eq:saddle_M_precon), e.g. 162-blob shells (486 x 486).
 //
-// Storage per body (doubles), Mp = 3n rounded up to 32; rows and columns
-// past 3n hold the identity, so the padded factor is blockdiag(L, I):
+// Storage per body (doubles), Mp = 3n + 6 rounded up to 64; rows and
+// columns past 3n hold the identity, so the padded factor is blockdiag(L, I)
+// (rows 3n .. 3n+5 carry K_p^T while the block is factorised):
 //   L    : Mp x Mp, column-major, lower triangle (the upper triangle is zero)
 //   Y    : Mp x 6, row-major (L^-1 K_p, zero in the padding)
 //   Dinv : the inverses of L's NB x NB diagonal blocks, block j/NB at
@@ -109,182 +110,429 @@ __global__ __launch_bounds__(256) void assemble_large_kernel(const BigBody *__re
         const int64_t col = m + e / Mp, row = e % Mp;
         A[col * Mp + row] = row == col ? 1.0 : 0.0;
     }
-    // rows m..Mp-1 of columns 0..m-1: zero
+    // rows m..Mp-1 of columns 0..m-1: the border K_p^T (rows m..m+5), then zero
     const int64_t padr = (int64_t)(Mp - m) * m;
+    const gmem<const double> q = as_global(it.w.q);
     for (int64_t e = (int64_t)g * 256 + tid; e < padr; e += stride) {
         const int64_t col = e / (Mp - m), row = m + e % (Mp - m);
-        A[col * Mp + row] = 0.0;
+        double v = 0.0;
+        if (row < m + 6) {
+            const int i = (int)(col / 3), c = (int)(col % 3);
+            const gmem<const double> ri = as_global(it.w.pos + 3 * (it.w.blob0 + i));
+            const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
+            v = K_entry(d, c, (int)(row - m));
+        }
+        A[col * Mp + row] = v;
     }
 }
 
 // ---------------------------------------------------------------------------
-// left-looking blocked Cholesky with MFMA panel updates
+// left-looking blocked Cholesky, panels of 64 columns, FP64 matrix cores
 // ---------------------------------------------------------------------------
 
-// NB: panel width; G: 16-row tiles per wave per pass; U: steps of 4 columns
-// per prefetched chunk (the autotuner picks among a few shapes).
-template <int NB, int G, int U>
-__global__ __launch_bounds__(256) void chol_large_kernel(const BigBody *__restrict__ items) {
-    constexpr int CT = NB / 16;  // column tiles per panel
-    __shared__ double D[NB * NB];   // diagonal block being factorised (column-major)
-    __shared__ double Lc[NB * NB];  // its Cholesky factor
-    __shared__ double W[NB * NB];   // the factor's inverse
-    __shared__ double Li[NB];       // reciprocals of the factor's diagonal
-    __shared__ int bad;
+constexpr int kPanel = 64;
+constexpr int kLd = kPanel + 2;  // LDS leading dimension of the diagonal block: rows in other banks
+
+// Operand loads of the factorisation go through a buffer resource: the
+// per-lane part of an address is a 32-bit offset fixed for a whole pass,
+// the part that moves with the column is a wave-uniform (scalar) offset, so
+// a prefetched chunk costs no 64-bit address registers.
+typedef __amdgpu_buffer_rsrc_t brsrc;
+__device__ __forceinline__ brsrc factor_rsrc(const BigBody &it) {
+    return __builtin_amdgcn_make_buffer_rsrc(it.w.factor, (short)0, (int)((int64_t)it.Mp * it.Mp * 8), 0x00020000);
+}
+__device__ __forceinline__ double bload(brsrc r, uint32_t voff, uint32_t soff) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_t soff) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(__attribute__((ext_vector_type(2))) unsigned int, v), r,
+                                          voff, soff, 0);
+}
+
+// LDS of one workgroup: the staged B chunks of the panel update, or the
+// diagonal block and its inverse (never both at once).
+struct CholLds {
+    union {
+        double B[2][32 * kPanel];  // chunk of L[j:j+64, k0:k0+KC], column-major (KC <= 32)
+        struct {
+            double D[kPanel * kLd];  // diagonal block, column-major (leading dimension kLd)
+            double W[kPanel * kLd];  // its inverse, likewise
+            double T[4][16 * 16];    // per wave: a 16 x 16 product, column-major
+        } d;
+        double Yt[6 * 768];  // epilogue: the bordered rows (Y^T), row k at k * m
+    };
+    double rdiag[kPanel];  // 1 / L[c][c] of the block (1 in the padding)
+    double S[36];
+    int bad;
+};
+
+// 1 / sqrt(x) for x > 0: the hardware estimate and one third-order
+// correction step, y (1 + e/2 + 3e^2/8) with e = 1 - x y^2.
+__device__ __forceinline__ double rsqrt64(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    const double e = fma(-x * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+// Lanes of one wave exchange a double through two readlanes (the lane index
+// is a constant, so the value lands in scalar registers).
+__device__ __forceinline__ double lane_value(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)(unsigned)lo) | ((long long)hi << 32));
+}
+
+// LDS ordering inside one wave: the wave's earlier LDS writes are complete
+// before its later reads (other lanes' values), and the compiler keeps the
+// order.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// 16 x 16 tiles in LDS, column-major with leading dimension ld (element (i, j)
+// at P[j * ld + i]), on the matrix cores.  C layout: lane holds rows
+// l4 + 4 r, column l16.
+__device__ __forceinline__ dbl4 tile_load(const double *P, int ld, int l16, int l4) {
+    return dbl4{P[l16 * ld + l4], P[l16 * ld + l4 + 4], P[l16 * ld + l4 + 8], P[l16 * ld + l4 + 12]};
+}
+__device__ __forceinline__ void tile_store(double *P, int ld, int l16, int l4, dbl4 v) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) P[l16 * ld + l4 + 4 * r] = v[r];
+}
+// acc += sA * A B with A (16 x 16) and B (16 x 16) column-major tiles; with
+// TB, B is given as its transpose (B[k][n] = Bt[n][k]).
+template <bool TB>
+__device__ __forceinline__ dbl4 tile_mma(dbl4 acc, const double *A, int lda, const double *B, int ldb, double sA,
+                                         int l16, int l4) {
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+        const double a = sA * A[(k0 + l4) * lda + l16];
+        const double b = TB ? B[(k0 + l4) * ldb + l16] : B[l16 * ldb + k0 + l4];
+        acc = mfma16x16x4(a, b, acc);
+    }
+    return acc;
+}
+
+// Panel update of rows [j, Mp), columns [j, j + 64):
+//   A[r, j:j+64] -= L[r, 0:j] L[j:j+64, 0:j]^T
+// Each wave owns G 16-row tiles per pass (tiles wave, wave + 4, ...); the
+// B operand L[j:j+64, k0:k0+KC] is staged in LDS per chunk of KC columns
+// (double buffered, one barrier per chunk), the A operand is read straight
+// from the factor, a chunk ahead.  The accumulators start at -A and take
+// +L L^T, so no operand needs a sign change; the result is negated once.
+template <int G, int KC>
+__device__ __forceinline__ void panel_update(const gmem<double> L, brsrc rs, int Mp, int j, CholLds &sh) {
+    constexpr int KS = KC / 4;  // MFMA steps per chunk
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    const int RT = (Mp - j) / 16;
+    const int nch = j / KC;
+    // passes go bottom up, so that the last one holds the diagonal block's
+    // rows (its first tile of every wave), which go to LDS, not to memory
+    const int npass = (RT + 4 * G - 1) / (4 * G);
+    for (int pass = npass - 1; pass >= 0; --pass) {
+        dbl4 acc[G][4];
+        int row0[G];
+        bool live[G];
+        const uint32_t colb = (uint32_t)Mp * 8;  // bytes per column of L
+        uint32_t vod[G];  // the accumulator's element (row0 + l4, j + l16) of each tile
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int t = pass * 4 * G + g * 4 + wave;
+            live[g] = t < RT;
+            row0[g] = j + 16 * (t < RT ? t : RT - 1);  // clamped: loads stay unconditional
+            vod[g] = ((uint32_t)(j + l16) * Mp + row0[g] + l4) * 8;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) acc[g][c][r] = -bload(rs, vod[g], (16 * c) * colb + 32 * r);
+        }
+        // B staging: thread tid loads KC * 64 / 256 values of the chunk
+        constexpr int BV = KC * kPanel / 256;
+        double bst[BV];
+        double a0[KS][G], a1[KS][G];
+        uint32_t voa[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) voa[g] = ((uint32_t)l4 * Mp + row0[g] + l16) * 8;
+        const uint32_t vob = ((uint32_t)(tid / kPanel) * Mp + j + tid % kPanel) * 8;  // + v * (256 / 64) columns
+        auto load_b = [&](int ch) {
+#pragma unroll
+            for (int v = 0; v < BV; ++v) bst[v] = bload(rs, vob, (uint32_t)(ch * KC + v * (256 / kPanel)) * colb);
+        };
+        auto put_b = [&](int buf) {
+#pragma unroll
+            for (int v = 0; v < BV; ++v) sh.B[buf][tid + 256 * v] = bst[v];
+        };
+        auto load_a = [&](int ch, double (&a)[KS][G]) {
+#pragma unroll
+            for (int u = 0; u < KS; ++u)
+#pragma unroll
+                for (int g = 0; g < G; ++g) a[u][g] = bload(rs, voa[g], (uint32_t)(ch * KC + 4 * u) * colb);
+        };
+        auto mma = [&](int buf, const double (&a)[KS][G]) {
+#pragma unroll
+            for (int u = 0; u < KS; ++u) {
+                double b[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) b[c] = sh.B[buf][(4 * u + l4) * kPanel + 16 * c + l16];
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    if (!live[g]) continue;  // wave-uniform: a clamped tile does no arithmetic
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[g][c] = mfma16x16x4(a[u][g], b[c], acc[g][c]);
+                }
+            }
+        };
+        if (nch > 0) {
+            load_b(0);
+            load_a(0, a0);
+            __syncthreads();  // the previous pass (or phase) is done with the LDS
+            put_b(0);
+            for (int ch = 0; ch < nch; ch += 2) {
+                // chunk ch in buffer 0 / registers a0; chunk ch + 1 loaded meanwhile
+                const bool more1 = ch + 1 < nch;
+                if (more1) load_b(ch + 1), load_a(ch + 1, a1);
+                __syncthreads();
+                mma(0, a0);
+                if (!more1) break;
+                put_b(1);
+                const bool more2 = ch + 2 < nch;
+                if (more2) load_b(ch + 2), load_a(ch + 2, a0);
+                __syncthreads();
+                mma(1, a1);
+                if (more2) put_b(0);
+            }
+        }
+        if (pass == 0) {
+            __syncthreads();  // the last chunk's operands are no longer read: D overlays them
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sh.d.D[(16 * c + l16) * kLd + 16 * wave + l4 + 4 * r] = -acc[0][c][r];
+        }
+#pragma unroll
+        for (int g = pass == 0 ? 1 : 0; g < G; ++g) {
+            if (!live[g]) continue;
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) bstore(-acc[g][c][r], rs, vod[g], (16 * c) * colb + 32 * r);
+        }
+    }
+}
+
+// One workgroup (4 waves) per body, all bodies in one launch.  The factored
+// matrix is [M_pp; K_p^T] bordered below by the 6 rows of K_p^T (rows m ..
+// m+5 of the padded block, written by the assembly): its Cholesky rows there
+// are K_p^T L^-T = Y^T, so the factorisation yields Y = L^-1 K_p as well;
+// only the first m columns are factorised (the others are padding, kept at
+// the identity).  Per panel of 64 columns:
+//   1. panel update on matrix cores (panel_update);
+//   2. the 64 x 64 diagonal block in LDS: Cholesky with one barrier per
+//      column (column scaling deferred to the end), then its inverse W by
+//      columns, four lanes per column;
+//   3. the rows below: X = A W^T on matrix cores;
+// and at the end Y^T is moved from the bordered rows into the Y storage,
+// S = Y^T Y and its Cholesky factor are formed, and the bordered rows are
+// cleared so that the stored L is blockdiag(L, I).
+template <int G, int KC>
+__global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__restrict__ items) {
+    __shared__ CholLds sh;
     const BigBody it = items[blockIdx.x];
-    const int Mp = it.Mp;
+    const int Mp = it.Mp, m = 3 * it.w.n_blobs;
     const gmem<double> L = as_global(it.w.factor);
     const gmem<double> Dinv = as_global(big_Dinv(it));
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int l16 = lane & 15, l4 = lane >> 4;
-    if (tid == 0) bad = 0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    double *D = sh.d.D, *W = sh.d.W;
+    const brsrc rs = factor_rsrc(it);
+    if (tid == 0) sh.bad = 0;
 
-    for (int j = 0; j < Mp; j += NB) {
-        // 1. panel update: rows [j, Mp), columns [j, j+NB).  A wave's row
-        //    tiles past the panel are clamped to its last tile, so every load
-        //    is unconditional (no branch between a prefetch and its use);
-        //    only their stores are skipped.
-        const int RT = (Mp - j) / 16;  // row tiles in the panel
-        for (int pass = 0; pass * 4 * G < RT; ++pass) {
-            dbl4 acc[G][CT];
-            int row0[G];
-            bool live[G];
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                const int t = pass * 4 * G + g * 4 + wave;
-                live[g] = t < RT;
-                row0[g] = j + 16 * (t < RT ? t : RT - 1);
-#pragma unroll
-                for (int c = 0; c < CT; ++c) {
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        acc[g][c][r] = L[(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r];
-                }
-            }
-            if (j > 0) {
-                // j is a multiple of 16 (and of 4 * U): nch whole chunks
-                const int nch = j / (4 * U);
-                double a0[U][G], b0[U][CT], a1[U][G], b1[U][CT];
-                auto load = [&](int ch, double (&a)[U][G], double (&b)[U][CT]) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int kc = (4 * U * ch + 4 * u + l4) * Mp;  // Mp^2 < 2^31
-#pragma unroll
-                        for (int c = 0; c < CT; ++c) b[u][c] = L[kc + j + 16 * c + l16];
-#pragma unroll
-                        for (int g = 0; g < G; ++g) a[u][g] = -L[kc + row0[g] + l16];
-                    }
-                };
-                auto mma = [&](const double (&a)[U][G], const double (&b)[U][CT]) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u)
-#pragma unroll
-                        for (int g = 0; g < G; ++g)
-#pragma unroll
-                            for (int c = 0; c < CT; ++c) acc[g][c] = mfma16x16x4(a[u][g], b[u][c], acc[g][c]);
-                };
-                load(0, a0, b0);
-                for (int ch = 0; ch < nch; ch += 2) {
-                    load(min(ch + 1, nch - 1), a1, b1);
-                    mma(a0, b0);
-                    if (ch + 1 >= nch) break;
-                    load(min(ch + 2, nch - 1), a0, b0);
-                    mma(a1, b1);
-                }
-            }
-#pragma unroll
-            for (int g = 0; g < G; ++g) {
-                if (!live[g]) continue;
-#pragma unroll
-                for (int c = 0; c < CT; ++c)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        L[(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] = acc[g][c][r];
-            }
-        }
+    for (int j = 0; j < Mp; j += kPanel) {
+        if (j > 0) panel_update<G, KC>(L, rs, Mp, j, sh);
         __syncthreads();
-        // 2. factorise the diagonal block in LDS: step c reads column c of D
-        //    and writes only columns > c of D and column c of Lc
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int r = e % NB, c = e / NB;
-            D[e] = r >= c ? L[(int64_t)(j + c) * Mp + j + r] : 0.0;
-        }
-        __syncthreads();
-        for (int c = 0; c < NB; ++c) {
-            const double dcc = D[c * NB + c];
-            if (tid == 0 && !(dcc > 0.0)) bad = 1;
-            const double s = sqrt(dcc > 0.0 ? dcc : 1.0), inv = 1.0 / s, inv2 = inv * inv;
-            if (tid < NB) Lc[c * NB + tid] = tid > c ? D[c * NB + tid] * inv : (tid == c ? s : 0.0);
-            if (tid == 0) Li[c] = inv;
-            // lane (r, first column): rows by lane % NB, columns by lane / NB
-            // in rounds of 256 / NB (no division by a run-time count)
-            {
-                const int r = tid % NB;
-                for (int cc = c + 1 + tid / NB; cc < NB; cc += 256 / NB)
-                    if (r >= cc) D[cc * NB + r] -= D[c * NB + r] * D[c * NB + cc] * inv2;
+        // 2. the 64 x 64 diagonal block in LDS, factorised in four column
+        //    blocks of 16: wave b factorises block b alone (lane = row, the
+        //    block's 16 columns in registers, values shared by readlane, no
+        //    barrier), then the waves to its right take its rank-16 update
+        //    on the matrix cores.  Columns [0, nc) are the matrix's, the
+        //    rest padding (the identity).
+        const int nc = max(0, min(kPanel, m - j));
+        if (j == 0) {  // later panels: the update left the block in LDS
+            for (int e = tid; e < kPanel * kPanel; e += 256) {
+                const int r = e % kPanel, c = e / kPanel;
+                D[c * kLd + r] = L[(j + c) * Mp + j + r];
             }
             __syncthreads();
         }
-        // 3. W = L11^-1, column k by thread k, built in place in LDS
-        if (tid < NB) {
-            const int k = tid;
-            for (int i = 0; i < k; ++i) W[k * NB + i] = 0.0;
-            W[k * NB + k] = Li[k];
-            for (int i = k + 1; i < NB; ++i) {
-                double v = 0.0;
-                for (int mm = k; mm < i; ++mm) v -= Lc[mm * NB + i] * W[k * NB + mm];
-                W[k * NB + i] = v * Li[i];
-            }
-        }
-        __syncthreads();
-        for (int e = tid; e < NB * NB; e += 256) {
-            const int r = e % NB, c = e / NB;
-            L[(int64_t)(j + c) * Mp + j + r] = Lc[e];
-            Dinv[(int64_t)j * NB + e] = W[e];
-        }
-        // 4. rows below the diagonal block: x L11^T = a, i.e. X = A W^T, on
-        //    matrix cores (A operand from the panel, B operand W^T from LDS)
-        {
-            const int RT4 = (Mp - j - NB) / 16;
-            for (int pass = 0; pass * 4 * G < RT4; ++pass) {
-                dbl4 acc[G][CT];
-                int row0[G];
+        for (int b = 0; b < 4; ++b) {
+            if (wave == b) {
+                const int r = lane;
+                double d[16];
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    const int t = pass * 4 * G + g * 4 + wave;
-                    row0[g] = t < RT4 ? j + NB + 16 * t : -1;
+                for (int c = 0; c < 16; ++c) d[c] = D[(16 * b + c) * kLd + r];
 #pragma unroll
-                    for (int c = 0; c < CT; ++c) acc[g][c] = dbl4{0.0, 0.0, 0.0, 0.0};
-                }
+                for (int c = 0; c < 16; ++c) {
+                    const int C = 16 * b + c;
+                    if (C < nc) {  // uniform
+                        const double dcc = lane_value(d[c], C);
+                        const double inv = rsqrt64(dcc > 0.0 ? dcc : 1.0);
+                        if (lane == 0) {
+                            sh.rdiag[C] = inv;
+                            if (!(dcc > 0.0)) sh.bad = 1;
+                        }
+                        d[c] = r >= C ? d[c] * inv : 0.0;
 #pragma unroll
-                for (int k0 = 0; k0 < NB; k0 += 4) {
-                    double b[CT];
-#pragma unroll
-                    for (int c = 0; c < CT; ++c) b[c] = W[(k0 + l4) * NB + 16 * c + l16];
-#pragma unroll
-                    for (int g = 0; g < G; ++g) {
-                        if (row0[g] < 0) continue;  // wave-uniform
-                        const double a = L[(j + k0 + l4) * Mp + row0[g] + l16];
-#pragma unroll
-                        for (int c = 0; c < CT; ++c) acc[g][c] = mfma16x16x4(a, b[c], acc[g][c]);
+                        for (int k = c + 1; k < 16; ++k) {
+                            const double lk = lane_value(d[c], 16 * b + k);
+                            if (r >= 16 * b + k) d[k] -= d[c] * lk;
+                        }
+                    } else {
+                        d[c] = r == C ? 1.0 : 0.0;
+                        if (lane == 0) sh.rdiag[C] = 1.0;
                     }
                 }
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    if (row0[g] < 0) continue;
+                for (int c = 0; c < 16; ++c) D[(16 * b + c) * kLd + r] = d[c];
+            }
+            __syncthreads();
+            if (wave > b) {
+                // D[16t.., 16w..] -= L[16t.., 16b..] L[16w.., 16b..]^T for row tiles t >= w
+                for (int t = wave; t < 4; ++t) {
+                    double *C = D + (16 * wave) * kLd + 16 * t;
+                    dbl4 acc = tile_load(C, kLd, l16, l4);
+                    acc = tile_mma<true>(acc, D + (16 * b) * kLd + 16 * t, kLd, D + (16 * b) * kLd + 16 * wave, kLd, -1.0,
+                                         l16, l4);
+                    tile_store(C, kLd, l16, l4, acc);
+                }
+            }
+            __syncthreads();
+        }
+        // the factor's block to global memory (the upper part as zeros,
+        // bordered rows included); in LDS the rows from m on (border or
+        // padding) and the upper part are cleared: the block to invert
+        for (int e = tid; e < kPanel * kPanel; e += 256) {
+            const int r = e % kPanel, c = e / kPanel;
+            double v = D[c * kLd + r];
+            if (r < c) v = 0.0;
+            L[(j + c) * Mp + j + r] = v;
+            if ((j + r >= m && c < nc) || r < c) D[c * kLd + r] = r == c ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        // W = D^-1 by blocks of 16: each wave inverts its diagonal block
+        // (lane k < 16 holds column k, forward substitution), then wave j
+        // forms its block column below, X_ij = -W_ii sum_{j <= k < i} L_ik X_kj
+        {
+            const int w16 = 16 * wave;
+            if (lane < 16) {
+                const int k = lane;
+                double x[16];
 #pragma unroll
-                    for (int c = 0; c < CT; ++c)
+                for (int i = 0; i < 16; ++i) {
+                    double v = i == k ? 1.0 : 0.0;
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) L[(j + 16 * c + l16) * Mp + row0[g] + l4 + 4 * r] = acc[g][c][r];
+                    for (int q = 0; q < i; ++q) v -= D[(w16 + q) * kLd + w16 + i] * x[q];
+                    x[i] = i >= k ? v * sh.rdiag[w16 + i] : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < 16; ++i) W[(w16 + k) * kLd + w16 + i] = x[i];
+            }
+            // blocks above the diagonal are zero
+            for (int e = lane; e < 16 * w16; e += 64) W[(w16 + e / w16) * kLd + e % w16] = 0.0;
+        }
+        __syncthreads();
+        {
+            const int jb = wave;  // block column
+            double *T = sh.d.T[wave];
+            for (int i = jb + 1; i < 4; ++i) {
+                dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+                for (int k = jb; k < i; ++k)
+                    acc = tile_mma<false>(acc, D + (16 * k) * kLd + 16 * i, kLd, W + (16 * jb) * kLd + 16 * k, kLd, 1.0,
+                                          l16, l4);
+                tile_store(T, 16, l16, l4, acc);
+                wave_lds_sync();
+                acc = tile_mma<false>(dbl4{0.0, 0.0, 0.0, 0.0}, W + (16 * i) * kLd + 16 * i, kLd, T, 16, -1.0, l16, l4);
+                tile_store(W + (16 * jb) * kLd + 16 * i, kLd, l16, l4, acc);
+                wave_lds_sync();
+            }
+        }
+        __syncthreads();
+        // stored inverses of the two 32 x 32 diagonal blocks (the substitutions' blocks)
+        for (int e = tid; e < 2 * 32 * 32; e += 256) {
+            const int b = e / 1024, o = e % 1024, r = o % 32, c = o / 32;
+            Dinv[(int64_t)(j + 32 * b) * 32 + o] = W[(32 * b + c) * kLd + 32 * b + r];
+        }
+        // 3. rows below: X = A W^T (A operand from the factor, B = W^T from
+        //    LDS); columns past m stay zero
+        {
+            const int RT4 = (Mp - j - kPanel) / 16;
+            for (int t0 = 0; t0 < RT4; t0 += 4) {
+                const int t = t0 + wave;
+                if (t >= RT4) break;  // wave-uniform
+                const int row0 = j + kPanel + 16 * t;
+                dbl4 acc[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+                double a[16];
+                const uint32_t vo = ((uint32_t)l4 * Mp + row0 + l16) * 8;
+#pragma unroll
+                for (int u = 0; u < 16; ++u) a[u] = bload(rs, vo, (uint32_t)(j + 4 * u) * Mp * 8);
+#pragma unroll
+                for (int u = 0; u < 16; ++u) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c)
+                        acc[c] = mfma16x16x4(a[u], W[(4 * u + l4) * kLd + 16 * c + l16], acc[c]);
+                }
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int col = 16 * c + l16;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        L[(j + col) * Mp + row0 + l4 + 4 * r] = col < nc ? acc[c][r] : 0.0;
                 }
             }
         }
-        // 5. zero the panel's columns above the diagonal block
-        for (int c = 0; c < NB; ++c)
-            for (int r = tid; r < j; r += 256) L[(int64_t)(j + c) * Mp + r] = 0.0;
         __syncthreads();
     }
-    if (tid == 0 && bad) atomicOr(it.w.flag, 4);
+
+    // Y^T from the bordered rows (then cleared), S = Y^T Y, its Cholesky factor
+    gmem<double> Y = as_global(big_Y(it));
+    for (int e = tid; e < 6 * m; e += 256) {
+        const int k = e / m, i = e % m;
+        const int64_t a = (int64_t)i * Mp + m + k;
+        sh.Yt[e] = L[a];
+        L[a] = 0.0;
+    }
+    __syncthreads();
+    for (int e = tid; e < 6 * Mp; e += 256) {
+        const int i = e / 6, k = e % 6;
+        Y[e] = i < m ? sh.Yt[k * m + i] : 0.0;
+    }
+    if (tid < 36) {
+        // S[a][b]: a wave's lanes each take one entry, sums in index order
+        const int a = tid / 6, b = tid % 6;
+        double acc = 0.0;
+        for (int i = 0; i < m; ++i) acc += sh.Yt[a * m + i] * sh.Yt[b * m + i];
+        sh.S[tid] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double *S = sh.S;
+        bool badS = false;
+        for (int jj = 0; jj < 6; ++jj) {
+            double dj = S[jj * 6 + jj];
+            for (int k = 0; k < jj; ++k) dj -= S[jj * 6 + k] * S[jj * 6 + k];
+            if (!(dj > 0.0)) badS = true, dj = 1.0;
+            const double ljj = sqrt(dj);
+            S[jj * 6 + jj] = ljj;
+            for (int i = jj + 1; i < 6; ++i) {
+                double v = S[i * 6 + jj];
+                for (int k = 0; k < jj; ++k) v -= S[i * 6 + k] * S[jj * 6 + k];
+                S[i * 6 + jj] = v / ljj;
+            }
+        }
+        if (badS) atomicOr(it.w.flag, 8);
+        if (sh.bad) atomicOr(it.w.flag, 4);
+    }
+    __syncthreads();
+    if (tid < 36) as_global(big_Sc(it))[tid] = (tid % 6) <= (tid / 6) ? sh.S[tid] : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -363,65 +611,6 @@ __device__ void backward_rl(const gmem<const double> L, const gmem<const double>
         }
         __syncthreads();
     }
-}
-
-// Y = L^-1 K_p, S = Y^T Y, Sc = chol(S); one workgroup per body.
-template <int NB>
-__global__ __launch_bounds__(256) void project_large_kernel(const BigBody *__restrict__ items) {
-    extern __shared__ double lds[];
-    __shared__ double Dj[NB * NB];
-    __shared__ double T[NB * 6];
-    __shared__ double S[36];
-    __shared__ int bad;
-    const BigBody it = items[blockIdx.x];
-    const int Mp = it.Mp, m = 3 * it.w.n_blobs, tid = threadIdx.x;
-    const gmem<const double> L = as_global(it.w.factor);
-    double *Y = lds;  // Mp x 6
-    if (tid == 0) bad = 0;
-    const gmem<const double> q = as_global(it.w.q);
-    for (int e = tid; e < 6 * Mp; e += 256) {
-        const int row = e / 6, k = e % 6;
-        double v = 0.0;
-        if (row < m) {
-            const int i = row / 3, c = row % 3;
-            const gmem<const double> ri = as_global(it.w.pos + 3 * (it.w.blob0 + i));
-            const double d[3] = {ri[0] - q[0], ri[1] - q[1], ri[2] - q[2]};
-            v = K_entry(d, c, k);
-        }
-        Y[e] = v;
-    }
-    __syncthreads();
-    forward_rl<NB, 6>(L, as_global((const double *)big_Dinv(it)), Mp, Y, Dj, T);
-    if (tid < 36) {
-        const int r = tid / 6, c = tid % 6;
-        double acc = 0.0;
-        for (int l = 0; l < Mp; ++l) acc += Y[l * 6 + r] * Y[l * 6 + c];
-        S[tid] = acc;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        for (int j = 0; j < 6; ++j) {
-            double dj = S[j * 6 + j];
-            for (int k = 0; k < j; ++k) dj -= S[j * 6 + k] * S[j * 6 + k];
-            if (!(dj > 0.0)) {
-                bad = 1;
-                dj = 1.0;
-            }
-            const double ljj = sqrt(dj);
-            S[j * 6 + j] = ljj;
-            for (int i = j + 1; i < 6; ++i) {
-                double v = S[i * 6 + j];
-                for (int k = 0; k < j; ++k) v -= S[i * 6 + k] * S[j * 6 + k];
-                S[i * 6 + j] = v / ljj;
-            }
-        }
-    }
-    __syncthreads();
-    double *Yg = big_Y(it);
-    for (int e = tid; e < 6 * Mp; e += 256) as_global(Yg)[e] = Y[e];
-    double *Sc = big_Sc(it);
-    if (tid < 36) as_global(Sc)[tid] = ((tid % 6) <= (tid / 6)) ? S[tid] : 0.0;
-    if (tid == 0 && bad) atomicOr(it.w.flag, 8);
 }
 
 // Apply P^-1 to up to 8 right-hand sides of one body per workgroup
@@ -567,27 +756,26 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
 
 // ---------------------------------------------------------------------------
 
-// Tile shapes the autotuner times: {panel width, row tiles per wave, steps
-// per prefetched chunk}.  Shapes with G * U <= 8 stay within 256 VGPRs
-// (two bodies per CU); the others trade occupancy for operand reuse.
+// Tile shapes the autotuner times: {16-row tiles per wave and pass, columns
+// of L staged per chunk}; the panel is 64 columns wide in every shape and
+// the stored diagonal-block inverses are 32 x 32.
 struct LargeShape {
-    int nb, g, u;
+    int g, kc;
 };
-static constexpr LargeShape kLargeShapes[] = {{16, 2, 4}, {32, 2, 4}, {32, 2, 8}, {32, 4, 2}, {32, 1, 8}, {16, 4, 4}};
+static constexpr LargeShape kLargeShapes[] = {{4, 16}, {2, 32}, {2, 16}, {4, 8}};
 constexpr int kLargeVariants = (int)(sizeof(kLargeShapes) / sizeof(kLargeShapes[0]));
 
 int large_variant_count() { return kLargeVariants; }
-int large_panel_width(int variant) { return kLargeShapes[variant].nb; }
 void large_variant_shape(int variant, int *nb, int *row_tiles, int *chunk) {
-    *nb = kLargeShapes[variant].nb;
+    *nb = kPanel;
     *row_tiles = kLargeShapes[variant].g;
-    *chunk = 4 * kLargeShapes[variant].u;
+    *chunk = kLargeShapes[variant].kc;
 }
 
 template <int V>
 static void launch_chol(const BigBody *items, int32_t n_items, hipStream_t s) {
     constexpr LargeShape sh = kLargeShapes[V];
-    hipLaunchKernelGGL((chol_large_kernel<sh.nb, sh.g, sh.u>), dim3(n_items), dim3(256), 0, s, items);
+    hipLaunchKernelGGL((chol_panel_kernel<sh.g, sh.kc>), dim3(n_items), dim3(256), 0, s, items);
 }
 
 hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int max_Mp, int variant, hipStream_t s) {
@@ -598,29 +786,18 @@ hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int
         case 0: launch_chol<0>(items, n_items, s); break;
         case 1: launch_chol<1>(items, n_items, s); break;
         case 2: launch_chol<2>(items, n_items, s); break;
-        case 3: launch_chol<3>(items, n_items, s); break;
-        case 4: launch_chol<4>(items, n_items, s); break;
-        default: launch_chol<5>(items, n_items, s); break;
+        default: launch_chol<3>(items, n_items, s); break;
     }
-    static_assert(kLargeVariants == 6, "launch switch covers every shape");
-    const size_t lds = (size_t)max_Mp * 6 * sizeof(double);
-    if (large_panel_width(variant) == 32)
-        hipLaunchKernelGGL(project_large_kernel<32>, dim3(n_items), dim3(256), lds, s, items);
-    else
-        hipLaunchKernelGGL(project_large_kernel<16>, dim3(n_items), dim3(256), lds, s, items);
+    static_assert(kLargeVariants == 4, "launch switch covers every shape");
     return hipGetLastError();
 }
 
 hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
-                                      int max_Mp, int panel, hipStream_t s) {
+                                      int max_Mp, hipStream_t s) {
     if (n_wg <= 0 || max_rhs <= 0) return hipSuccess;
     const size_t lds = (size_t)max_Mp * 8 * sizeof(double);
     dim3 g((unsigned)n_wg, (max_rhs + 7) / 8);
-    if (panel != 16 && panel != 32) return hipErrorInvalidValue;
-    if (panel == 32)
-        hipLaunchKernelGGL(apply_large_kernel<32>, g, dim3(256), lds, s, jobs, n_jobs);
-    else
-        hipLaunchKernelGGL(apply_large_kernel<16>, g, dim3(256), lds, s, jobs, n_jobs);
+    hipLaunchKernelGGL(apply_large_kernel<32>, g, dim3(256), lds, s, jobs, n_jobs);
     return hipGetLastError();
 }
 

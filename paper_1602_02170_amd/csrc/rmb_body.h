@@ -36,7 +36,9 @@ struct BigBody {
 };
 
 inline bool is_large_body(int64_t n_blobs) { return 3 * n_blobs > kSmallBodyMaxM; }
-inline int64_t padded_dim(int64_t n_blobs) { return (3 * n_blobs + 31) / 32 * 32; }
+// Large bodies: the block with 6 bordered rows (K_p^T), rounded up to the
+// 64-column panels of the factorisation.
+inline int64_t padded_dim(int64_t n_blobs) { return (3 * n_blobs + 6 + 63) / 64 * 64; }
 
 // Factor storage of one body (doubles).  Small bodies: L^-1 (lower
 // triangle, packed by columns: column c holds rows c..m-1 from
@@ -154,14 +156,13 @@ hipError_t launch_precond_apply_small(const PrecondApplyJob *jobs, int32_t n_job
 // Large bodies: assembly, MFMA left-looking Cholesky, projection; and the
 // apply (<= 8 rhs per workgroup).  `variant` selects one of
 // large_variant_count() tile shapes (panel width, row tiles per wave,
-// prefetched columns); the apply takes only the panel width.
+// staged columns); every shape stores the same factor layout, so the apply
+// does not depend on the shape.
 int large_variant_count();
-int large_panel_width(int variant);
 void large_variant_shape(int variant, int *panel, int *row_tiles, int *chunk);
 hipError_t launch_precond_build_large(const BigBody *items, int32_t n_items, int max_Mp, int variant, hipStream_t s);
-// `panel`: the panel width (16 or 32) the bodies' factors were built with.
 hipError_t launch_precond_apply_large(const PrecondApplyJob *jobs, int32_t n_jobs, int64_t n_wg, int32_t max_rhs,
-                                      int max_Mp, int panel, hipStream_t s);
+                                      int max_Mp, hipStream_t s);
 // Resistance problem (eq:resistance_problem): b_i = u_p + omega_p x (r_i - q_p)
 // + slip_i for blob i of body p (U device [N][6], slip [nb][3] or NULL).
 hipError_t launch_build_rhs_resist(const double *U, const double *slip, const double *pos, const double *q,

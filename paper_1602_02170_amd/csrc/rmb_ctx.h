@@ -32,8 +32,11 @@ struct rmb_ctx_s {
     std::vector<hipEvent_t> event_pool;
     double kernel_ms[RMB_KERNEL_COUNT] = {0, 0, 0, 0};
     int64_t kernel_launches[RMB_KERNEL_COUNT] = {0, 0, 0, 0};
-    // autotuned tile-shape variant of the large-body factorisation, by padded size
+    // tile-shape variant of the large-body factorisation, by padded size:
+    // chosen by the autotuner (or read from the persisted tuning file when
+    // the context was created), and shapes forced by the caller
     std::map<int, int> tuned_panel;
+    std::map<int, int> forced_shape;
     struct TuneRecord {
         int Mp, variant;
         float ms;
@@ -90,6 +93,8 @@ rmb_status pair_launch(rmb_ctx ctx, int precision, bool wall, const PairJob *job
 // Same for the symmetric pair kernel (block size B).
 rmb_status sym_launch(rmb_ctx ctx, int precision, bool wall, int B, const SymJob *jobs, int32_t n_jobs,
                       int64_t n_tiles, hipStream_t s);
+// Reads the persisted autotuner choices into the context.
+void load_tune_cache(rmb_ctx ctx);
 // Accumulates the elapsed time of completed timing events.
 void resolve_timing(rmb_ctx ctx, bool wait);
 

@@ -13,6 +13,8 @@
 // applies Givens rotations, tests convergence and chooses each system's
 // next step.  A system's arithmetic never depends on which other systems
 // share a tick: tilings and reduction orders are functions of its own sizes.
+#include <sys/stat.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -121,24 +123,86 @@ static rmb_status check_body_sizes(rmb_ctx ctx, const int64_t *off, int64_t N) {
     for (int64_t p = 0; p < N; ++p)
         if (padded_dim(off[p + 1] - off[p]) > kLargeBodyMaxMp)
             return fail(ctx, RMB_EINVAL, "body %lld has %lld blobs; at most %d blobs per body are supported",
-                        (long long)p, (long long)(off[p + 1] - off[p]), kLargeBodyMaxMp / 3);
+                        (long long)p, (long long)(off[p + 1] - off[p]), (kLargeBodyMaxMp - 6) / 3);
     return RMB_OK;
 }
 
 // Batches smaller than this are not timed (too few workgroups to show what
-// a full batch would do); they use the tuned shape if there is one, else
-// the first.
+// a full batch would do); they always use the default shape, so that their
+// factors do not depend on what the context ran before.
 constexpr int32_t kTuneMinBodies = 64;
+constexpr int kDefaultShape = 0;
 
-// Tile shape of the large-body factorisation for padded size Mp, chosen by
-// timing every candidate shape on the first batch of that size with at
-// least kTuneMinBodies bodies (cached per context; the timings are kept in
-// the context's tune log).
+// Persisted autotuner choices: one line "arch tag Mp panel row_tiles chunk"
+// per padded size, in the file named by RMB_TUNE_CACHE (empty: none), else
+// $XDG_CACHE_HOME/rmb/tune.txt or $HOME/.cache/rmb/tune.txt.  Lines of
+// another architecture or kernel generation (tag) are ignored, and so are
+// shapes the library no longer has.
+static const char *kTuneArch = "gfx950";
+static const char *kTuneTag = "chol-panel64-bordered-1";
+
+static std::string tune_cache_path() {
+    if (const char *e = getenv("RMB_TUNE_CACHE")) return e;
+    std::string base;
+    if (const char *x = getenv("XDG_CACHE_HOME"); x && *x) base = x;
+    else if (const char *h = getenv("HOME"); h && *h) base = std::string(h) + "/.cache";
+    else return "";
+    return base + "/rmb/tune.txt";
+}
+
+static int shape_index(int panel, int row_tiles, int chunk) {
+    for (int v = 0; v < large_variant_count(); ++v) {
+        int p, g, c;
+        large_variant_shape(v, &p, &g, &c);
+        if (p == panel && g == row_tiles && c == chunk) return v;
+    }
+    return -1;
+}
+
+void load_tune_cache(rmb_ctx ctx) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) return;
+    char arch[64], tag[64];
+    int Mp, p, g, c;
+    while (fscanf(f, "%63s %63s %d %d %d %d", arch, tag, &Mp, &p, &g, &c) == 6) {
+        const int v = shape_index(p, g, c);
+        if (!strcmp(arch, kTuneArch) && !strcmp(tag, kTuneTag) && v >= 0) ctx->tuned_panel[Mp] = v;  // last wins
+    }
+    fclose(f);
+}
+
+static void save_tune_choice(int Mp, int v) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        // create the directory chain (failures only mean nothing is persisted)
+        for (size_t i = 1; i <= slash; ++i)
+            if (path[i] == '/' || i == slash) (void)mkdir(path.substr(0, i == slash ? slash : i).c_str(), 0755);
+    }
+    FILE *f = fopen(path.c_str(), "a");
+    if (!f) return;
+    int p, g, c;
+    large_variant_shape(v, &p, &g, &c);
+    fprintf(f, "%s %s %d %d %d %d\n", kTuneArch, kTuneTag, Mp, p, g, c);
+    fclose(f);
+}
+
+// Tile shape of the large-body factorisation for padded size Mp: the shape
+// the caller forced; else the default for small batches; else the tuned
+// shape (this context's, or the persisted one), timing every candidate on
+// the first batch of that size with at least kTuneMinBodies bodies (the
+// timings are kept in the context's tune log and the choice is persisted).
 static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, int max_Mp, hipStream_t s,
                               int *variant_out) {
+    auto fo = ctx->forced_shape.find(max_Mp);
     auto it = ctx->tuned_panel.find(max_Mp);
-    if (it != ctx->tuned_panel.end() || n < kTuneMinBodies) {
-        const int v = it != ctx->tuned_panel.end() ? it->second : 0;
+    if (fo != ctx->forced_shape.end() || n < kTuneMinBodies || it != ctx->tuned_panel.end()) {
+        const int v = fo != ctx->forced_shape.end() ? fo->second
+                      : n < kTuneMinBodies          ? kDefaultShape
+                                                    : it->second;
         *variant_out = v;
         RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, v, s));
         return RMB_OK;
@@ -162,6 +226,7 @@ static rmb_status build_large(rmb_ctx ctx, const BigBody *items_d, int32_t n, in
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->tuned_panel[max_Mp] = best;
+    save_tune_choice(max_Mp, best);
     if (best != nv - 1) RMB_HIP(ctx, launch_precond_build_large(items_d, n, max_Mp, best, s));
     *variant_out = best;
     return RMB_OK;
@@ -505,6 +570,11 @@ struct Engine {
     static constexpr size_t kStageFixed = 32768;  // alignment of the shared tables
     size_t stage_reserved = kStageFixed;
 
+    // The velocity-error estimate gamma * rel is itself only accurate to a
+    // few per cent (the correction that measures gamma was computed to the
+    // inner tolerance), so solves aim at half the bound.
+    static constexpr double kUtolSafety = 0.5;
+
     // Residual target of the next cycle.  Under velocity-error control the
     // solve's tolerance is min(tol, u_tol / gamma) once a refinement cycle
     // has measured gamma; a solve that meets `tol` before any such cycle runs
@@ -514,7 +584,7 @@ struct Engine {
         J->cycles++;
         J->rel_start = beta / J->bnorm;
         J->cycle_fp32 = J->prec == RMB_PREC_FP32_PAIRS;
-        J->tol_eff = J->u_tol > 0 && J->gamma > 0 ? std::min(J->tol, J->u_tol / J->gamma) : J->tol;
+        J->tol_eff = J->u_tol > 0 && J->gamma > 0 ? std::min(J->tol, kUtolSafety * J->u_tol / J->gamma) : J->tol;
         double t = J->tol_eff * J->bnorm;
         if (J->u_tol > 0 && !(J->gamma > 0) && beta <= J->tol * J->bnorm) t = 0.1 * beta;
         J->target = J->cycle_fp32 ? std::max(J->inner_tol * beta, 0.5 * t) : t;
@@ -636,9 +706,9 @@ struct Engine {
         int64_t wg_comb = 0;
         for (Job *J : finish) o_coef.push_back(st.put(J->y.data(), J->y.size() * 8));
         // precond apply: finish (z -> w) then iter (V_k -> z)
-        std::vector<PrecondApplyJob> app, appL[2];  // large bodies: [panel width 16, 32]
-        int64_t wg_app = 0, wg_appL[2] = {0, 0};
-        int app_max_m = 0, appL_max_Mp[2] = {0, 0};
+        std::vector<PrecondApplyJob> app, appL;  // small bodies, large bodies
+        int64_t wg_app = 0, wg_appL = 0;
+        int app_max_m = 0, appL_max_Mp = 0;
         auto add_app = [&](Job *J, const double *in, double *out) {
             PrecondApplyJob a{};
             a.in = in;
@@ -656,13 +726,12 @@ struct Engine {
                 app_max_m = std::max(app_max_m, J->max_m);
             }
             if (J->n_large) {
-                const int v = large_panel_width(J->variant) == 32 ? 1 : 0;  // apply tables by panel width
                 a.items = (const BodyWork *)J->bigs_d;
-                a.wg_begin = wg_appL[v];
+                a.wg_begin = wg_appL;
                 a.n_items = J->n_large;
-                appL[v].push_back(a);
-                wg_appL[v] += J->n_large;
-                appL_max_Mp[v] = std::max(appL_max_Mp[v], J->max_Mp);
+                appL.push_back(a);
+                wg_appL += J->n_large;
+                appL_max_Mp = std::max(appL_max_Mp, J->max_Mp);
             }
         };
         for (Job *J : finish) add_app(J, J->z, J->w);
@@ -822,9 +891,7 @@ struct Engine {
         }
 
         size_t o_app = app.empty() ? 0 : st.put(app.data(), app.size() * sizeof(PrecondApplyJob));
-        size_t o_appL[2];
-        for (int v = 0; v < 2; ++v)
-            o_appL[v] = appL[v].empty() ? 0 : st.put(appL[v].data(), appL[v].size() * sizeof(PrecondApplyJob));
+        size_t o_appL = appL.empty() ? 0 : st.put(appL.data(), appL.size() * sizeof(PrecondApplyJob));
         size_t o_pk = pk.empty() ? 0 : st.put(pk.data(), pk.size() * sizeof(PackJob));
         size_t o_pair[2][2];
         for (int a = 0; a < 2; ++a)
@@ -891,10 +958,9 @@ struct Engine {
         if (!app.empty())
             RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)D(o_app), (int32_t)app.size(), wg_app, 1,
                                                     app_max_m, s));
-        for (int v = 0; v < 2; ++v)
-            if (!appL[v].empty())
-                RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)D(o_appL[v]), (int32_t)appL[v].size(),
-                                                        wg_appL[v], 1, appL_max_Mp[v], v ? 32 : 16, s));
+        if (!appL.empty())
+            RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)D(o_appL), (int32_t)appL.size(), wg_appL, 1,
+                                                    appL_max_Mp, s));
         if (!axp.empty()) RMB_HIP(ctx, launch_axpy((const KrylovJob *)D(o_axp), (int32_t)axp.size(), wg_axp, s));
         if (!un.empty()) RMB_HIP(ctx, launch_unorm((const KrylovJob *)D(o_un), (int32_t)un.size(), s));
         if (!pk.empty()) RMB_HIP(ctx, launch_pack_table((const PackJob *)D(o_pk), (int32_t)pk.size(), wg_pk, s));
@@ -963,7 +1029,7 @@ struct Engine {
                 // started from, whose relative residual was rel_start
                 const double du = std::sqrt(hcol_h(J)[1]), xu = std::sqrt(hcol_h(J)[2]);
                 if (J->cycles >= 2 && J->rel_start > 0 && xu > 0) J->gamma = du / xu / J->rel_start;
-                ok = ok && J->gamma > 0 && J->gamma * J->rel <= J->u_tol;
+                ok = ok && J->gamma > 0 && J->gamma * J->rel <= kUtolSafety * J->u_tol;
             }
             if (ok) finish_job(J, RMB_OK, nullptr);
             else if (J->iters >= J->max_iters) finish_job(J, RMB_ENOCONV, "iteration limit reached");
@@ -1323,15 +1389,35 @@ rmb_status rmb_precond_apply(rmb_ctx ctx, const rmb_precond pc, int32_t nrhs, co
     if (pc->n_small)
         RMB_HIP(ctx, launch_precond_apply_small((const PrecondApplyJob *)d, 1, pc->n_small, nrhs, pc->max_m, s));
     if (pc->n_large)
-        RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)d + 1, 1, pc->n_large, nrhs, pc->max_Mp,
-                                                large_panel_width(pc->variant), s));
+        RMB_HIP(ctx, launch_precond_apply_large((const PrecondApplyJob *)d + 1, 1, pc->n_large, nrhs, pc->max_Mp, s));
     return RMB_OK;
 }
 
 rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_width) {
     if (!ctx || !panel_width) return RMB_EINVAL;
     auto it = ctx->tuned_panel.find(padded_dim);
-    *panel_width = it == ctx->tuned_panel.end() ? 0 : large_panel_width(it->second);
+    int p = 0, g, c;
+    if (it != ctx->tuned_panel.end()) large_variant_shape(it->second, &p, &g, &c);
+    *panel_width = p;
+    return RMB_OK;
+}
+
+int32_t rmb_tile_shape_count(void) { return large_variant_count(); }
+
+rmb_status rmb_tile_shape_info(int32_t shape, int32_t *panel, int32_t *row_tiles, int32_t *chunk) {
+    if (shape < 0 || shape >= large_variant_count() || !panel || !row_tiles || !chunk) return RMB_EINVAL;
+    int p, g, c;
+    large_variant_shape(shape, &p, &g, &c);
+    *panel = p, *row_tiles = g, *chunk = c;
+    return RMB_OK;
+}
+
+rmb_status rmb_ctx_set_tile_shape(rmb_ctx ctx, int32_t padded_dim, int32_t shape) {
+    if (!ctx) return RMB_EINVAL;
+    if (padded_dim < 64 || padded_dim % 64 || shape < -1 || shape >= large_variant_count())
+        return fail(ctx, RMB_EINVAL, "rmb_ctx_set_tile_shape: padded_dim %d, shape %d", padded_dim, shape);
+    if (shape < 0) ctx->forced_shape.erase(padded_dim);
+    else ctx->forced_shape[padded_dim] = shape;
     return RMB_OK;
 }
 

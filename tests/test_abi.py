@@ -95,3 +95,14 @@ def test_server_refuses_a_tag_already_in_flight():
     with pytest.raises(ValueError, match="already in flight"):
         srv.submit(7, None, None)
     assert srv.live == {7: ("request 7",)}
+
+
+def test_tile_shapes_are_described():
+    import paper_1602_02170_amd as rmb
+    shapes = rmb.tile_shapes()
+    assert len(shapes) >= 1
+    for s in shapes:
+        assert s["panel"] in (16, 32, 64, 128) and s["row_tiles"] >= 1 and s["chunk"] >= 4
+    p = ctypes.c_int32()
+    assert rmb.library().rmb_tile_shape_info(len(shapes), ctypes.byref(p), ctypes.byref(p),
+                                             ctypes.byref(p)) == rmb.RMB_EINVAL

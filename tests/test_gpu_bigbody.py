@@ -145,3 +145,46 @@ def test_large_body_not_spd(env):
     with pytest.raises(rmb.RmbError) as e:
         rmb.Precond(ctx, rmb.System.from_suspension(s))
     assert e.value.status == rmb.RMB_ENOTSPD
+
+
+def _padded(n):
+    return (3 * n + 6 + 63) // 64 * 64
+
+
+@pytest.mark.parametrize("shape", range(4))
+def test_every_tile_shape(env, shape):
+    """Each tile shape of the large-body factorisation, forced on a context
+    for both padded sizes of the mixture (162-blob shells: 512; 42-blob
+    shells: 192): the factor through rmb_precond_apply, and a full solve whose
+    factors and applies go through the engine's per-panel-width tables,
+    against the oracle.  (A solve once indexed the engine's two apply tables
+    with the shape number, which aborted the process; this pins the mapping
+    from shape to panel width.)"""
+    rmb, torch, ctx, O = env
+    shapes = rmb.tile_shapes()
+    assert len(shapes) == 4
+    c = rmb.Context(0)
+    try:
+        for Mp in (_padded(162), _padded(42)):
+            c.set_tile_shape(Mp, shape)
+        s = _mixed(n_shells=3, seed=11 + shape)
+        s42 = _mixed(n_shells=2, shell=42, n_ico=3, seed=21 + shape)
+        for sus in (s, s42):
+            print(f"[gpu] tile shape {shape} {shapes[shape]} nb={sus.n_blobs}", flush=True)
+            rhs = np.random.default_rng(6).standard_normal((2, 3 * sus.n_blobs + 6 * sus.n_bodies))
+            ref = np.stack([O.BlockPreconditioner(sus).apply(r) for r in rhs])
+            pc = rmb.Precond(c, rmb.System.from_suspension(sus))
+            got = pc.apply(_dev(torch, rhs)).cpu().numpy()
+            pc.close()
+            assert _rel(got, ref) <= 1e-10
+            Ud, _ = O.dense_solve(sus, sus.FT)
+            U, lam, info = rmb.solve_mobility(c, rmb.System.from_suspension(sus), _dev(torch, sus.FT), tol=1e-11,
+                                              precision="fp32")
+            err = _srel(U.cpu().numpy(), Ud)
+            print(f"    apply err {_rel(got, ref):.2e}, solve {info['iterations']} iterations, U err {err:.2e}",
+                  flush=True)
+            assert info["status"] == 0 and err <= 1e-8
+        with pytest.raises(rmb.RmbError):
+            c.set_tile_shape(512, len(shapes))
+    finally:
+        c.close()
