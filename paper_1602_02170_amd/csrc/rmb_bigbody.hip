@@ -237,7 +237,7 @@ __device__ __forceinline__ void panel_update(const gmem<double> L, brsrc rs, int
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int t = pass * 4 * G + g * 4 + wave;
-            live[g] = t < RT;
+            live[g] = __builtin_amdgcn_readfirstlane(t < RT ? 1 : 0) != 0;  // wave-uniform: a scalar branch
             row0[g] = j + 16 * (t < RT ? t : RT - 1);  // clamped: loads stay unconditional
             vod[g] = ((uint32_t)(j + l16) * Mp + row0[g] + l4) * 8;
 #pragma unroll
@@ -282,23 +282,25 @@ __device__ __forceinline__ void panel_update(const gmem<double> L, brsrc rs, int
             }
         };
         if (nch > 0) {
+            // The prefetches are unconditional (the chunk index is clamped at
+            // the last chunk): with no branch around them the compiler counts
+            // exactly how many loads are in flight behind each operand and
+            // waits for that one only.
             load_b(0);
             load_a(0, a0);
             __syncthreads();  // the previous pass (or phase) is done with the LDS
             put_b(0);
             for (int ch = 0; ch < nch; ch += 2) {
                 // chunk ch in buffer 0 / registers a0; chunk ch + 1 loaded meanwhile
-                const bool more1 = ch + 1 < nch;
-                if (more1) load_b(ch + 1), load_a(ch + 1, a1);
+                load_b(min(ch + 1, nch - 1)), load_a(min(ch + 1, nch - 1), a1);
                 __syncthreads();
                 mma(0, a0);
-                if (!more1) break;
+                if (ch + 1 >= nch) break;
                 put_b(1);
-                const bool more2 = ch + 2 < nch;
-                if (more2) load_b(ch + 2), load_a(ch + 2, a0);
+                load_b(min(ch + 2, nch - 1)), load_a(min(ch + 2, nch - 1), a0);
                 __syncthreads();
                 mma(1, a1);
-                if (more2) put_b(0);
+                put_b(0);  // every wave is past mma(0): buffer 0 is free
             }
         }
         if (pass == 0) {
@@ -333,6 +335,121 @@ __device__ __forceinline__ void panel_update(const gmem<double> L, brsrc rs, int
 // and at the end Y^T is moved from the bordered rows into the Y storage,
 // S = Y^T Y and its Cholesky factor are formed, and the bordered rows are
 // cleared so that the stored L is blockdiag(L, I).
+// Step 2 of a panel (see chol_panel_kernel): the 64 x 64 diagonal block,
+// left in LDS by the update, is factorised (its L written to the factor at
+// columns [j, j+64)) and inverted into W.  A function of its own so that its
+// registers are allocated apart from the matrix-core phases'.
+__device__ __attribute__((noinline)) void diag_block(gmem<double> L, int Mp, int j, int m, CholLds &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    double *D = sh.d.D, *W = sh.d.W;
+    // 2. the 64 x 64 diagonal block in LDS, factorised in four column
+    //    blocks of 16: wave b factorises block b alone (lane = row, the
+    //    block's 16 columns in registers, values shared by readlane, no
+    //    barrier), then the waves to its right take its rank-16 update
+    //    on the matrix cores.  Columns [0, nc) are the matrix's, the
+    //    rest padding (the identity).
+    const int nc = max(0, min(kPanel, m - j));
+    if (j == 0) {  // later panels: the update left the block in LDS
+        for (int e = tid; e < kPanel * kPanel; e += 256) {
+            const int r = e % kPanel, c = e / kPanel;
+            D[c * kLd + r] = L[(j + c) * Mp + j + r];
+        }
+        __syncthreads();
+    }
+    for (int b = 0; b < 4; ++b) {
+        if (wave == b) {
+            const int r = lane;
+            double d[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) d[c] = D[(16 * b + c) * kLd + r];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int C = 16 * b + c;
+                if (C < nc) {  // uniform
+                    const double dcc = lane_value(d[c], C);
+                    const double inv = rsqrt64(dcc > 0.0 ? dcc : 1.0);
+                    if (lane == 0) {
+                        sh.rdiag[C] = inv;
+                        if (!(dcc > 0.0)) sh.bad = 1;
+                    }
+                    d[c] = r >= C ? d[c] * inv : 0.0;
+#pragma unroll
+                    for (int k = c + 1; k < 16; ++k) {
+                        const double lk = lane_value(d[c], 16 * b + k);
+                        if (r >= 16 * b + k) d[k] -= d[c] * lk;
+                    }
+                } else {
+                    d[c] = r == C ? 1.0 : 0.0;
+                    if (lane == 0) sh.rdiag[C] = 1.0;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 16; ++c) D[(16 * b + c) * kLd + r] = d[c];
+        }
+        __syncthreads();
+        if (wave > b) {
+            // D[16t.., 16w..] -= L[16t.., 16b..] L[16w.., 16b..]^T for row tiles t >= w
+            for (int t = wave; t < 4; ++t) {
+                double *C = D + (16 * wave) * kLd + 16 * t;
+                dbl4 acc = tile_load(C, kLd, l16, l4);
+                acc = tile_mma<true>(acc, D + (16 * b) * kLd + 16 * t, kLd, D + (16 * b) * kLd + 16 * wave, kLd, -1.0,
+                                     l16, l4);
+                tile_store(C, kLd, l16, l4, acc);
+            }
+        }
+        __syncthreads();
+    }
+    // the factor's block to global memory (the upper part as zeros,
+    // bordered rows included); in LDS the rows from m on (border or
+    // padding) and the upper part are cleared: the block to invert
+    for (int e = tid; e < kPanel * kPanel; e += 256) {
+        const int r = e % kPanel, c = e / kPanel;
+        double v = D[c * kLd + r];
+        if (r < c) v = 0.0;
+        L[(j + c) * Mp + j + r] = v;
+        if ((j + r >= m && c < nc) || r < c) D[c * kLd + r] = r == c ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // W = D^-1 by blocks of 16: each wave inverts its diagonal block
+    // (lane k < 16 holds column k, forward substitution), then wave j
+    // forms its block column below, X_ij = -W_ii sum_{j <= k < i} L_ik X_kj
+    {
+        const int w16 = 16 * wave;
+        if (lane < 16) {
+            const int k = lane;
+            double x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                double v = i == k ? 1.0 : 0.0;
+#pragma unroll
+                for (int q = 0; q < i; ++q) v -= D[(w16 + q) * kLd + w16 + i] * x[q];
+                x[i] = i >= k ? v * sh.rdiag[w16 + i] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) W[(w16 + k) * kLd + w16 + i] = x[i];
+        }
+        // blocks above the diagonal are zero
+        for (int e = lane; e < 16 * w16; e += 64) W[(w16 + e / w16) * kLd + e % w16] = 0.0;
+    }
+    __syncthreads();
+    {
+        const int jb = wave;  // block column
+        double *T = sh.d.T[wave];
+        for (int i = jb + 1; i < 4; ++i) {
+            dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+            for (int k = jb; k < i; ++k)
+                acc = tile_mma<false>(acc, D + (16 * k) * kLd + 16 * i, kLd, W + (16 * jb) * kLd + 16 * k, kLd, 1.0,
+                                      l16, l4);
+            tile_store(T, 16, l16, l4, acc);
+            wave_lds_sync();
+            acc = tile_mma<false>(dbl4{0.0, 0.0, 0.0, 0.0}, W + (16 * i) * kLd + 16 * i, kLd, T, 16, -1.0, l16, l4);
+            tile_store(W + (16 * jb) * kLd + 16 * i, kLd, l16, l4, acc);
+            wave_lds_sync();
+        }
+    }
+    __syncthreads();
+}
+
 template <int G, int KC>
 __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__restrict__ items) {
     __shared__ CholLds sh;
@@ -348,137 +465,41 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
     for (int j = 0; j < Mp; j += kPanel) {
         if (j > 0) panel_update<G, KC>(L, rs, Mp, j, sh);
         __syncthreads();
-        // 2. the 64 x 64 diagonal block in LDS, factorised in four column
-        //    blocks of 16: wave b factorises block b alone (lane = row, the
-        //    block's 16 columns in registers, values shared by readlane, no
-        //    barrier), then the waves to its right take its rank-16 update
-        //    on the matrix cores.  Columns [0, nc) are the matrix's, the
-        //    rest padding (the identity).
+        diag_block(L, Mp, j, m, sh);
         const int nc = max(0, min(kPanel, m - j));
-        if (j == 0) {  // later panels: the update left the block in LDS
-            for (int e = tid; e < kPanel * kPanel; e += 256) {
-                const int r = e % kPanel, c = e / kPanel;
-                D[c * kLd + r] = L[(j + c) * Mp + j + r];
-            }
-            __syncthreads();
-        }
-        for (int b = 0; b < 4; ++b) {
-            if (wave == b) {
-                const int r = lane;
-                double d[16];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) d[c] = D[(16 * b + c) * kLd + r];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    const int C = 16 * b + c;
-                    if (C < nc) {  // uniform
-                        const double dcc = lane_value(d[c], C);
-                        const double inv = rsqrt64(dcc > 0.0 ? dcc : 1.0);
-                        if (lane == 0) {
-                            sh.rdiag[C] = inv;
-                            if (!(dcc > 0.0)) sh.bad = 1;
-                        }
-                        d[c] = r >= C ? d[c] * inv : 0.0;
-#pragma unroll
-                        for (int k = c + 1; k < 16; ++k) {
-                            const double lk = lane_value(d[c], 16 * b + k);
-                            if (r >= 16 * b + k) d[k] -= d[c] * lk;
-                        }
-                    } else {
-                        d[c] = r == C ? 1.0 : 0.0;
-                        if (lane == 0) sh.rdiag[C] = 1.0;
-                    }
-                }
-#pragma unroll
-                for (int c = 0; c < 16; ++c) D[(16 * b + c) * kLd + r] = d[c];
-            }
-            __syncthreads();
-            if (wave > b) {
-                // D[16t.., 16w..] -= L[16t.., 16b..] L[16w.., 16b..]^T for row tiles t >= w
-                for (int t = wave; t < 4; ++t) {
-                    double *C = D + (16 * wave) * kLd + 16 * t;
-                    dbl4 acc = tile_load(C, kLd, l16, l4);
-                    acc = tile_mma<true>(acc, D + (16 * b) * kLd + 16 * t, kLd, D + (16 * b) * kLd + 16 * wave, kLd, -1.0,
-                                         l16, l4);
-                    tile_store(C, kLd, l16, l4, acc);
-                }
-            }
-            __syncthreads();
-        }
-        // the factor's block to global memory (the upper part as zeros,
-        // bordered rows included); in LDS the rows from m on (border or
-        // padding) and the upper part are cleared: the block to invert
-        for (int e = tid; e < kPanel * kPanel; e += 256) {
-            const int r = e % kPanel, c = e / kPanel;
-            double v = D[c * kLd + r];
-            if (r < c) v = 0.0;
-            L[(j + c) * Mp + j + r] = v;
-            if ((j + r >= m && c < nc) || r < c) D[c * kLd + r] = r == c ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        // W = D^-1 by blocks of 16: each wave inverts its diagonal block
-        // (lane k < 16 holds column k, forward substitution), then wave j
-        // forms its block column below, X_ij = -W_ii sum_{j <= k < i} L_ik X_kj
-        {
-            const int w16 = 16 * wave;
-            if (lane < 16) {
-                const int k = lane;
-                double x[16];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    double v = i == k ? 1.0 : 0.0;
-#pragma unroll
-                    for (int q = 0; q < i; ++q) v -= D[(w16 + q) * kLd + w16 + i] * x[q];
-                    x[i] = i >= k ? v * sh.rdiag[w16 + i] : 0.0;
-                }
-#pragma unroll
-                for (int i = 0; i < 16; ++i) W[(w16 + k) * kLd + w16 + i] = x[i];
-            }
-            // blocks above the diagonal are zero
-            for (int e = lane; e < 16 * w16; e += 64) W[(w16 + e / w16) * kLd + e % w16] = 0.0;
-        }
-        __syncthreads();
-        {
-            const int jb = wave;  // block column
-            double *T = sh.d.T[wave];
-            for (int i = jb + 1; i < 4; ++i) {
-                dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
-                for (int k = jb; k < i; ++k)
-                    acc = tile_mma<false>(acc, D + (16 * k) * kLd + 16 * i, kLd, W + (16 * jb) * kLd + 16 * k, kLd, 1.0,
-                                          l16, l4);
-                tile_store(T, 16, l16, l4, acc);
-                wave_lds_sync();
-                acc = tile_mma<false>(dbl4{0.0, 0.0, 0.0, 0.0}, W + (16 * i) * kLd + 16 * i, kLd, T, 16, -1.0, l16, l4);
-                tile_store(W + (16 * jb) * kLd + 16 * i, kLd, l16, l4, acc);
-                wave_lds_sync();
-            }
-        }
-        __syncthreads();
         // stored inverses of the two 32 x 32 diagonal blocks (the substitutions' blocks)
         for (int e = tid; e < 2 * 32 * 32; e += 256) {
             const int b = e / 1024, o = e % 1024, r = o % 32, c = o / 32;
             Dinv[(int64_t)(j + 32 * b) * 32 + o] = W[(32 * b + c) * kLd + 32 * b + r];
         }
         // 3. rows below: X = A W^T (A operand from the factor, B = W^T from
-        //    LDS); columns past m stay zero
+        //    LDS); columns past m stay zero.  Wave w takes row tiles w, w + 4,
+        //    ...; the next tile's operands are loaded (unconditionally, the
+        //    index clamped) while the current one is multiplied.
         {
             const int RT4 = (Mp - j - kPanel) / 16;
-            for (int t0 = 0; t0 < RT4; t0 += 4) {
-                const int t = t0 + wave;
-                if (t >= RT4) break;  // wave-uniform
-                const int row0 = j + kPanel + 16 * t;
-                dbl4 acc[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
-                double a[16];
+            const int ntile = RT4 > wave ? (RT4 - wave + 3) / 4 : 0;
+            auto load_t = [&](int q, double (&a)[16]) {
+                const int row0 = j + kPanel + 16 * (wave + 4 * min(q, ntile - 1));
                 const uint32_t vo = ((uint32_t)l4 * Mp + row0 + l16) * 8;
 #pragma unroll
                 for (int u = 0; u < 16; ++u) a[u] = bload(rs, vo, (uint32_t)(j + 4 * u) * Mp * 8);
+            };
+            auto solve_t = [&](int q, const double (&a)[16]) {
+                const int row0 = j + kPanel + 16 * (wave + 4 * q);
+                dbl4 acc[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
+                    double b[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c)
-                        acc[c] = mfma16x16x4(a[u], W[(4 * u + l4) * kLd + 16 * c + l16], acc[c]);
+                    for (int c = 0; c < 4; ++c) b[c] = W[(4 * u + l4) * kLd + 16 * c + l16];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) acc[c] = mfma16x16x4(a[u], b[c], acc[c]);
+                    // keep the operand reads next to their products (hoisting
+                    // all of them would hold 64 more registers)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
@@ -486,6 +507,17 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         L[(j + col) * Mp + row0 + l4 + 4 * r] = col < nc ? acc[c][r] : 0.0;
+                }
+            };
+            if (ntile > 0) {
+                double a0[16], a1[16];
+                load_t(0, a0);
+                for (int q = 0; q < ntile; q += 2) {
+                    load_t(q + 1, a1);
+                    solve_t(q, a0);
+                    if (q + 1 >= ntile) break;
+                    load_t(q + 2, a0);
+                    solve_t(q + 1, a1);
                 }
             }
         }
