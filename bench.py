@@ -495,6 +495,8 @@ def main():
     ap.add_argument("--serve-budget-gib", type=int, default=0, help="server context budget (0: 16 GiB)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--only-step", action="store_true", help="timed solves only (for profiling)")
+    ap.add_argument("--only-factor", action="store_true",
+                    help="the batched large-body factorisation leg only (for profiling); prints its results")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -508,6 +510,13 @@ def main():
     import suspensions as S
 
     ctx = rmb.Context(0)
+    if args.only_factor:
+        res = factor_leg(rmb, torch, ctx, S)
+        if args.calib_copy:
+            copy_calibration(torch, args.calib_copy)
+        ctx.close()
+        print(json.dumps({"batched_factor": res}), flush=True)
+        return
     sus = S.boomerangs_wall()
     sysd = rmb.System.from_suspension(sus)
     FT = torch.tensor(sus.FT, dtype=torch.float64, device="cuda")
