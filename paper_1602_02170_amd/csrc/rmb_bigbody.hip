@@ -11,17 +11,19 @@
 //          offset j*NB, each column-major (room for NB = 32: Mp x 32)
 //   Sc   : 6 x 6 lower (Cholesky factor of S = Y^T Y)
 //
-// Build, each launch covering all bodies: assembly of the lower triangle,
-// Cholesky (with the diagonal-block inverses), projection (Y, S, Sc).
+// Build, two launches covering all bodies: assembly of the lower triangle
+// (with the bordered rows), then the factorisation, which yields L, the
+// diagonal-block inverses, Y, S and Sc.
 //
-// Cholesky: one workgroup (4 waves) per body, left-looking by panels of NB
+// Cholesky: one workgroup (4 waves) per body, left-looking by panels of 64
 // columns.  Panel update
-//   A[j:, j:j+NB] -= L[j:, 0:j] L[j:j+NB, 0:j]^T
+//   A[j:, j:j+64] -= L[j:, 0:j] L[j:j+64, 0:j]^T
 // runs on FP64 matrix cores (v_mfma_f64_16x16x4: D[16x16] += A[16x4] B[4x16]);
-// the operands of the next 16 columns of L are loaded while the current ones
-// are multiplied.  The panel's NB x NB diagonal block is then factorised in
-// LDS (one barrier per column) and inverted, and the rows below it become
-// x = a L11^-T, a product with the inverse, also on matrix cores.
+// the operands of the next chunk of columns of L are loaded while the
+// current ones are multiplied.  The panel's diagonal block is updated first,
+// factorised in LDS and inverted; then the rows below are updated pass by
+// pass and, still in registers, become x = a L11^-T, a product with the
+// inverse, also on matrix cores, so each element of L is stored once.
 //
 // Substitutions (projection and apply) go by panels, right-looking: the
 // panel's unknowns are x_j = Dinv_j b_j, then every later (earlier, for
@@ -149,17 +151,22 @@ __device__ __forceinline__ void bstore(double v, brsrc r, uint32_t voff, uint32_
                                           voff, soff, 0);
 }
 
-// LDS of one workgroup: the staged B chunks of the panel update, or the
-// diagonal block and its inverse (never both at once).
+// LDS of one workgroup.  W, the inverse of the panel's diagonal block, lives
+// from its factorisation through the panel's row solve; the rest is shared
+// by phases that never overlap: the block itself while it is factorised, the
+// staged B chunks of an update pass, the per-wave transposes of the row
+// solve (after the pass's last chunk), and the bordered rows at the end.
+constexpr int kXld = 17;  // leading dimension of a transposed 16 x 64 tile
 struct CholLds {
+    double W[kPanel * kLd];  // column-major (leading dimension kLd)
     union {
-        double B[2][32 * kPanel];  // chunk of L[j:j+64, k0:k0+KC], column-major (KC <= 32)
         struct {
             double D[kPanel * kLd];  // diagonal block, column-major (leading dimension kLd)
-            double W[kPanel * kLd];  // its inverse, likewise
             double T[4][16 * 16];    // per wave: a 16 x 16 product, column-major
         } d;
-        double Yt[6 * 768];  // epilogue: the bordered rows (Y^T), row k at k * m
+        double B[2][32 * kPanel];    // chunk of L[j:j+64, k0:k0+KC], column-major (KC <= 32)
+        double X[4][kPanel * kXld];  // per wave: a 16 x 64 tile, column-major
+        double Yt[6 * 768];          // epilogue: the bordered rows (Y^T), row k at k * m
     };
     double rdiag[kPanel];  // 1 / L[c][c] of the block (1 in the padding)
     double S[36];
@@ -212,112 +219,94 @@ __device__ __forceinline__ dbl4 tile_mma(dbl4 acc, const double *A, int lda, con
     return acc;
 }
 
-// Panel update of rows [j, Mp), columns [j, j + 64):
-//   A[r, j:j+64] -= L[r, 0:j] L[j:j+64, 0:j]^T
-// Each wave owns G 16-row tiles per pass (tiles wave, wave + 4, ...); the
-// B operand L[j:j+64, k0:k0+KC] is staged in LDS per chunk of KC columns
+// Update of row tiles of panel j (columns [j, j + 64)) by the columns [0, j)
+// to its left,
+//   A[r, j:j+64] -= L[r, 0:j] L[j:j+64, 0:j]^T,
+// wave w taking tiles tb + w + 4 g, g < G, of rows [j, Mp) (clamped at the
+// last tile: a clamped tile does no arithmetic, live[g] false).  The B
+// operand L[j:j+64, k0:k0+KC] is staged in LDS per chunk of KC columns
 // (double buffered, one barrier per chunk), the A operand is read straight
 // from the factor, a chunk ahead.  The accumulators start at -A and take
-// +L L^T, so no operand needs a sign change; the result is negated once.
+// +L L^T, so no operand needs a sign change: acc[g] ends as minus the
+// updated tile, lane holding rows l4 + 4 r, column 16 c + l16 in
+// acc[g][c][r], and vod[g] is the byte offset of that lane's element
+// (row l4, column l16) of the tile.  With j = 0 the tiles are just loaded.
 template <int G, int KC>
-__device__ __forceinline__ void panel_update(const gmem<double> L, brsrc rs, int Mp, int j, CholLds &sh) {
+__device__ __forceinline__ void update_tiles(brsrc rs, int Mp, int j, int tb, dbl4 (&acc)[G][4], bool (&live)[G],
+                                             uint32_t (&vod)[G], CholLds &sh) {
     constexpr int KS = KC / 4;  // MFMA steps per chunk
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
     const int RT = (Mp - j) / 16;
     const int nch = j / KC;
-    // passes go bottom up, so that the last one holds the diagonal block's
-    // rows (its first tile of every wave), which go to LDS, not to memory
-    const int npass = (RT + 4 * G - 1) / (4 * G);
-    for (int pass = npass - 1; pass >= 0; --pass) {
-        dbl4 acc[G][4];
-        int row0[G];
-        bool live[G];
-        const uint32_t colb = (uint32_t)Mp * 8;  // bytes per column of L
-        uint32_t vod[G];  // the accumulator's element (row0 + l4, j + l16) of each tile
+    const uint32_t colb = (uint32_t)Mp * 8;  // bytes per column of L
+    int row0[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int t = pass * 4 * G + g * 4 + wave;
-            live[g] = __builtin_amdgcn_readfirstlane(t < RT ? 1 : 0) != 0;  // wave-uniform: a scalar branch
-            row0[g] = j + 16 * (t < RT ? t : RT - 1);  // clamped: loads stay unconditional
-            vod[g] = ((uint32_t)(j + l16) * Mp + row0[g] + l4) * 8;
+    for (int g = 0; g < G; ++g) {
+        const int t = tb + g * 4 + wave;
+        live[g] = __builtin_amdgcn_readfirstlane(t < RT ? 1 : 0) != 0;  // wave-uniform: a scalar branch
+        row0[g] = j + 16 * (t < RT ? t : RT - 1);  // clamped: loads stay unconditional
+        vod[g] = ((uint32_t)(j + l16) * Mp + row0[g] + l4) * 8;
 #pragma unroll
-            for (int c = 0; c < 4; ++c)
+        for (int c = 0; c < 4; ++c)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) acc[g][c][r] = -bload(rs, vod[g], (16 * c) * colb + 32 * r);
-        }
-        // B staging: thread tid loads KC * 64 / 256 values of the chunk
-        constexpr int BV = KC * kPanel / 256;
-        double bst[BV];
-        double a0[KS][G], a1[KS][G];
-        uint32_t voa[G];
+            for (int r = 0; r < 4; ++r) acc[g][c][r] = -bload(rs, vod[g], (16 * c) * colb + 32 * r);
+    }
+    if (nch == 0) return;
+    // B staging: thread tid loads KC * 64 / 256 values of the chunk
+    constexpr int BV = KC * kPanel / 256;
+    double bst[BV];
+    double a0[KS][G], a1[KS][G];
+    uint32_t voa[G];
 #pragma unroll
-        for (int g = 0; g < G; ++g) voa[g] = ((uint32_t)l4 * Mp + row0[g] + l16) * 8;
-        const uint32_t vob = ((uint32_t)(tid / kPanel) * Mp + j + tid % kPanel) * 8;  // + v * (256 / 64) columns
-        auto load_b = [&](int ch) {
+    for (int g = 0; g < G; ++g) voa[g] = ((uint32_t)l4 * Mp + row0[g] + l16) * 8;
+    const uint32_t vob = ((uint32_t)(tid / kPanel) * Mp + j + tid % kPanel) * 8;  // + v * (256 / 64) columns
+    auto load_b = [&](int ch) {
 #pragma unroll
-            for (int v = 0; v < BV; ++v) bst[v] = bload(rs, vob, (uint32_t)(ch * KC + v * (256 / kPanel)) * colb);
-        };
-        auto put_b = [&](int buf) {
+        for (int v = 0; v < BV; ++v) bst[v] = bload(rs, vob, (uint32_t)(ch * KC + v * (256 / kPanel)) * colb);
+    };
+    auto put_b = [&](int buf) {
 #pragma unroll
-            for (int v = 0; v < BV; ++v) sh.B[buf][tid + 256 * v] = bst[v];
-        };
-        auto load_a = [&](int ch, double (&a)[KS][G]) {
+        for (int v = 0; v < BV; ++v) sh.B[buf][tid + 256 * v] = bst[v];
+    };
+    auto load_a = [&](int ch, double (&a)[KS][G]) {
 #pragma unroll
-            for (int u = 0; u < KS; ++u)
+        for (int u = 0; u < KS; ++u)
 #pragma unroll
-                for (int g = 0; g < G; ++g) a[u][g] = bload(rs, voa[g], (uint32_t)(ch * KC + 4 * u) * colb);
-        };
-        auto mma = [&](int buf, const double (&a)[KS][G]) {
+            for (int g = 0; g < G; ++g) a[u][g] = bload(rs, voa[g], (uint32_t)(ch * KC + 4 * u) * colb);
+    };
+    auto mma = [&](int buf, const double (&a)[KS][G]) {
 #pragma unroll
-            for (int u = 0; u < KS; ++u) {
-                double b[4];
+        for (int u = 0; u < KS; ++u) {
+            double b[4];
 #pragma unroll
-                for (int c = 0; c < 4; ++c) b[c] = sh.B[buf][(4 * u + l4) * kPanel + 16 * c + l16];
+            for (int c = 0; c < 4; ++c) b[c] = sh.B[buf][(4 * u + l4) * kPanel + 16 * c + l16];
 #pragma unroll
-                for (int g = 0; g < G; ++g) {
-                    if (!live[g]) continue;  // wave-uniform: a clamped tile does no arithmetic
+            for (int g = 0; g < G; ++g) {
+                if (!live[g]) continue;  // wave-uniform: a clamped tile does no arithmetic
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[g][c] = mfma16x16x4(a[u][g], b[c], acc[g][c]);
-                }
-            }
-        };
-        if (nch > 0) {
-            // The prefetches are unconditional (the chunk index is clamped at
-            // the last chunk): with no branch around them the compiler counts
-            // exactly how many loads are in flight behind each operand and
-            // waits for that one only.
-            load_b(0);
-            load_a(0, a0);
-            __syncthreads();  // the previous pass (or phase) is done with the LDS
-            put_b(0);
-            for (int ch = 0; ch < nch; ch += 2) {
-                // chunk ch in buffer 0 / registers a0; chunk ch + 1 loaded meanwhile
-                load_b(min(ch + 1, nch - 1)), load_a(min(ch + 1, nch - 1), a1);
-                __syncthreads();
-                mma(0, a0);
-                if (ch + 1 >= nch) break;
-                put_b(1);
-                load_b(min(ch + 2, nch - 1)), load_a(min(ch + 2, nch - 1), a0);
-                __syncthreads();
-                mma(1, a1);
-                put_b(0);  // every wave is past mma(0): buffer 0 is free
+                for (int c = 0; c < 4; ++c) acc[g][c] = mfma16x16x4(a[u][g], b[c], acc[g][c]);
             }
         }
-        if (pass == 0) {
-            __syncthreads();  // the last chunk's operands are no longer read: D overlays them
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sh.d.D[(16 * c + l16) * kLd + 16 * wave + l4 + 4 * r] = -acc[0][c][r];
-        }
-#pragma unroll
-        for (int g = pass == 0 ? 1 : 0; g < G; ++g) {
-            if (!live[g]) continue;
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) bstore(-acc[g][c][r], rs, vod[g], (16 * c) * colb + 32 * r);
-        }
+    };
+    // The prefetches are unconditional (the chunk index is clamped at the
+    // last chunk): with no branch around them the compiler counts exactly
+    // how many loads are in flight behind each operand and waits for that
+    // one only.
+    load_b(0);
+    load_a(0, a0);
+    __syncthreads();  // the previous phase is done with the LDS
+    put_b(0);
+    for (int ch = 0; ch < nch; ch += 2) {
+        // chunk ch in buffer 0 / registers a0; chunk ch + 1 loaded meanwhile
+        load_b(min(ch + 1, nch - 1)), load_a(min(ch + 1, nch - 1), a1);
+        __syncthreads();
+        mma(0, a0);
+        if (ch + 1 >= nch) break;
+        put_b(1);
+        load_b(min(ch + 2, nch - 1)), load_a(min(ch + 2, nch - 1), a0);
+        __syncthreads();
+        mma(1, a1);
+        put_b(0);  // every wave is past mma(0): buffer 0 is free
     }
 }
 
@@ -327,21 +316,22 @@ __device__ __forceinline__ void panel_update(const gmem<double> L, brsrc rs, int
 // are K_p^T L^-T = Y^T, so the factorisation yields Y = L^-1 K_p as well;
 // only the first m columns are factorised (the others are padding, kept at
 // the identity).  Per panel of 64 columns:
-//   1. panel update on matrix cores (panel_update);
-//   2. the 64 x 64 diagonal block in LDS: Cholesky with one barrier per
-//      column (column scaling deferred to the end), then its inverse W by
-//      columns, four lanes per column;
-//   3. the rows below: X = A W^T on matrix cores;
-// and at the end Y^T is moved from the bordered rows into the Y storage,
+//   1. the panel's diagonal block, updated on matrix cores (update_tiles),
+//      to LDS;
+//   2. its Cholesky factor and inverse W (diag_block);
+//   3. the rows below, in passes of row tiles: each tile updated, then
+//      solved in registers, X = A W^T, on matrix cores, and stored once.
+// At the end Y^T is moved from the bordered rows into the Y storage,
 // S = Y^T Y and its Cholesky factor are formed, and the bordered rows are
 // cleared so that the stored L is blockdiag(L, I).
-// Step 2 of a panel (see chol_panel_kernel): the 64 x 64 diagonal block,
-// left in LDS by the update, is factorised (its L written to the factor at
-// columns [j, j+64)) and inverted into W.  A function of its own so that its
-// registers are allocated apart from the matrix-core phases'.
+//
+// Step 2: the 64 x 64 diagonal block in LDS is factorised (its L written to
+// the factor at columns [j, j+64)) and inverted into W.  A function of its
+// own so that its registers are allocated apart from the matrix-core
+// phases'.
 __device__ __attribute__((noinline)) void diag_block(gmem<double> L, int Mp, int j, int m, CholLds &sh) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
-    double *D = sh.d.D, *W = sh.d.W;
+    double *D = sh.d.D, *W = sh.W;
     // 2. the 64 x 64 diagonal block in LDS, factorised in four column
     //    blocks of 16: wave b factorises block b alone (lane = row, the
     //    block's 16 columns in registers, values shared by readlane, no
@@ -349,13 +339,6 @@ __device__ __attribute__((noinline)) void diag_block(gmem<double> L, int Mp, int
     //    on the matrix cores.  Columns [0, nc) are the matrix's, the
     //    rest padding (the identity).
     const int nc = max(0, min(kPanel, m - j));
-    if (j == 0) {  // later panels: the update left the block in LDS
-        for (int e = tid; e < kPanel * kPanel; e += 256) {
-            const int r = e % kPanel, c = e / kPanel;
-            D[c * kLd + r] = L[(j + c) * Mp + j + r];
-        }
-        __syncthreads();
-    }
     for (int b = 0; b < 4; ++b) {
         if (wave == b) {
             const int r = lane;
@@ -458,70 +441,73 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
     const gmem<double> L = as_global(it.w.factor);
     const gmem<double> Dinv = as_global(big_Dinv(it));
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
-    double *D = sh.d.D, *W = sh.d.W;
+    const uint32_t colb = (uint32_t)Mp * 8;  // bytes per column of L
     const brsrc rs = factor_rsrc(it);
     if (tid == 0) sh.bad = 0;
 
     for (int j = 0; j < Mp; j += kPanel) {
-        if (j > 0) panel_update<G, KC>(L, rs, Mp, j, sh);
+        const int RT = (Mp - j) / 16;
+        {
+            // 1. the diagonal block's rows (tile w of wave w), updated, to LDS
+            dbl4 acc[1][4];
+            bool live[1];
+            uint32_t vod[1];
+            update_tiles<1, KC>(rs, Mp, j, 0, acc, live, vod, sh);
+            __syncthreads();  // the staged chunks are no longer read: D overlays them
+#pragma unroll
+            for (int c = 0; c < 4; ++c)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sh.d.D[(16 * c + l16) * kLd + 16 * wave + l4 + 4 * r] = -acc[0][c][r];
+        }
         __syncthreads();
         diag_block(L, Mp, j, m, sh);
         const int nc = max(0, min(kPanel, m - j));
         // stored inverses of the two 32 x 32 diagonal blocks (the substitutions' blocks)
         for (int e = tid; e < 2 * 32 * 32; e += 256) {
             const int b = e / 1024, o = e % 1024, r = o % 32, c = o / 32;
-            Dinv[(int64_t)(j + 32 * b) * 32 + o] = W[(32 * b + c) * kLd + 32 * b + r];
+            Dinv[(int64_t)(j + 32 * b) * 32 + o] = sh.W[(32 * b + c) * kLd + 32 * b + r];
         }
-        // 3. rows below: X = A W^T (A operand from the factor, B = W^T from
-        //    LDS); columns past m stay zero.  Wave w takes row tiles w, w + 4,
-        //    ...; the next tile's operands are loaded (unconditionally, the
-        //    index clamped) while the current one is multiplied.
-        {
-            const int RT4 = (Mp - j - kPanel) / 16;
-            const int ntile = RT4 > wave ? (RT4 - wave + 3) / 4 : 0;
-            auto load_t = [&](int q, double (&a)[16]) {
-                const int row0 = j + kPanel + 16 * (wave + 4 * min(q, ntile - 1));
-                const uint32_t vo = ((uint32_t)l4 * Mp + row0 + l16) * 8;
+        // 3. the rows below, 4G tiles per pass: each tile updated, then
+        //    X = A W^T with A from the accumulators (through a per-wave
+        //    transpose in LDS) and B = W^T from LDS; columns past m are zero.
+        //    Every element of L below the diagonal block is stored once.
+        for (int tb = 4; tb < RT; tb += 4 * G) {
+            dbl4 acc[G][4];
+            bool live[G];
+            uint32_t vod[G];
+            update_tiles<G, KC>(rs, Mp, j, tb, acc, live, vod, sh);
+            __syncthreads();  // the staged chunks are no longer read: the transposes overlay them
+            double *Xw = sh.X[wave];
 #pragma unroll
-                for (int u = 0; u < 16; ++u) a[u] = bload(rs, vo, (uint32_t)(j + 4 * u) * Mp * 8);
-            };
-            auto solve_t = [&](int q, const double (&a)[16]) {
-                const int row0 = j + kPanel + 16 * (wave + 4 * q);
-                dbl4 acc[4];
+            for (int g = 0; g < G; ++g) {
+                if (!live[g]) continue;  // wave-uniform
 #pragma unroll
-                for (int c = 0; c < 4; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, 0.0};
+                for (int c = 0; c < 4; ++c)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) Xw[(16 * c + l16) * kXld + l4 + 4 * r] = -acc[g][c][r];
+                wave_lds_sync();
+                dbl4 x[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) x[c] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
                 for (int u = 0; u < 16; ++u) {
+                    const double a = Xw[(4 * u + l4) * kXld + l16];
                     double b[4];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) b[c] = W[(4 * u + l4) * kLd + 16 * c + l16];
+                    for (int c = 0; c < 4; ++c) b[c] = sh.W[(4 * u + l4) * kLd + 16 * c + l16];
 #pragma unroll
-                    for (int c = 0; c < 4; ++c) acc[c] = mfma16x16x4(a[u], b[c], acc[c]);
-                    // keep the operand reads next to their products (hoisting
-                    // all of them would hold 64 more registers)
-                    __builtin_amdgcn_sched_barrier(0);
+                    for (int c = 0; c < 4; ++c) x[c] = mfma16x16x4(a, b[c], x[c]);
                 }
 #pragma unroll
                 for (int c = 0; c < 4; ++c) {
-                    const int col = 16 * c + l16;
+                    const bool keep = 16 * c + l16 < nc;
 #pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        L[(j + col) * Mp + row0 + l4 + 4 * r] = col < nc ? acc[c][r] : 0.0;
+                    for (int r = 0; r < 4; ++r) bstore(keep ? x[c][r] : 0.0, rs, vod[g], (16 * c) * colb + 32 * r);
                 }
-            };
-            if (ntile > 0) {
-                double a0[16], a1[16];
-                load_t(0, a0);
-                for (int q = 0; q < ntile; q += 2) {
-                    load_t(q + 1, a1);
-                    solve_t(q, a0);
-                    if (q + 1 >= ntile) break;
-                    load_t(q + 2, a0);
-                    solve_t(q + 1, a1);
-                }
+                wave_lds_sync();  // the tile's reads are done before the next tile's writes
             }
         }
-        __syncthreads();
+        __syncthreads();  // the next panel's phases reuse the LDS
     }
 
     // Y^T from the bordered rows (then cleared), S = Y^T Y, its Cholesky factor
