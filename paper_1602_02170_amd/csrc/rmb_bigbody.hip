@@ -310,14 +310,77 @@ __device__ __forceinline__ void update_tiles(brsrc rs, int Mp, int j, int tb, db
     }
 }
 
+// The panel's diagonal block, updated, into LDS:
+//   D = A[j:j+64, j:j+64] - L[j:j+64, 0:j] L[j:j+64, 0:j]^T,
+// its lower 16 x 16 tiles only (the upper ones are left as they are and
+// never read).  The k range of the product is split over the waves (wave w
+// takes columns [w j/4, (w+1) j/4)), and one set of loads serves as both
+// operands, since both are rows of L[j:j+64, 0:j]; the next step's operands
+// are loaded while the current ones are multiplied.  Then wave 0 stores A
+// minus its sum and each further wave subtracts its own, in wave order.
+__device__ __forceinline__ void diag_rows(brsrc rs, int Mp, int j, CholLds &sh) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
+    double *D = sh.d.D;
+    const uint32_t colb = (uint32_t)Mp * 8;  // bytes per column of L
+    dbl4 acc[10];                            // tile (t, c), c <= t, at t (t + 1) / 2 + c
+#pragma unroll
+    for (int i = 0; i < 10; ++i) acc[i] = dbl4{0.0, 0.0, 0.0, 0.0};
+    const int kq = j / 4;  // a multiple of 16
+    const int k0 = wave * kq, k1 = k0 + kq;
+    uint32_t vo[4];  // lane's element (row j + 16 t + l16, column l4)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) vo[t] = ((uint32_t)l4 * Mp + j + 16 * t + l16) * 8;
+    auto load = [&](int k, double (&v)[4]) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = bload(rs, vo[t], (uint32_t)k * colb);
+    };
+    auto mma = [&](const double (&v)[4]) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int c = 0; c <= t; ++c) acc[t * (t + 1) / 2 + c] = mfma16x16x4(v[t], v[c], acc[t * (t + 1) / 2 + c]);
+    };
+    if (kq > 0) {
+        double v0[4], v1[4];
+        load(k0, v0);
+        for (int k = k0; k < k1; k += 8) {
+            load(k + 4, v1);  // kq is a multiple of 8: k + 4 < k1
+            mma(v0);
+            load(min(k + 8, k1 - 4), v0);  // clamped on the last step (loaded, not used)
+            mma(v1);
+        }
+    }
+    for (int w = 0; w < 4; ++w) {
+        if (w > 0 && kq == 0) break;  // uniform: nothing to subtract
+        if (wave == w) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+#pragma unroll
+                for (int c = 0; c <= t; ++c) {
+                    double *C = D + (16 * c) * kLd + 16 * t;
+                    dbl4 x;
+                    if (w == 0) {
+                        const uint32_t va = ((uint32_t)(j + 16 * c + l16) * Mp + j + 16 * t + l4) * 8;
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) x[r] = bload(rs, va, 32 * r);
+                    } else {
+                        x = tile_load(C, kLd, l16, l4);
+                    }
+                    tile_store(C, kLd, l16, l4, x - acc[t * (t + 1) / 2 + c]);
+                }
+        }
+        __syncthreads();
+    }
+}
+
 // One workgroup (4 waves) per body, all bodies in one launch.  The factored
 // matrix is [M_pp; K_p^T] bordered below by the 6 rows of K_p^T (rows m ..
 // m+5 of the padded block, written by the assembly): its Cholesky rows there
 // are K_p^T L^-T = Y^T, so the factorisation yields Y = L^-1 K_p as well;
 // only the first m columns are factorised (the others are padding, kept at
 // the identity).  Per panel of 64 columns:
-//   1. the panel's diagonal block, updated on matrix cores (update_tiles),
-//      to LDS;
+//   1. the panel's diagonal block, updated on matrix cores (diag_rows), to
+//      LDS;
 //   2. its Cholesky factor and inverse W (diag_block);
 //   3. the rows below, in passes of row tiles: each tile updated, then
 //      solved in registers, X = A W^T, on matrix cores, and stored once.
@@ -447,19 +510,7 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
 
     for (int j = 0; j < Mp; j += kPanel) {
         const int RT = (Mp - j) / 16;
-        {
-            // 1. the diagonal block's rows (tile w of wave w), updated, to LDS
-            dbl4 acc[1][4];
-            bool live[1];
-            uint32_t vod[1];
-            update_tiles<1, KC>(rs, Mp, j, 0, acc, live, vod, sh);
-            __syncthreads();  // the staged chunks are no longer read: D overlays them
-#pragma unroll
-            for (int c = 0; c < 4; ++c)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sh.d.D[(16 * c + l16) * kLd + 16 * wave + l4 + 4 * r] = -acc[0][c][r];
-        }
-        __syncthreads();
+        diag_rows(rs, Mp, j, sh);  // 1. (ends with a barrier)
         diag_block(L, Mp, j, m, sh);
         const int nc = max(0, min(kPanel, m - j));
         // stored inverses of the two 32 x 32 diagonal blocks (the substitutions' blocks)
