@@ -402,6 +402,8 @@ __device__ __attribute__((noinline)) void diag_block(gmem<double> L, int Mp, int
     //    on the matrix cores.  Columns [0, nc) are the matrix's, the
     //    rest padding (the identity).
     const int nc = max(0, min(kPanel, m - j));
+    // unrolled: every readlane below takes a constant lane
+#pragma unroll
     for (int b = 0; b < 4; ++b) {
         if (wave == b) {
             const int r = lane;
@@ -419,11 +421,10 @@ __device__ __attribute__((noinline)) void diag_block(gmem<double> L, int Mp, int
                         if (!(dcc > 0.0)) sh.bad = 1;
                     }
                     d[c] = r >= C ? d[c] * inv : 0.0;
+                    // rows above a later column's diagonal take the update
+                    // too; they are cleared when that column is finished
 #pragma unroll
-                    for (int k = c + 1; k < 16; ++k) {
-                        const double lk = lane_value(d[c], 16 * b + k);
-                        if (r >= 16 * b + k) d[k] -= d[c] * lk;
-                    }
+                    for (int k = c + 1; k < 16; ++k) d[k] -= d[c] * lane_value(d[c], 16 * b + k);
                 } else {
                     d[c] = r == C ? 1.0 : 0.0;
                     if (lane == 0) sh.rdiag[C] = 1.0;
