@@ -606,9 +606,17 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
 }
 
 // ---------------------------------------------------------------------------
-// blocked substitutions with R right-hand sides held in LDS (row-major
-// Mp x R).  Dj: NB x NB staging, T: NB x R.
+// blocked substitutions with R right-hand sides held in LDS, one column of
+// Mp per right-hand side (X[c * Mp + row]: threads updating consecutive rows
+// touch consecutive words).  Dj: the NB x NB diagonal-block inverse staged
+// with leading dimension NB + 1 (read by rows and by columns without bank
+// conflicts), T: NB x R.
 // ---------------------------------------------------------------------------
+
+template <int NB>
+__device__ __forceinline__ void stage_dinv(const gmem<const double> Dinv, int j, double *Dj) {
+    for (int e = threadIdx.x; e < NB * NB; e += 256) Dj[(e / NB) * (NB + 1) + e % NB] = Dinv[(int64_t)j * NB + e];
+}
 
 // X <- L^-1 X
 template <int NB, int R>
@@ -616,17 +624,17 @@ __device__ void forward_rl(const gmem<const double> L, const gmem<const double> 
                            double *Dj, double *T) {
     const int tid = threadIdx.x;
     for (int j = 0; j < Mp; j += NB) {
-        for (int e = tid; e < NB * NB; e += 256) Dj[e] = Dinv[(int64_t)j * NB + e];
+        stage_dinv<NB>(Dinv, j, Dj);
         __syncthreads();
         // x_j = Dinv_j b_j
         for (int o = tid; o < NB * R; o += 256) {
-            const int r = o / R, c = o % R;
+            const int r = o % NB, c = o / NB;
             double acc = 0.0;
-            for (int l = 0; l <= r; ++l) acc += Dj[l * NB + r] * X[(j + l) * R + c];
+            for (int l = 0; l <= r; ++l) acc += Dj[l * (NB + 1) + r] * X[c * Mp + j + l];
             T[o] = acc;
         }
         __syncthreads();
-        for (int o = tid; o < NB * R; o += 256) X[j * R + o] = T[o];
+        for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[o];
         __syncthreads();
         // later rows: b[r] -= L[r, j:j+NB] x_j
         for (int r = j + NB + tid; r < Mp; r += 256) {
@@ -637,10 +645,10 @@ __device__ void forward_rl(const gmem<const double> L, const gmem<const double> 
             for (int l = 0; l < NB; ++l) {
                 const double lv = L[(int64_t)(j + l) * Mp + r];
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lv * X[(j + l) * R + c];
+                for (int c = 0; c < R; ++c) acc[c] += lv * X[c * Mp + j + l];
             }
 #pragma unroll
-            for (int c = 0; c < R; ++c) X[r * R + c] -= acc[c];
+            for (int c = 0; c < R; ++c) X[c * Mp + r] -= acc[c];
         }
         __syncthreads();
     }
@@ -652,17 +660,17 @@ __device__ void backward_rl(const gmem<const double> L, const gmem<const double>
                             double *Dj, double *T) {
     const int tid = threadIdx.x;
     for (int j = Mp - NB; j >= 0; j -= NB) {
-        for (int e = tid; e < NB * NB; e += 256) Dj[e] = Dinv[(int64_t)j * NB + e];
+        stage_dinv<NB>(Dinv, j, Dj);
         __syncthreads();
         // x_j = Dinv_j^T b_j: x[r] = sum_{l >= r} Dinv_j[l][r] b[l]
         for (int o = tid; o < NB * R; o += 256) {
-            const int r = o / R, c = o % R;
+            const int r = o % NB, c = o / NB;
             double acc = 0.0;
-            for (int l = r; l < NB; ++l) acc += Dj[r * NB + l] * X[(j + l) * R + c];
+            for (int l = r; l < NB; ++l) acc += Dj[r * (NB + 1) + l] * X[c * Mp + j + l];
             T[o] = acc;
         }
         __syncthreads();
-        for (int o = tid; o < NB * R; o += 256) X[j * R + o] = T[o];
+        for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[o];
         __syncthreads();
         // earlier rows: b[k] -= sum_l L[j+l][k] x[j+l]
         for (int k = tid; k < j; k += 256) {
@@ -674,10 +682,10 @@ __device__ void backward_rl(const gmem<const double> L, const gmem<const double>
             for (int l = 0; l < NB; ++l) {
                 const double lv = col[l];
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lv * X[(j + l) * R + c];
+                for (int c = 0; c < R; ++c) acc[c] += lv * X[c * Mp + j + l];
             }
 #pragma unroll
-            for (int c = 0; c < R; ++c) X[k * R + c] -= acc[c];
+            for (int c = 0; c < R; ++c) X[c * Mp + k] -= acc[c];
         }
         __syncthreads();
     }
@@ -689,7 +697,7 @@ template <int NB>
 __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob *__restrict__ jobs, int32_t n_jobs) {
     constexpr int R = 8, QP = 16;  // rhs per workgroup; partial sums per (rhs, k) of Y^T t
     extern __shared__ double lds[];
-    __shared__ double Dj[NB * NB > QP * R * 6 ? NB * NB : QP * R * 6];
+    __shared__ double Dj[NB * (NB + 1) > QP * R * 6 ? NB * (NB + 1) : QP * R * 6];
     __shared__ double T[NB * R];
     __shared__ double g[R][6];
     const int64_t w = blockIdx.x;
@@ -706,7 +714,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     if (nr <= 0) return;
     const gmem<const double> L = as_global(it.w.factor);
     const double *Y = big_Y(it), *Dinv = big_Dinv(it), *Sc = big_Sc(it);
-    double *X = lds;  // Mp x 8
+    double *X = lds;  // 8 columns of Mp: X[c * Mp + row]
     const bool resist = J.mode != 0;  // resistance problem: lambda = M_pp^-1 s only
     const int64_t b3 = 3 * it.w.blob0, u6 = resist ? 0 : J.nb3 + 6 * (int64_t)it.w.body;
     // with a shared reference-shape factor, the right-hand sides are taken
@@ -714,7 +722,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     const gmem<const double> Rot = as_global(it.w.rot);
     if (it.w.rot) {
         for (int e = tid; e < Mp * R; e += 256) {
-            const int row = e / R, c = e % R;
+            const int row = e % Mp, c = e / Mp;
             double v = 0.0;
             if (row < m && c < nr) {
                 const gmem<const double> x = as_global(J.in) + (int64_t)(r0 + c) * J.ld + b3 + row - row % 3;
@@ -725,7 +733,7 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         }
     } else {
         for (int e = tid; e < Mp * R; e += 256) {
-            const int row = e / R, c = e % R;
+            const int row = e % Mp, c = e / Mp;
             X[e] = (row < m && c < nr) ? as_global(J.in)[(int64_t)(r0 + c) * J.ld + b3 + row] : 0.0;
         }
     }
@@ -736,11 +744,11 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         // for k = 0..5, then the QP partials are added in order
         double *part = Dj;  // [QP][R][6]
         if (tid < QP * R) {
-            const int c = tid % R, qp = tid / R;
+            const int c = tid / QP, qp = tid % QP;
             double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
             for (int l = qp; l < Mp; l += QP) {
-                const double x = X[l * R + c];
+                const double x = X[c * Mp + l];
 #pragma unroll
                 for (int k = 0; k < 6; ++k) acc[k] += as_global(Y)[l * 6 + k] * x;
             }
@@ -786,10 +794,10 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
             for (int k = 0; k < 6; ++k) yk[k] = as_global(Y)[row * 6 + k];
 #pragma unroll
             for (int c = 0; c < R; ++c) {
-                double acc = X[row * R + c];
+                double acc = X[c * Mp + row];
 #pragma unroll
                 for (int k = 0; k < 6; ++k) acc += yk[k] * g[c][k];
-                X[row * R + c] = acc;
+                X[c * Mp + row] = acc;
             }
         }
         __syncthreads();
@@ -798,11 +806,12 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
     if (it.w.rot) {
         // backward_rl ends with a barrier, so all of X is final here
         for (int e = tid; e < m * R; e += 256) {
-            const int row = e / R, c = e % R;
+            const int row = e % m, c = e / m;
             if (c < nr) {
                 const int b = row - row % 3, k = row % 3;
+                const double *xc = X + c * Mp;
                 as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] =
-                    Rot[3 * k] * X[b * R + c] + Rot[3 * k + 1] * X[(b + 1) * R + c] + Rot[3 * k + 2] * X[(b + 2) * R + c];
+                    Rot[3 * k] * xc[b] + Rot[3 * k + 1] * xc[b + 1] + Rot[3 * k + 2] * xc[b + 2];
             }
         }
         if (tid < R * 6 && !resist) {
@@ -815,8 +824,8 @@ __global__ __launch_bounds__(256) void apply_large_kernel(const PrecondApplyJob 
         return;
     }
     for (int e = tid; e < m * R; e += 256) {
-        const int row = e / R, c = e % R;
-        if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] = X[e];
+        const int row = e % m, c = e / m;
+        if (c < nr) as_global(J.out)[(int64_t)(r0 + c) * J.ld + b3 + row] = X[c * Mp + row];
     }
     if (tid < R * 6 && !resist) {
         const int c = tid / 6, k = tid % 6;
