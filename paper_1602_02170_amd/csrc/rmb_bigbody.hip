@@ -610,12 +610,24 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
 // Mp per right-hand side (X[c * Mp + row]: threads updating consecutive rows
 // touch consecutive words).  Dj: the NB x NB diagonal-block inverse staged
 // with leading dimension NB + 1 (read by rows and by columns without bank
-// conflicts), T: NB x R.
+// conflicts); T: the block's solved unknowns x_j, row-major NB x R, read by
+// the other rows' updates as broadcasts.  Per block: the next block's
+// inverse and the first row's operands of this block's update are loaded
+// before they are needed (neither depends on x_j).
 // ---------------------------------------------------------------------------
 
 template <int NB>
-__device__ __forceinline__ void stage_dinv(const gmem<const double> Dinv, int j, double *Dj) {
-    for (int e = threadIdx.x; e < NB * NB; e += 256) Dj[(e / NB) * (NB + 1) + e % NB] = Dinv[(int64_t)j * NB + e];
+__device__ __forceinline__ void load_dinv(const gmem<const double> Dinv, int j, double (&d)[NB * NB / 256]) {
+#pragma unroll
+    for (int i = 0; i < NB * NB / 256; ++i) d[i] = Dinv[(int64_t)j * NB + threadIdx.x + 256 * i];
+}
+template <int NB>
+__device__ __forceinline__ void put_dinv(const double (&d)[NB * NB / 256], double *Dj) {
+#pragma unroll
+    for (int i = 0; i < NB * NB / 256; ++i) {
+        const int e = threadIdx.x + 256 * i;
+        Dj[(e / NB) * (NB + 1) + e % NB] = d[i];
+    }
 }
 
 // X <- L^-1 X
@@ -623,32 +635,46 @@ template <int NB, int R>
 __device__ void forward_rl(const gmem<const double> L, const gmem<const double> Dinv, int Mp, double *X,
                            double *Dj, double *T) {
     const int tid = threadIdx.x;
+    double dn[NB * NB / 256];
+    load_dinv<NB>(Dinv, 0, dn);
     for (int j = 0; j < Mp; j += NB) {
-        stage_dinv<NB>(Dinv, j, Dj);
+        put_dinv<NB>(dn, Dj);
+        // the first row's operands of the update below
+        const int rf = j + NB + tid;
+        double lf[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) lf[l] = rf < Mp ? L[(int64_t)(j + l) * Mp + rf] : 0.0;
         __syncthreads();
         // x_j = Dinv_j b_j
         for (int o = tid; o < NB * R; o += 256) {
             const int r = o % NB, c = o / NB;
             double acc = 0.0;
             for (int l = 0; l <= r; ++l) acc += Dj[l * (NB + 1) + r] * X[c * Mp + j + l];
-            T[o] = acc;
+            T[r * R + c] = acc;
         }
         __syncthreads();
-        for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[o];
-        __syncthreads();
-        // later rows: b[r] -= L[r, j:j+NB] x_j
-        for (int r = j + NB + tid; r < Mp; r += 256) {
+        for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[(o % NB) * R + o / NB];
+        if (j + NB < Mp) load_dinv<NB>(Dinv, j + NB, dn);
+        // later rows: b[r] -= L[r, j:j+NB] x_j (rows disjoint from the copy above)
+        auto update = [&](int r, const double (&lv)[NB]) {
+            // x_j is re-read from LDS for every row (held in registers across
+            // rows it would take 2 NB R of them)
+            asm volatile("" ::: "memory");
             double acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0.0;
 #pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                const double lv = L[(int64_t)(j + l) * Mp + r];
+            for (int l = 0; l < NB; ++l)
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lv * X[c * Mp + j + l];
-            }
+                for (int c = 0; c < R; ++c) acc[c] += lv[l] * T[l * R + c];
 #pragma unroll
             for (int c = 0; c < R; ++c) X[c * Mp + r] -= acc[c];
+        };
+        if (rf < Mp) update(rf, lf);
+        for (int r = rf + 256; r < Mp; r += 256) {
+#pragma unroll
+            for (int l = 0; l < NB; ++l) lf[l] = L[(int64_t)(j + l) * Mp + r];
+            update(r, lf);
         }
         __syncthreads();
     }
@@ -659,33 +685,46 @@ template <int NB, int R>
 __device__ void backward_rl(const gmem<const double> L, const gmem<const double> Dinv, int Mp, double *X,
                             double *Dj, double *T) {
     const int tid = threadIdx.x;
+    double dn[NB * NB / 256];
+    load_dinv<NB>(Dinv, Mp - NB, dn);
     for (int j = Mp - NB; j >= 0; j -= NB) {
-        stage_dinv<NB>(Dinv, j, Dj);
+        put_dinv<NB>(dn, Dj);
+        // the first earlier row's operands: column tid of L, rows j .. j+NB
+        const int kf = tid;
+        double lf[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) lf[l] = kf < j ? L[(int64_t)kf * Mp + j + l] : 0.0;
         __syncthreads();
         // x_j = Dinv_j^T b_j: x[r] = sum_{l >= r} Dinv_j[l][r] b[l]
         for (int o = tid; o < NB * R; o += 256) {
             const int r = o % NB, c = o / NB;
             double acc = 0.0;
             for (int l = r; l < NB; ++l) acc += Dj[r * (NB + 1) + l] * X[c * Mp + j + l];
-            T[o] = acc;
+            T[r * R + c] = acc;
         }
         __syncthreads();
-        for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[o];
-        __syncthreads();
-        // earlier rows: b[k] -= sum_l L[j+l][k] x[j+l]
-        for (int k = tid; k < j; k += 256) {
+        for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[(o % NB) * R + o / NB];
+        if (j > 0) load_dinv<NB>(Dinv, j - NB, dn);
+        // earlier rows: b[k] -= sum_l L[j+l][k] x[j+l] (rows disjoint from the copy above)
+        auto update = [&](int k, const double (&lv)[NB]) {
+            // x_j is re-read from LDS for every row (held in registers across
+            // rows it would take 2 NB R of them)
+            asm volatile("" ::: "memory");
             double acc[R];
 #pragma unroll
             for (int c = 0; c < R; ++c) acc[c] = 0.0;
-            const gmem<const double> col = L + (int64_t)k * Mp + j;
 #pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                const double lv = col[l];
+            for (int l = 0; l < NB; ++l)
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lv * X[c * Mp + j + l];
-            }
+                for (int c = 0; c < R; ++c) acc[c] += lv[l] * T[l * R + c];
 #pragma unroll
             for (int c = 0; c < R; ++c) X[c * Mp + k] -= acc[c];
+        };
+        if (kf < j) update(kf, lf);
+        for (int k = kf + 256; k < j; k += 256) {
+#pragma unroll
+            for (int l = 0; l < NB; ++l) lf[l] = L[(int64_t)k * Mp + j + l];
+            update(k, lf);
         }
         __syncthreads();
     }
