@@ -680,20 +680,30 @@ __device__ void forward_rl(const gmem<const double> L, const gmem<const double> 
     }
 }
 
-// X <- L^-T X
+// X <- L^-T X.  The earlier rows' update of block j,
+//   X[k][c] -= sum_l L[j+l][k] x_j[l][c],  k < j,
+// runs on the matrix cores, 16 columns of L per tile: lane (l16, l4) holds
+// L[j + 4s + l4][k0 + l16] (four consecutive words of one column) as the A
+// operand and x_j[4s + l4][l16] (zero for l16 >= R) as the B operand; the
+// next tile's operands are loaded while the current one is multiplied.
 template <int NB, int R>
 __device__ void backward_rl(const gmem<const double> L, const gmem<const double> Dinv, int Mp, double *X,
                             double *Dj, double *T) {
-    const int tid = threadIdx.x;
+    static_assert(NB == 32 && R <= 16, "tiles of 16 columns, 8 MFMA steps of 4 rows");
+    constexpr int S = NB / 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
     double dn[NB * NB / 256];
     load_dinv<NB>(Dinv, Mp - NB, dn);
     for (int j = Mp - NB; j >= 0; j -= NB) {
         put_dinv<NB>(dn, Dj);
-        // the first earlier row's operands: column tid of L, rows j .. j+NB
-        const int kf = tid;
-        double lf[NB];
+        const int nt = j / 16;  // column tiles of the earlier rows
+        auto load_tile = [&](int t, double (&a)[S]) {
+            const int64_t k = 16 * min(t, nt - 1) + l16;  // clamped: the loads stay unconditional
 #pragma unroll
-        for (int l = 0; l < NB; ++l) lf[l] = kf < j ? L[(int64_t)kf * Mp + j + l] : 0.0;
+            for (int s = 0; s < S; ++s) a[s] = L[k * Mp + j + 4 * s + l4];
+        };
+        double a0[S], a1[S];
+        if (nt > 0) load_tile(wave, a0);  // before the block solve: it does not depend on x_j
         __syncthreads();
         // x_j = Dinv_j^T b_j: x[r] = sum_{l >= r} Dinv_j[l][r] b[l]
         for (int o = tid; o < NB * R; o += 256) {
@@ -705,26 +715,24 @@ __device__ void backward_rl(const gmem<const double> L, const gmem<const double>
         __syncthreads();
         for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[(o % NB) * R + o / NB];
         if (j > 0) load_dinv<NB>(Dinv, j - NB, dn);
-        // earlier rows: b[k] -= sum_l L[j+l][k] x[j+l] (rows disjoint from the copy above)
-        auto update = [&](int k, const double (&lv)[NB]) {
-            // x_j is re-read from LDS for every row (held in registers across
-            // rows it would take 2 NB R of them)
-            asm volatile("" ::: "memory");
-            double acc[R];
+        double bx[S];
 #pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] = 0.0;
+        for (int s = 0; s < S; ++s) bx[s] = l16 < R ? T[(4 * s + l4) * R + l16] : 0.0;
+        auto tile = [&](int t, const double (&a)[S]) {
+            dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int l = 0; l < NB; ++l)
+            for (int s = 0; s < S; ++s) acc = mfma16x16x4(a[s], bx[s], acc);
+            if (l16 < R) {
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lv[l] * T[l * R + c];
-#pragma unroll
-            for (int c = 0; c < R; ++c) X[c * Mp + k] -= acc[c];
+                for (int r = 0; r < 4; ++r) X[l16 * Mp + 16 * t + l4 + 4 * r] -= acc[r];
+            }
         };
-        if (kf < j) update(kf, lf);
-        for (int k = kf + 256; k < j; k += 256) {
-#pragma unroll
-            for (int l = 0; l < NB; ++l) lf[l] = L[(int64_t)k * Mp + j + l];
-            update(k, lf);
+        for (int t = wave; t < nt; t += 8) {
+            load_tile(t + 4, a1);
+            tile(t, a0);
+            if (t + 4 >= nt) break;
+            load_tile(t + 8, a0);
+            tile(t + 4, a1);
         }
         __syncthreads();
     }
