@@ -610,10 +610,9 @@ __global__ __launch_bounds__(256, 2) void chol_panel_kernel(const BigBody *__res
 // Mp per right-hand side (X[c * Mp + row]: threads updating consecutive rows
 // touch consecutive words).  Dj: the NB x NB diagonal-block inverse staged
 // with leading dimension NB + 1 (read by rows and by columns without bank
-// conflicts); T: the block's solved unknowns x_j, row-major NB x R, read by
-// the other rows' updates as broadcasts.  Per block: the next block's
-// inverse and the first row's operands of this block's update are loaded
-// before they are needed (neither depends on x_j).
+// conflicts); T: the block's solved unknowns x_j, row-major NB x R.  Per
+// block: the next block's inverse and the first tile's operands of this
+// block's update are loaded before they are needed (neither depends on x_j).
 // ---------------------------------------------------------------------------
 
 template <int NB>
@@ -630,20 +629,31 @@ __device__ __forceinline__ void put_dinv(const double (&d)[NB * NB / 256], doubl
     }
 }
 
-// X <- L^-1 X
+// X <- L^-1 X.  The later rows' update of block j,
+//   X[r][c] -= sum_l L[r][j+l] x_j[l][c],  r >= j + NB,
+// runs on the matrix cores, 16 rows per tile: lane (l16, l4) holds
+// L[r0 + l16][j + 4s + l4] (16 consecutive words of a column across the
+// lanes) as the A operand and x_j[4s + l4][l16] (zero for l16 >= R) as the B
+// operand; the next tile's operands are loaded while the current one is
+// multiplied.
 template <int NB, int R>
 __device__ void forward_rl(const gmem<const double> L, const gmem<const double> Dinv, int Mp, double *X,
                            double *Dj, double *T) {
-    const int tid = threadIdx.x;
+    static_assert(NB == 32 && R <= 16, "tiles of 16 rows, 8 MFMA steps of 4 columns");
+    constexpr int S = NB / 4;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
     double dn[NB * NB / 256];
     load_dinv<NB>(Dinv, 0, dn);
     for (int j = 0; j < Mp; j += NB) {
         put_dinv<NB>(dn, Dj);
-        // the first row's operands of the update below
-        const int rf = j + NB + tid;
-        double lf[NB];
+        const int r0 = j + NB, nt = (Mp - r0) / 16;  // row tiles below the block
+        auto load_tile = [&](int t, double (&a)[S]) {
+            const int64_t r = r0 + 16 * min(t, nt - 1) + l16;  // clamped: the loads stay unconditional
 #pragma unroll
-        for (int l = 0; l < NB; ++l) lf[l] = rf < Mp ? L[(int64_t)(j + l) * Mp + rf] : 0.0;
+            for (int s = 0; s < S; ++s) a[s] = L[(int64_t)(j + 4 * s + l4) * Mp + r];
+        };
+        double a0[S], a1[S];
+        if (nt > 0) load_tile(wave, a0);  // before the block solve: it does not depend on x_j
         __syncthreads();
         // x_j = Dinv_j b_j
         for (int o = tid; o < NB * R; o += 256) {
@@ -655,26 +665,24 @@ __device__ void forward_rl(const gmem<const double> L, const gmem<const double> 
         __syncthreads();
         for (int o = tid; o < NB * R; o += 256) X[(o / NB) * Mp + j + o % NB] = T[(o % NB) * R + o / NB];
         if (j + NB < Mp) load_dinv<NB>(Dinv, j + NB, dn);
-        // later rows: b[r] -= L[r, j:j+NB] x_j (rows disjoint from the copy above)
-        auto update = [&](int r, const double (&lv)[NB]) {
-            // x_j is re-read from LDS for every row (held in registers across
-            // rows it would take 2 NB R of them)
-            asm volatile("" ::: "memory");
-            double acc[R];
+        double bx[S];
 #pragma unroll
-            for (int c = 0; c < R; ++c) acc[c] = 0.0;
+        for (int s = 0; s < S; ++s) bx[s] = l16 < R ? T[(4 * s + l4) * R + l16] : 0.0;
+        auto tile = [&](int t, const double (&a)[S]) {
+            dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int l = 0; l < NB; ++l)
+            for (int s = 0; s < S; ++s) acc = mfma16x16x4(a[s], bx[s], acc);
+            if (l16 < R) {
 #pragma unroll
-                for (int c = 0; c < R; ++c) acc[c] += lv[l] * T[l * R + c];
-#pragma unroll
-            for (int c = 0; c < R; ++c) X[c * Mp + r] -= acc[c];
+                for (int r = 0; r < 4; ++r) X[l16 * Mp + r0 + 16 * t + l4 + 4 * r] -= acc[r];
+            }
         };
-        if (rf < Mp) update(rf, lf);
-        for (int r = rf + 256; r < Mp; r += 256) {
-#pragma unroll
-            for (int l = 0; l < NB; ++l) lf[l] = L[(int64_t)(j + l) * Mp + r];
-            update(r, lf);
+        for (int t = wave; t < nt; t += 8) {
+            load_tile(t + 4, a1);
+            tile(t, a0);
+            if (t + 4 >= nt) break;
+            load_tile(t + 8, a0);
+            tile(t + 4, a1);
         }
         __syncthreads();
     }
