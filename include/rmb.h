@@ -107,7 +107,13 @@ typedef struct {
 /* Creates a context on HIP device `device`.  `hbm_budget_bytes` caps the
  * device memory the library may hold for workspaces, factors and Krylov
  * bases (0 = 16 GiB).  Memory is reserved lazily.  *out receives the
- * handle.  Errors: RMB_EINVAL (null out, bad device), RMB_EDEVICE. */
+ * handle.  Errors: RMB_EINVAL (null out, bad device), RMB_EDEVICE.
+ * The environment variable RMB_SYM_BAND_BYTES (a positive byte count, read
+ * here) sets the budget of one band of the symmetric product's tile partials
+ * (default 4 GiB, counted at FP64 size): the product evaluates its tile
+ * triangle in bands of tile rows that fit it, so a smaller value bounds the
+ * workspace of very large systems (and makes small systems take several
+ * bands).  The value changes the order of the FP64 sums only. */
 rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out);
 
 /* Releases every device allocation the context holds.  Preconditioners and
@@ -143,7 +149,7 @@ rmb_status rmb_ctx_kernel_time(rmb_ctx ctx, int32_t kernel, double *total_ms, in
 rmb_status rmb_pair_plan(int64_t nb, int32_t *symmetric, int32_t *block);
 
 /* Tile shapes of the large-body factorisation (bodies whose 3n x 3n block
- * is too large for the LDS path; padded_dim = 3n rounded up to 32).  Which
+ * is too large for the LDS path; padded_dim = 3n + 6 rounded up to 64).  Which
  * shape a batch uses:
  *   - the shape forced with rmb_ctx_set_tile_shape for its padded size;
  *   - else, for batches of fewer than 64 bodies, shape 0 (small batches are
@@ -165,7 +171,7 @@ rmb_status rmb_tile_shape_info(int32_t shape, int32_t *panel, int32_t *row_tiles
 
 /* Forces `shape` for blocks of padded size `padded_dim` on this context
  * (shape -1 returns the choice to the rules above).  RMB_EINVAL for a
- * padded_dim that is not a positive multiple of 32 or an unknown shape. */
+ * padded_dim that is not a positive multiple of 64 or an unknown shape. */
 rmb_status rmb_ctx_set_tile_shape(rmb_ctx ctx, int32_t padded_dim, int32_t shape);
 
 /* Panel width of the tuned shape for padded size `padded_dim` on this
@@ -175,7 +181,7 @@ rmb_status rmb_ctx_tuned_panel(rmb_ctx ctx, int32_t padded_dim, int32_t *panel_w
 
 /* One timing of the large-body factorisation autotuner. */
 typedef struct rmb_tune_record {
-    int32_t padded_dim; /* Mp: block size rounded up to 32 */
+    int32_t padded_dim; /* Mp: 3n + 6 rounded up to 64 */
     int32_t panel;      /* columns per Cholesky panel */
     int32_t row_tiles;  /* 16-row tiles per wave per pass of the panel update */
     int32_t chunk;      /* columns of L whose matrix-core operands are loaded ahead */

@@ -1,5 +1,6 @@
 // Context management, validation and the blob mobility product entry points.
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 
@@ -260,6 +261,11 @@ rmb_status rmb_ctx_create(int device, size_t hbm_budget_bytes, rmb_ctx *out) {
     c->device = device;
     c->arena = new Arena(hbm_budget_bytes ? hbm_budget_bytes : (size_t(16) << 30));
     c->noalloc_work = noalloc_work_address(device);
+    if (const char *e = getenv("RMB_SYM_BAND_BYTES"); e && *e) {
+        char *end = nullptr;
+        const unsigned long long v = strtoull(e, &end, 10);
+        if (end && *end == 0 && v > 0) c->sym_band_bytes = (size_t)v;
+    }
     load_tune_cache(c);
     *out = c;
     return RMB_OK;
@@ -408,9 +414,9 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
     RMB_TRY(enter(ctx, s));
     RMB_TRY(check_product_args(ctx, sys, precision, lambda, vel));
     char *base = nullptr;
-    RMB_TRY(ctx_scratch(ctx, product_work_bytes(sys->n_blobs, precision, kSymBandBytes), (void **)&base));
+    RMB_TRY(ctx_scratch(ctx, product_work_bytes(sys->n_blobs, precision, ctx->sym_band_bytes), (void **)&base));
     RMB_TRY(check_positions(ctx, sys, (int *)base, s));
-    return product_enqueue(ctx, sys, precision, lambda, vel, base, kSymBandBytes, true, s);
+    return product_enqueue(ctx, sys, precision, lambda, vel, base, ctx->sym_band_bytes, true, s);
 }
 
 __global__ void zero_flag_kernel(int *flag) { *as_global(flag) = 0; }

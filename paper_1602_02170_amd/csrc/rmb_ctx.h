@@ -45,6 +45,9 @@ struct rmb_ctx_s {
     // this device's copy of the no-allocation entry point's static workspace
     // (device address from hipGetSymbolAddress; null if it could not be had)
     void *noalloc_work = nullptr;
+    // budget of one band of the symmetric product's tile partials
+    // (RMB_SYM_BAND_BYTES at creation)
+    size_t sym_band_bytes = rmb::kSymBandBytes;
 };
 
 namespace rmb {

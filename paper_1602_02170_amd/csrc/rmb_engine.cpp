@@ -271,6 +271,7 @@ struct Job {
     bool sym = false;
     int32_t symB = 0, symT = 0;
     std::vector<SymBand> bands;  // symmetric product: bands of tile rows
+    size_t band_bytes = kSymBandBytes;  // their partials' budget (the context's)
     BodyWork *items_d = nullptr;
     double *x = nullptr, *b = nullptr, *w = nullptr, *z = nullptr, *V = nullptr;
     double *P1 = nullptr, *P2 = nullptr, *P3 = nullptr;
@@ -296,7 +297,7 @@ struct Job {
 static size_t job_bytes(Job &J) {
     const int64_t nb = J.nb, N = J.N, n = J.n;
     size_t t = 0;
-    const size_t part = J.sym ? sym_band_partial_doubles(nb, kSymBandBytes) * 8 : (size_t)J.pj.n_split * nb * 24;
+    const size_t part = J.sym ? sym_band_partial_doubles(nb, J.band_bytes) * 8 : (size_t)J.pj.n_split * nb * 24;
     t += al((N + 1) * 8) + al(nb * 4) + al(J.sym ? 0 : nb * sizeof(SrcF64)) + al(part) + al(nb * 24);
     t += 4 * al(n * 8) + al((size_t)(J.m + 1) * J.ldv * 8);
     t += 2 * al((size_t)(J.m + 1) * J.nseg * 8) + al(J.nseg * 8) + al(256 * 8);
@@ -315,7 +316,7 @@ static void job_carve(Job &J) {
     J.off_d = (int64_t *)take((N + 1) * 8);
     J.blob_body = (int32_t *)take(nb * 4);
     J.src = J.sym ? nullptr : take(nb * sizeof(SrcF64));  // packed sources: one-sided kernel only
-    J.partial = (double *)take(J.sym ? sym_band_partial_doubles(nb, kSymBandBytes) * 8 : (size_t)J.pj.n_split * nb * 24);
+    J.partial = (double *)take(J.sym ? sym_band_partial_doubles(nb, J.band_bytes) * 8 : (size_t)J.pj.n_split * nb * 24);
     J.vel = (double *)take(nb * 24);
     J.x = (double *)take(n * 8);
     J.b = (double *)take(n * 8);
@@ -471,7 +472,8 @@ struct Engine {
         J->sym = use_sym(J->nb);
         if (J->sym) {
             sym_plan(J->nb, &J->symB, &J->symT);
-            J->bands = sym_bands(J->nb, kSymBandBytes);
+            J->band_bytes = ctx->sym_band_bytes;
+            J->bands = sym_bands(J->nb, J->band_bytes);
         }
         J->bytes = job_bytes(*J);
         if (J->bytes > ctx->arena->budget())
@@ -782,7 +784,7 @@ struct Engine {
                 y.tpos = J->sys.pos;
                 y.lam = xin;
                 y.vpart = J->partial;
-                y.upart = J->partial + sym_band_partial_doubles(J->nb, kSymBandBytes) / 2;
+                y.upart = J->partial + sym_band_partial_doubles(J->nb, J->band_bytes) / 2;
                 y.vel = J->vel;
                 y.acc = J->vel;  // unused by the product otherwise (the reduction writes the saddle rows)
                 y.nb = J->nb;

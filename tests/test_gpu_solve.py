@@ -123,6 +123,42 @@ def test_full_boomerang_suspension_velocities(env):
         assert _rel(U, Uo) <= 1e-8
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_band_product_and_solve(env, prec, monkeypatch):
+    """The symmetric product in many bands of tile rows (the path of systems
+    above about 210,000 blobs, forced here on 1,200 blobs by a 64 KiB band
+    budget: 19 tile rows in about a dozen bands) against the one-band
+    product and solve of the default context, and the solve against the
+    oracle."""
+    rmb, torch, ctx, O = env
+    s = small_wall()
+    monkeypatch.setenv("RMB_SYM_BAND_BYTES", str(64 << 10))
+    cb = rmb.Context(0)
+    try:
+        print(f"[gpu] multi-band 80 boomerangs {prec}", flush=True)
+        sysd = rmb.System.from_suspension(s)
+        lam = _dev(torch, np.random.default_rng(61).standard_normal((s.n_blobs, 3)))
+        v1 = rmb.mobility_matvec(ctx, sysd, lam, prec).cpu().numpy()
+        vb = rmb.mobility_matvec(cb, sysd, lam, prec).cpu().numpy()
+        ref = O.matvec(s.pos, lam.cpu().numpy(), s.a, s.eta, s.wall)
+        print(f"    product: bands vs one band {parity.rel2(vb, v1):.2e}, vs oracle {parity.err(vb, ref):.2e}",
+              flush=True)
+        assert parity.err(vb, v1) <= 1e-14  # only the order of the FP64 sums over bands differs
+        assert parity.err(vb, ref) <= (1e-12 if prec == "fp64" else 1e-5)
+        Ud, _ = O.dense_solve(s, s.FT)
+        U1, _, i1 = _solve(env, s, tol=1e-11, precision=prec)
+        Ub, lb, ib = rmb.solve_mobility(cb, sysd, _dev(torch, s.FT), tol=1e-11, precision=prec)
+        Ub, lb = Ub.cpu().numpy(), lb.cpu().numpy()
+        res = O.relative_residual(s, s.FT, None, Ub, lb)
+        print(f"    solve: iterations {ib['iterations']} (one band {i1['iterations']}), oracle residual {res:.2e}, "
+              f"U err {_rel(Ub, Ud):.2e}, vs one band {_rel(Ub, U1):.2e}", flush=True)
+        assert ib["status"] == 0 and res <= 1.05e-11
+        assert _rel(Ub, Ud) <= 1e-8
+        assert abs(ib["iterations"] - i1["iterations"]) <= 1
+    finally:
+        cb.close()
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "relaxed"])
 def test_velocity_error_control(env, prec):
     """80 wall boomerangs: with u_tol = 1e-8 the velocities match the dense
