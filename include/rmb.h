@@ -359,8 +359,10 @@ typedef struct {
                             tol_internal (half the bound absorbs the error of the
                             estimate itself).  A solve whose first cycle already meets
                             `tol` runs one short verification cycle (residual reduced
-                            tenfold) to measure gamma.  RMB_EINVAL for resistance
-                            solves. */
+                            tenfold) to measure gamma.  A gamma measured by a cycle
+                            that reduced the residual less than 1000-fold (such as
+                            that one) is trusted less: the target is then
+                            u_tol / (4 gamma).  RMB_EINVAL for resistance solves. */
 } rmb_solve_opts;
 
 typedef struct {
@@ -373,7 +375,8 @@ typedef struct {
     double rel_residual;   /* final ||b - A x|| / ||b|| with the FP64 operator */
     double seconds;        /* host wall time from admission to completion */
     double tol_internal;   /* residual target the solve ended with: tol, or
-                              min(tol, u_tol / (2 gamma)) under velocity-error control */
+                              min(tol, u_tol / (2 gamma)) (u_tol / (4 gamma) after a
+                              short cycle) under velocity-error control */
     double u_err_est;      /* estimated ||U - U_exact|| / ||U_exact|| of the result
                               (gamma * rel_residual), or -1 when u_tol is off or no
                               refinement cycle has measured gamma */

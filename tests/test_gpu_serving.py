@@ -123,3 +123,42 @@ def test_staging_is_reserved_when_the_budget_is_full(env, oracle_mod):
     srv.close()
     ctx.close()
     big.close()
+
+
+def test_velocity_bound_in_the_mix(env, oracle_mod):
+    """Requests with the velocity-error bound (u_tol = 1e-8) in all three
+    precisions, served together: each result equals the same request solved
+    alone, bit for bit, and the small ones' velocities match the oracle's
+    dense solution to 1e-8."""
+    rmb, torch = env
+    sizes = (12, 30, 8, 45, 20, 16)
+    precs = ("fp32", "relaxed", "fp64", "fp32", "relaxed", "fp64")
+    reqs, systems, FTs = _reqs(rmb, torch, sizes)
+    big = rmb.Context(0)
+    alone = [rmb.solve_mobility(big, systems[i], FTs[i], tol=1e-8, u_tol=1e-8, precision=precs[i])
+             for i in range(len(sizes))]
+    torch.cuda.synchronize()
+    ctx = rmb.Context(0)
+    srv = rmb.Server(ctx, max_active=64)
+    for i in range(len(sizes)):
+        srv.submit(i, systems[i], FTs[i], tol=1e-8, u_tol=1e-8, precision=precs[i])
+    got, steps = {}, 0
+    while len(got) < len(sizes):
+        srv.step()
+        for tag, U, lam, info in srv.poll():
+            got[tag] = (U, lam, info)
+        steps += 1
+        assert steps < 10000
+    for i, (Ua, la, ia) in enumerate(alone):
+        Um, lm, im = got[i]
+        assert im["status"] == 0 and im["u_err_est"] <= 1e-8
+        assert torch.equal(Ua, Um) and torch.equal(la, lm)
+        if reqs[i].n_blobs <= 600:
+            Ud, _ = oracle_mod.dense_solve(reqs[i], reqs[i].FT)
+            err = np.linalg.norm(Um.cpu().numpy() - Ud) / np.linalg.norm(Ud)
+            print(f"[gpu] request {i} ({precs[i]}, {reqs[i].n_blobs} blobs): U err {err:.2e}, "
+                  f"estimate {im['u_err_est']:.2e}", flush=True)
+            assert err <= 1e-8
+    srv.close()
+    ctx.close()
+    big.close()
