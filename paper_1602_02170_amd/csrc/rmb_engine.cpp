@@ -362,10 +362,14 @@ struct Engine {
     std::deque<Job *> queue;
     std::vector<Job *> active;
     std::deque<Job *> done;
-    // mailbox: per slot, [flag word][hcol: restart + 2 doubles]
+    // mailbox: per slot, [flag word][hcol: restart + 2 doubles], in pinned
+    // host memory, one per tick buffer: the kernels of the tick using buffer
+    // `par` write mbox_hp[par] directly, and the host reads it once the
+    // tick's event has completed (no copy on the stream)
     static constexpr int kSlot = 260;
-    double *mbox_d = nullptr, *mbox_h = nullptr;  // mbox_h: the host copy being read
-    double *mbox_hp[2] = {nullptr, nullptr};     // host copies, one per tick buffer
+    double *mbox_h = nullptr;                 // the host buffer being read
+    double *mbox_hp[2] = {nullptr, nullptr};  // one per tick buffer
+    int cur = 0;                              // buffer of the tick being enqueued
     size_t mbox_hbytes[2] = {0, 0}, stage_hbytes[2] = {0, 0};  // sizes of the leased host buffers
     hipEvent_t tick_ev[2] = {nullptr, nullptr};  // end of the tick using buffer 0 / 1
     std::vector<int> free_slots;
@@ -389,7 +393,6 @@ struct Engine {
         for (Job *j : active) release(j), delete j;
         for (Job *j : queue) delete j;
         for (Job *j : done) delete j;
-        if (mbox_d) ctx->arena->free(mbox_d);
         for (int b = 0; b < 2; ++b) {
             pinned_give(ctx, mbox_hp[b], mbox_hbytes[b]);
             pinned_give(ctx, stage_hp[b], stage_hbytes[b]);
@@ -399,8 +402,6 @@ struct Engine {
     }
 
     rmb_status init() {
-        mbox_d = (double *)ctx->arena->alloc((size_t)max_active * kSlot * 8);
-        if (!mbox_d) return fail(ctx, RMB_ENOMEM, "server mailbox does not fit the budget");
         for (int b = 0; b < 2; ++b) {
             mbox_hp[b] = (double *)pinned_lease(ctx, (size_t)max_active * kSlot * 8, &mbox_hbytes[b]);
             if (!mbox_hp[b]) return fail(ctx, RMB_EDEVICE, "pinned host mailbox allocation failed");
@@ -411,9 +412,9 @@ struct Engine {
         return RMB_OK;
     }
 
-    int *flag_d(Job *j) { return (int *)(mbox_d + (size_t)j->slot * kSlot); }
+    int *flag_d(Job *j) { return (int *)(mbox_hp[cur] + (size_t)j->slot * kSlot); }
     int flag_h(Job *j) { return *(int *)(mbox_h + (size_t)j->slot * kSlot); }
-    double *hcol_d(Job *j) { return mbox_d + (size_t)j->slot * kSlot + 1; }
+    double *hcol_d(Job *j) { return mbox_hp[cur] + (size_t)j->slot * kSlot + 1; }
     double *hcol_h(Job *j) { return mbox_h + (size_t)j->slot * kSlot + 1; }
 
     void release(Job *j) {
@@ -683,12 +684,13 @@ struct Engine {
     }
 
     // Enqueues one tick for the given jobs: descriptor tables (through host
-    // staging buffer `par`), every launch, and the copy of the mailbox into
-    // host buffer `par`, followed by tick_ev[par].  koff = 1 builds the
+    // staging buffer `par`) and every launch, whose mailbox writes go to host
+    // buffer `par`, followed by tick_ev[par].  koff = 1 builds the
     // Arnoldi jobs' step for index k + 1 (a speculative step; its products
     // are counted apart until it is accepted).
     rmb_status launch(std::vector<Job *> &setup, std::vector<Job *> &finish, std::vector<Job *> &iter, int par,
                       int koff) {
+        cur = par;
         st.reset();
 
 
@@ -938,8 +940,6 @@ struct Engine {
         auto D = [&](size_t o) { return (void *)(stage_d + o); };
 
         // --- launches -------------------------------------------------------
-        int max_slot = 0;
-        for (Job *J : active) max_slot = std::max(max_slot, J->slot + 1);
         for (size_t i = 0; i < setup.size(); ++i) {
             Job *J = setup[i];
             RMB_HIP(ctx, hipMemsetAsync(flag_d(J), 0, sizeof(int), s));
@@ -1002,7 +1002,6 @@ struct Engine {
             RMB_HIP(ctx, launch_saddle((const SaddleJob *)D(o_sd), (int32_t)sd.size(), wg_sd_blob, wg_sd_body, s));
         if (!orth.empty())
             RMB_HIP(ctx, launch_orthogonalise((const KrylovJob *)D(o_orth), (int32_t)orth.size(), wg_orth, s));
-        RMB_HIP(ctx, hipMemcpyAsync(mbox_hp[par], mbox_d, (size_t)max_slot * kSlot * 8, hipMemcpyDeviceToHost, s));
         RMB_HIP(ctx, hipEventRecord(tick_ev[par], s));
         return RMB_OK;
     }
