@@ -565,8 +565,8 @@ def main():
     line = {"metric": METRIC, "value": value, "unit": "blob-pair interactions/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None,
-            "dtype": "f32 pairs (f32 sums over each tile of 64 sources at this size; 128-256 for larger systems), "
-                     "f64 accumulation across tiles, f64 residual/refinement",
+            "dtype": "f32 pairs, f32 sums over each group of 64 sources, f64 accumulation across groups and "
+                     "tiles, f64 residual/refinement",
             "data": "synthetic (seeded boomerang suspension; no dataset)",
             "config": {"workload": "wall RPY mobility solve, 1000 x 15-blob boomerangs (15,000 blobs), "
                                    "block-diagonal preconditioned GMRES, FP32 pairs + FP64 refinement to "

@@ -70,9 +70,10 @@ enum { RMB_GEOM_FREE = 0, RMB_GEOM_WALL = 1 };
  *                       two-float difference of the symmetric product),
  *                       pair blocks and products in FP32, sums of each
  *                       target's velocity in FP32 over blocks of 64 sources
- *                       and FP64 across blocks (the symmetric product keeps
- *                       each tile's sum, over 64 to 512 sources, as an FP32
- *                       value before the FP64 sum over tiles). */
+ *                       and FP64 across blocks (the symmetric product
+ *                       stores each tile's 64-source sums as FP32 values
+ *                       when its tiles hold 64 blobs, and the FP64 sum over
+ *                       a tile's groups of 64 for larger tiles). */
 enum { RMB_PREC_FP64 = 0, RMB_PREC_FP32_PAIRS = 1, RMB_PREC_RELAXED = 2 /* solves only, see rmb_solve_opts */ };
 
 typedef struct rmb_ctx_s *rmb_ctx;

@@ -97,7 +97,7 @@ hipError_t launch_pack_sub_sources(int precision, const double *pos, const doubl
 struct SymJob {
     const double *tpos;  // [nb][3] positions
     const double *lam;   // [nb][3] operand (the target's own force for M^T lambda)
-    double *vpart;       // [band tiles][3][B] target-side sums (FP32 pairs: floats at the same base)
+    double *vpart;       // [band tiles][3][B] target-side sums (FP32 pairs with B = 64: floats at the same base)
     double *upart;       // [band tiles][3][B] source-side sums (likewise)
     double *vel;         // [nb][3] result, prefactor applied (unused with epi)
     double *acc;         // [nb][3] FP64 sums of the bands so far (several bands only; may be vel)

@@ -25,6 +25,7 @@
 // tiles' contributions in a fixed order (bitwise reproducible, independent of
 // what shares the launch).
 #include <cmath>
+#include <type_traits>
 
 #include "rmb_body.h"
 
@@ -391,11 +392,13 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
     const R a = (R)J.a, four_a2 = (R)J.four_a2, kiso = (R)J.k_near_iso, krr = (R)J.k_near_rr;
     const R tiny = sizeof(R) == 4 ? (R)1e-30f : (R)1e-280;
-    // tile sums are stored in the pair precision: with FP32 pairs each one is
-    // an FP32 sum over 64 sources (exact as a float for B = 64; for larger B
-    // the FP64 sum over the tile's groups, rounded once)
-    const gmem<R> vout = as_global((R *)J.vpart + slot * (int64_t)B * 3);
-    const gmem<R> uout = as_global((R *)J.upart + slot * (int64_t)B * 3);
+    // tile sums: with FP32 pairs and B = 64 each one is an FP32 sum over 64
+    // sources, stored exactly as a float; larger tiles add their groups of 64
+    // in FP64 and store that sum as it is, so the FP32 part never spans more
+    // than 64 sources
+    using S = typename std::conditional<(B > 64), double, R>::type;
+    const gmem<S> vout = as_global((S *)J.vpart + slot * (int64_t)B * 3);
+    const gmem<S> uout = as_global((S *)J.upart + slot * (int64_t)B * 3);
 
     double u64[G][3];
 #pragma unroll
@@ -470,9 +473,9 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         }
         if (active) {
             const int e = sub * 64 + lane;
-            vout[e] = (R)vx;
-            vout[B + e] = (R)vy;
-            vout[2 * B + e] = (R)vz;
+            vout[e] = (S)vx;
+            vout[B + e] = (S)vy;
+            vout[2 * B + e] = (S)vz;
         }
     }
     if (!diag) {
@@ -481,9 +484,9 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
             const int64_t j = s0 + 64 * g + lane;
             if (j < s1) {
                 const int e = 64 * g + lane;
-                uout[e] = (R)u64[g][0];
-                uout[B + e] = (R)u64[g][1];
-                uout[2 * B + e] = (R)u64[g][2];
+                uout[e] = (S)u64[g][0];
+                uout[B + e] = (S)u64[g][1];
+                uout[2 * B + e] = (S)u64[g][2];
             }
         }
     }
@@ -628,7 +631,7 @@ __global__ __launch_bounds__(1024) void sym_reduce_kernel(const SymJob *__restri
         auto slot = [&](int64_t i, int64_t j) { return i * T - i * (i - 1) / 2 + (j - i) - J.t0; };
         const int32_t nv = K < I1 ? T - K : 0;            // row tiles (K, K + c)
         const int32_t n = nv + (K < I1 ? K : I1) - I0;    // then column tiles (I0 + c - nv, K)
-        if (J.f32) {
+        if (J.f32 && B == 64) {  // float partials (see the tile kernel)
 #pragma unroll 4
             for (int32_t c = q; c < n; c += kRedWaves) {
                 const gmem<const float> p = as_global(c < nv ? (const float *)J.vpart + slot(K, K + c) * B * 3 + kk
