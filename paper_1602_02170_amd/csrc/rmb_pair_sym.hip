@@ -181,6 +181,15 @@ struct VOp<double> {
 // image coefficients are c2 / L^2, c3 / L and c4 / L; and since R = r + 2 z_j z,
 // the e-term shares the direction r with the RPY term in x and y, the z row
 // taking the rest as g 2 z_j.
+//
+// Lengths are in units of the blob radius: the caller passes r / a and z_j / a
+// (positions are scaled by 1/a in FP64 before they are rounded to the pair
+// precision).  The RPY and image coefficients depend only on the ratios
+// a / r, a / L and z_j / L, so the near-field constants become the pure
+// numbers 9/32 and 3/32, the contact test is r^2 <= 4, a / L is the inverse
+// square root itself, and the coefficients of the (r . f) r and R-terms come
+// out as Bv a^2, c2 a^2 / L^2 and c_k a / L, which is what the scaled vectors
+// need: the contractions return M_ij f unchanged.
 template <typename R, bool WALL>
 struct PairCoef {
     using P = VOp<R>;
@@ -190,51 +199,51 @@ struct PairCoef {
 
     // NEAR_POSSIBLE = false: the caller knows r > 2a (far branch only).
     template <bool NEAR_POSSIBLE = true>
-    __device__ __forceinline__ void eval(R rx, R ry, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
+    __device__ __forceinline__ void eval(R rx, R ry, R rz, R zj, R tiny) {
         const R rxy2 = P::fma(ry, ry, P::mul(rx, rx));
         const R d2 = P::fma(rz, rz, rxy2);
-        eval_d2<NEAR_POSSIBLE>(rxy2, d2, rz, zj, a, four_a2, kiso, krr, tiny);
+        eval_d2<NEAR_POSSIBLE>(rxy2, d2, rz, zj, zj + zj, tiny);
     }
+    // zj2 = 2 z_j, passed in (the symmetric product stages it with the source)
     template <bool NEAR_POSSIBLE>
-    __device__ __forceinline__ void eval_d2(R rxy2, R d2, R rz, R zj, R a, R four_a2, R kiso, R krr, R tiny) {
+    __device__ __forceinline__ void eval_d2(R rxy2, R d2, R rz, R zj, R zj2_, R tiny) {
         // r = 0 (a blob with itself) only on the near branch; the far one has
-        // d2 > 4 a^2.  The guard is added in a form the compiler keeps inside
+        // r^2 > 4.  The guard is added in a form the compiler keeps inside
         // the near branch (hoisted, it would cost the far steps too).
-        const R inv_d = rsqrt_r(NEAR_POSSIBLE ? add_in_place(d2, tiny) : d2);
-        const R t = P::mul(a, inv_d);
+        const R t = rsqrt_r(NEAR_POSSIBLE ? add_in_place(d2, tiny) : d2);  // a / r
         const R t2 = P::mul(t, t);
         const R iso_far = P::mul(t, (R)0.5 * t2 + (R)0.75);
-        const R rr_far = P::mul(P::mul(t, (R)-1.5 * t2 + (R)0.75), P::mul(inv_d, inv_d));
+        const R rr_far = P::mul(P::mul(t, t2), (R)-1.5 * t2 + (R)0.75);
         R ciso = iso_far;
         crr = rr_far;
         if (NEAR_POSSIBLE) {
-            const R d = P::mul(d2, inv_d);
-            const R iso_near = P::one_minus(kiso, d);
-            const R rr_near = P::mul(krr, inv_d);
-            const bool near = d2 <= four_a2;
+            const R d = P::mul(d2, t);  // r / a
+            const R iso_near = (R)1 - (R)(9.0 / 32.0) * d;
+            const R rr_near = (R)(3.0 / 32.0) * t;
+            const bool near = d2 <= (R)4;
             ciso = near ? iso_near : iso_far;
             crr = near ? rr_near : rr_far;
         }
         if (WALL) {
-            zj2 = zj + zj;
+            zj2 = zj2_;
             Rz = zj2 + rz;
             const R L2 = P::fma(Rz, Rz, rxy2);
-            const R invL = rsqrt_r(L2);
-            const R xw = P::mul(a, invL), hh = P::mul(zj, invL), ez = P::mul(Rz, invL);
+            const R xw = rsqrt_r(L2);  // a / L
+            const R hh = P::mul(zj, xw), ez = P::mul(Rz, xw);
             const R xw2 = P::mul(xw, xw), xw4 = P::mul(xw2, xw2), ez2 = P::mul(ez, ez);
             const R hh2 = P::mul(hh, hh), ezh = P::mul(ez, hh);
             const R T = P::sub(hh2, ezh);
-            const R xwL = P::mul(xw, invL), xwLL = P::mul(xwL, invL);
+            const R xw3 = P::mul(xw, xw2);
             // c1 and c2 carry xi / 4, folded into their polynomials
             iso = P::fma(xw, P::fma(xw4, (R)-2.5 * ez2 + (R)0.5, P::fma(xw2, (R)1.5 * ez2 - (R)0.5, (R)1.5 * T - (R)0.75)),
                          ciso);
-            c2L = P::mul(xwLL,
+            c2L = P::mul(xw3,
                          P::fma(xw4, (R)17.5 * ez2 - (R)2.5, P::fma(xw2, (R)-7.5 * ez2 + (R)1.5, (R)-4.5 * T - (R)0.75)));
             const R hh15 = (R)1.5 * hh;
             const R m3 = P::mul(hh15, (R)-6 * ez2 + ((R)6 * ezh + (R)1));
             const R e3 = P::fma(xw4, (R)-35 * ez2 + (R)10, P::mul(xw2, (R)15 * ez2 - (R)3));
-            c3L = P::mul(xwL, P::fma(ez, e3, m3));
-            c4L = P::mul(xwL, P::fma((R)-5 * ez, xw4, hh15));
+            c3L = P::mul(xw2, P::fma(ez, e3, m3));
+            c4L = P::mul(xw2, P::fma((R)-5 * ez, xw4, hh15));
             isoz = P::fma(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)), iso);
         } else {
             iso = ciso;
@@ -300,7 +309,7 @@ struct Pos64 {
 
 template <>
 struct SymStage<float> {
-    float2 xy[128], zx[128], yz[128], fxy[128], fz[128];  // (xh, yh), (zh, xl), (yl, zl), (fx, fy), (fz, -)
+    float2 xy[128], zx[128], yz[128], fxy[128], fz[128];  // (xh, yh), (zh, xl), (yl, zl), (fx, fy), (fz, 2 zh)
     __device__ __forceinline__ void put(int l, double px, double py, double pz, float fx, float fy, float gz) {
         Pos2 q;
         q.set(px, py, pz);
@@ -308,17 +317,18 @@ struct SymStage<float> {
         zx[l] = zx[l + 64] = make_float2(q.zh, q.xl);
         yz[l] = yz[l + 64] = make_float2(q.yl, q.zl);
         fxy[l] = fxy[l + 64] = make_float2(fx, fy);
-        fz[l] = fz[l + 64] = make_float2(gz, 0.f);
+        fz[l] = fz[l + 64] = make_float2(gz, q.zh + q.zh);
     }
-    // r = target - source in FP32; zj = the source's height (its hi part)
+    // r = target - source in FP32; zj = the source's height (its hi part),
+    // zj2 = 2 zj
     __device__ __forceinline__ void diff(int e, const Pos2 &t, float &rx, float &ry, float &rz, float &fx, float &fy,
-                                         float &gz, float &zj) const {
+                                         float &gz, float &zj, float &zj2) const {
         using P = VOp<float>;
         const float2 a = xy[e], b = zx[e], c = yz[e], f = fxy[e], g = fz[e];
         rx = P::add(P::sub(t.xh, a.x), P::sub(t.xl, b.y));
         ry = P::add(P::sub(t.yh, a.y), P::sub(t.yl, c.x));
         rz = P::add(P::sub(t.zh, b.x), P::sub(t.zl, c.y));
-        fx = f.x, fy = f.y, gz = g.x, zj = b.x;
+        fx = f.x, fy = f.y, gz = g.x, zj = b.x, zj2 = g.y;
     }
 };
 template <>
@@ -333,10 +343,11 @@ struct SymStage<double> {
         fz[l] = fz[l + 64] = gz;
     }
     __device__ __forceinline__ void diff(int e, const Pos64 &t, double &rx, double &ry, double &rz, double &gx,
-                                         double &gy, double &gz, double &zj) const {
+                                         double &gy, double &gz, double &zj, double &zj2) const {
         rx = t.v[0] - x[e], ry = t.v[1] - y[e], rz = t.v[2] - z[e];
         gx = fx[e], gy = fy[e], gz = fz[e];
         zj = z[e];
+        zj2 = zj + zj;
     }
 };
 
@@ -390,7 +401,8 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     const gptr<double> __restrict__ slam = (gptr<double>)J.lam;
     const bool diag = I == Jb;
     const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
-    const R a = (R)J.a, four_a2 = (R)J.four_a2, kiso = (R)J.k_near_iso, krr = (R)J.k_near_rr;
+    // positions in units of the blob radius (see PairCoef)
+    const double inv_a = 1.0 / J.a;
     const R tiny = sizeof(R) == 4 ? (R)1e-30f : (R)1e-280;
     // tile sums: with FP32 pairs and B = 64 each one is an FP32 sum over 64
     // sources, stored exactly as a float; larger tiles add their groups of 64
@@ -409,7 +421,8 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         if ((int64_t)I * B + sub * 64 >= nb) break;  // wave-uniform
         const bool active = i < nb;
         const int64_t ii = active ? i : (int64_t)I * B + sub * 64;
-        const double xi = as_global(J.tpos)[3 * ii], yi = as_global(J.tpos)[3 * ii + 1], zi = as_global(J.tpos)[3 * ii + 2];
+        const double xi = as_global(J.tpos)[3 * ii] * inv_a, yi = as_global(J.tpos)[3 * ii + 1] * inv_a,
+                     zi = as_global(J.tpos)[3 * ii + 2] * inv_a;
         const auto tp = TargetPos<R>::make(xi, yi, zi);
         // the target's own force enters the transposed contraction
         const R fix = active ? (R)as_global(J.lam)[3 * ii] : (R)0, fiy = active ? (R)as_global(J.lam)[3 * ii + 1] : (R)0,
@@ -424,10 +437,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 const int je = (int)min((int64_t)64, s1 - jb);
                 for (int jj = 0; jj < je; ++jj) {
                     const int64_t j = jb + jj;
-                    const double sx = spos[3 * j], sy = spos[3 * j + 1], sz = spos[3 * j + 2];
+                    const double sx = spos[3 * j] * inv_a, sy = spos[3 * j + 1] * inv_a, sz = spos[3 * j + 2] * inv_a;
                     const R rx = (R)(xi - sx), ry = (R)(yi - sy), rz = (R)(zi - sz);
                     PairCoef<R, WALL> pc;
-                    pc.eval(rx, ry, rz, (R)sz, a, four_a2, kiso, krr, tiny);
+                    pc.eval(rx, ry, rz, (R)sz, tiny);
                     pc.template apply<false>(rx, ry, rz, (R)slam[3 * j], (R)slam[3 * j + 1], (R)slam[3 * j + 2], ax, ay,
                                              az);
                 }
@@ -437,7 +450,7 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 const int64_t jl = jb + lane;
                 const bool jvalid = jl < s1;
                 const int64_t js = jvalid ? jl : jb;
-                const double px = spos[3 * js], py = spos[3 * js + 1], pz = spos[3 * js + 2];
+                const double px = spos[3 * js] * inv_a, py = spos[3 * js + 1] * inv_a, pz = spos[3 * js + 2] * inv_a;
                 const R gx = jvalid ? (R)slam[3 * js] : (R)0, gy = jvalid ? (R)slam[3 * js + 1] : (R)0,
                         gz = jvalid ? (R)slam[3 * js + 2] : (R)0;
                 __syncthreads();  // the previous group's reads are done
@@ -446,18 +459,18 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 R ux = 0, uy = 0, uz = 0;
 #pragma unroll 2
                 for (int step = 0; step < 64; ++step) {
-                    R rx, ry, rz, sfx, sfy, sfz, szj;
-                    st.diff(lane - step + 64, tp, rx, ry, rz, sfx, sfy, sfz, szj);
+                    R rx, ry, rz, sfx, sfy, sfz, szj, szj2;
+                    st.diff(lane - step + 64, tp, rx, ry, rz, sfx, sfy, sfz, szj, szj2);
                     PairCoef<R, WALL> pc;
                     const R rxy2 = VOp<R>::fma(ry, ry, VOp<R>::mul(rx, rx));
                     const R d2 = VOp<R>::fma(rz, rz, rxy2);
                     // overlapping pairs (r <= 2a) are rare away from the
                     // diagonal tiles: when no lane of the wave has one, the
                     // far branch alone is evaluated (wave-uniform branch)
-                    if (__ballot(d2 <= four_a2) != 0)
-                        pc.template eval_d2<true>(rxy2, d2, rz, szj, a, four_a2, kiso, krr, tiny);
+                    if (__ballot(d2 <= (R)4) != 0)
+                        pc.template eval_d2<true>(rxy2, d2, rz, szj, szj2, tiny);
                     else
-                        pc.template eval_d2<false>(rxy2, d2, rz, szj, a, four_a2, kiso, krr, tiny);
+                        pc.template eval_d2<false>(rxy2, d2, rz, szj, szj2, tiny);
                     pc.template apply<false>(rx, ry, rz, sfx, sfy, sfz, ax, ay, az);
                     pc.template apply<true>(rx, ry, rz, fix, fiy, fiz, ux, uy, uz);
                     ux = rot1(ux), uy = rot1(uy), uz = rot1(uz);
@@ -524,10 +537,12 @@ __global__ __launch_bounds__(kPairBlock) void pair_lds_f32_kernel(const PairJob 
     const bool active = i < J.nb;
     const int64_t ii = active ? i : t0;  // idle lanes shadow a valid target
     const gmem<const double> tpos = as_global(J.tpos);
+    // positions in units of the blob radius (see PairCoef)
+    const double inv_a = 1.0 / J.a;
     Pos2 tp;
-    tp.set(tpos[3 * ii], tpos[3 * ii + 1], tpos[3 * ii + 2]);
+    tp.set(tpos[3 * ii] * inv_a, tpos[3 * ii + 1] * inv_a, tpos[3 * ii + 2] * inv_a);
     const gmem<const SrcF32> src = as_global((const SrcF32 *)J.src);
-    const float a = J.a_f, four_a2 = J.four_a2_f, kiso = J.k_near_iso_f, krr = J.k_near_rr_f, tiny = 1e-30f;
+    const float tiny = 1e-30f;
     double vx = 0.0, vy = 0.0, vz = 0.0;
 
     for (int64_t jb = s0; jb < s1; jb += kPairBlock) {
@@ -535,14 +550,14 @@ __global__ __launch_bounds__(kPairBlock) void pair_lds_f32_kernel(const PairJob 
         const int64_t js = j < s1 ? j : jb;
         const gmem<const SrcF32> r = src + js;
         Pos2 q;
-        q.set(r->x, r->y, r->z);
+        q.set(r->x * inv_a, r->y * inv_a, r->z * inv_a);
         const float fx = j < s1 ? r->fx : 0.f, fy = j < s1 ? r->fy : 0.f, gz = j < s1 ? r->fz : 0.f;
         __syncthreads();  // the previous block's reads are done
         st.xy[tid] = make_float2(q.xh, q.yh);
         st.zx[tid] = make_float2(q.zh, q.xl);
         st.yz[tid] = make_float2(q.yl, q.zl);
         st.fxy[tid] = make_float2(fx, fy);
-        st.fz[tid] = make_float2(gz, 0.f);
+        st.fz[tid] = make_float2(gz, q.zh + q.zh);
         __syncthreads();
         const int ne = (int)min((int64_t)kPairBlock, s1 - jb);
         for (int g = 0; g < ne; g += kAccBlock) {
@@ -557,10 +572,10 @@ __global__ __launch_bounds__(kPairBlock) void pair_lds_f32_kernel(const PairJob 
                 const float rxy2 = P::fma(ry, ry, P::mul(rx, rx));
                 const float d2 = P::fma(rz, rz, rxy2);
                 PairCoef<float, WALL> pc;
-                if (__ballot(d2 <= four_a2) != 0)
-                    pc.template eval_d2<true>(rxy2, d2, rz, zx.x, a, four_a2, kiso, krr, tiny);
+                if (__ballot(d2 <= 4.f) != 0)
+                    pc.template eval_d2<true>(rxy2, d2, rz, zx.x, fzz.y, tiny);
                 else
-                    pc.template eval_d2<false>(rxy2, d2, rz, zx.x, a, four_a2, kiso, krr, tiny);
+                    pc.template eval_d2<false>(rxy2, d2, rz, zx.x, fzz.y, tiny);
                 pc.template apply<false>(rx, ry, rz, f.x, f.y, fzz.x, ax, ay, az);
             }
             vx += (double)ax;
