@@ -237,11 +237,13 @@ struct PairCoef {
             // c1 and c2 carry xi / 4, folded into their polynomials
             iso = P::fma(xw, P::fma(xw4, (R)-2.5 * ez2 + (R)0.5, P::fma(xw2, (R)1.5 * ez2 - (R)0.5, (R)1.5 * T - (R)0.75)),
                          ciso);
-            c2L = P::mul(xw3,
-                         P::fma(xw4, (R)17.5 * ez2 - (R)2.5, P::fma(xw2, (R)-7.5 * ez2 + (R)1.5, (R)-4.5 * T - (R)0.75)));
+            const R q2 = P::fma(xw4, (R)17.5 * ez2 - (R)2.5, P::fma(xw2, (R)-7.5 * ez2 + (R)1.5, (R)-4.5 * T - (R)0.75));
+            c2L = P::mul(xw3, q2);
             const R hh15 = (R)1.5 * hh;
             const R m3 = P::mul(hh15, (R)-6 * ez2 + ((R)6 * ezh + (R)1));
-            const R e3 = P::fma(xw4, (R)-35 * ez2 + (R)10, P::mul(xw2, (R)15 * ez2 - (R)3));
+            // e3 = xw^4 (10 - 35 ez^2) + xw^2 (15 ez^2 - 3) equals 5 xw^4 minus
+            // twice the xw-part of q2
+            const R e3 = (R)-2 * q2 + ((R)5 * xw4 + ((R)-9 * T - (R)1.5));
             c3L = P::mul(xw2, P::fma(ez, e3, m3));
             c4L = P::mul(xw2, P::fma((R)-5 * ez, xw4, hh15));
             isoz = P::fma(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)), iso);
