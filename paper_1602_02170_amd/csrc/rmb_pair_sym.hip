@@ -234,17 +234,19 @@ struct PairCoef {
             const R hh2 = P::mul(hh, hh), ezh = P::mul(ez, hh);
             const R T = P::sub(hh2, ezh);
             const R xw3 = P::mul(xw, xw2);
-            // c1 and c2 carry xi / 4, folded into their polynomials
-            iso = P::fma(xw, P::fma(xw4, (R)-2.5 * ez2 + (R)0.5, P::fma(xw2, (R)1.5 * ez2 - (R)0.5, (R)1.5 * T - (R)0.75)),
-                         ciso);
+            // c1 and c2 carry xi / 4, folded into their polynomials:
+            //   c1 = xw q1, q1 = xw^4 (0.5 - 2.5 ez^2) + xw^2 (1.5 ez^2 - 0.5) + 1.5 T - 0.75
+            //   c2 = xw q2, q2 = xw^4 (17.5 ez^2 - 2.5) + xw^2 (1.5 - 7.5 ez^2) - 4.5 T - 0.75
+            // and q1 = -q2 / 5 + xw^4 ez^2 - 0.2 xw^2 + 0.6 T - 0.9
             const R q2 = P::fma(xw4, (R)17.5 * ez2 - (R)2.5, P::fma(xw2, (R)-7.5 * ez2 + (R)1.5, (R)-4.5 * T - (R)0.75));
+            const R q1 = (R)-0.2 * q2 + P::fma(xw4, ez2, (R)-0.2 * xw2 + ((R)0.6 * T - (R)0.9));
+            iso = P::fma(xw, q1, ciso);
             c2L = P::mul(xw3, q2);
+            // c3 = xw^2 (ez e3 + m3) with e3 = xw^4 (10 - 35 ez^2) + xw^2 (15 ez^2 - 3)
+            // and m3 = 1.5 hh (1 - 6 ez^2 + 6 ez hh) = 1.5 hh + 9 ez T; since
+            // e3 + 9 T = 5 xw^4 - 2 q2 - 1.5, ez e3 + m3 = ez (5 xw^4 - 2 q2 - 1.5) + 1.5 hh
             const R hh15 = (R)1.5 * hh;
-            const R m3 = P::mul(hh15, (R)-6 * ez2 + ((R)6 * ezh + (R)1));
-            // e3 = xw^4 (10 - 35 ez^2) + xw^2 (15 ez^2 - 3) equals 5 xw^4 minus
-            // twice the xw-part of q2
-            const R e3 = (R)-2 * q2 + ((R)5 * xw4 + ((R)-9 * T - (R)1.5));
-            c3L = P::mul(xw2, P::fma(ez, e3, m3));
+            c3L = P::mul(xw2, P::fma(ez, (R)-2 * q2 + ((R)5 * xw4 - (R)1.5), hh15));
             c4L = P::mul(xw2, P::fma((R)-5 * ez, xw4, hh15));
             isoz = P::fma(xw, P::fma(xw4, (R)15 * ez2 - (R)2, (R)-3 * P::fma(ez2, xw2, hh2)), iso);
         } else {
