@@ -361,9 +361,6 @@ static rmb_status product_enqueue(rmb_ctx ctx, const rmb_system *sys, int32_t pr
         J.acc = vel;
         J.nb = nb;
         J.a = sys->a;
-        J.four_a2 = 4.0 * sys->a * sys->a;
-        J.k_near_iso = 9.0 / (32.0 * sys->a);
-        J.k_near_rr = 3.0 / (32.0 * sys->a);
         J.pref = pref;
         J.f32 = precision == RMB_PREC_FP32_PAIRS;
         for (size_t b = 0; b < bands.size(); ++b) {

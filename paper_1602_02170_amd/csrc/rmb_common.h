@@ -58,9 +58,9 @@ struct PairJob {
     int64_t chunk;
     int32_t n_tblock;
     int32_t n_split;
-    // RPY constants (eq:RPYTensor) in both precisions: a, 4a^2, 9/(32a), 3/(32a)
+    // RPY constants (eq:RPYTensor): a, 4a^2, 9/(32a), 3/(32a) (the FP32
+    // kernel takes lengths in units of a and uses a alone)
     double a, four_a2, k_near_iso, k_near_rr;
-    float a_f, four_a2_f, k_near_iso_f, k_near_rr_f;
 };
 
 hipError_t launch_store_pair_job(const PairJob &j, PairJob *dst, hipStream_t s);
@@ -111,9 +111,9 @@ struct SymJob {
     int32_t B;
     int32_t I0, I1;      // block rows of the band
     int32_t first, last; // the band is the system's first / last
-    int32_t f32;         // partials are floats (FP32 pairs: each tile's sums are FP32 values)
+    int32_t f32;         // FP32 pairs (with B = 64 the tile partials are floats)
     int32_t pad;
-    double a, four_a2, k_near_iso, k_near_rr;
+    double a;            // blob radius (the kernel takes lengths in units of a)
     double pref;
 };
 

@@ -799,9 +799,6 @@ struct Engine {
                 y.n_blk = J->symT;
                 y.B = J->symB;
                 y.a = J->sys.a;
-                y.four_a2 = 4.0 * J->sys.a * J->sys.a;
-                y.k_near_iso = 9.0 / (32.0 * J->sys.a);
-                y.k_near_rr = 3.0 / (32.0 * J->sys.a);
                 y.pref = mobility_prefactor(J->sys.a, J->sys.eta);
                 y.f32 = f32 ? 1 : 0;
                 const int bi = bidx(J->symB);

@@ -65,10 +65,6 @@ void pair_job_init_rect(PairJob *J, const double *tpos, int64_t nt, const void *
     J->four_a2 = 4.0 * a * a;
     J->k_near_iso = 9.0 / (32.0 * a);
     J->k_near_rr = 3.0 / (32.0 * a);
-    J->a_f = (float)J->a;
-    J->four_a2_f = (float)J->four_a2;
-    J->k_near_iso_f = (float)J->k_near_iso;
-    J->k_near_rr_f = (float)J->k_near_rr;
 }
 
 // ---------------------------------------------------------------------------
