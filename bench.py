@@ -32,8 +32,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Flop counts of the implemented pair kernels (FMA = 2, add/mul = 1,
-# reciprocal square root = 1, compares/selects/conversions = 0):
+# Flop counts of the pair arithmetic (FMA = 2, add/mul = 1, reciprocal
+# square root = 1, compares/selects/conversions = 0), counted once from the
+# first implemented form of each kernel and held fixed as the unit of work
+# (the current forms execute fewer: lengths in units of a, shared wall
+# polynomials):
 #  one-sided kernel, per ordered pair;
 #  symmetric kernel, per unordered off-diagonal pair (coefficients once, both
 #  contractions) and per ordered pair of its diagonal tiles.
