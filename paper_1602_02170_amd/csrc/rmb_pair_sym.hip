@@ -158,12 +158,6 @@ struct VOp<float> {
         asm("v_fma_f32 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "v"(c));
         return d;
     }
-    // 1 - a b
-    static __device__ __forceinline__ float one_minus(float a, float b) {
-        float d;
-        asm("v_fma_f32 %0, -%1, %2, 1.0" : "=v"(d) : "v"(a), "v"(b));
-        return d;
-    }
 };
 template <>
 struct VOp<double> {
@@ -171,7 +165,6 @@ struct VOp<double> {
     static __device__ __forceinline__ double add(double a, double b) { return a + b; }
     static __device__ __forceinline__ double sub(double a, double b) { return a - b; }
     static __device__ __forceinline__ double fma(double a, double b, double c) { return ::fma(a, b, c); }
-    static __device__ __forceinline__ double one_minus(double a, double b) { return ::fma(-a, b, 1.0); }
 };
 
 // Coefficients of one pair block, shared by both contractions:
