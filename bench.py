@@ -123,22 +123,32 @@ def solve_leg(rmb, torch, ctx, sysd, FT, precision, steps, warmup, tol=1e-8, u_t
 def matvec_leg(rmb, torch, ctx, S, reps=20):
     """Wall mobility products of prefixes of the 128 x 128 icosahedron
     monolayer (1024 ... 16384 bodies, 12,288 ... 196,608 blobs): median of
-    `reps` launches after a warm-up, each launch timed with its own events."""
+    `reps` launches after a warm-up, each launch timed with its own events.
+    The FP32 leg takes float32 forces and returns float32 velocities
+    (rmb_mobility_matvec_f32), the FP64 leg float64 ones."""
     res = {"workload": "wall RPY mobility product, 16384 x 12-blob icosahedra monolayer (196,608 blobs) and "
-                       "prefixes of it", "sweep": []}
+                       "prefixes of it", "forces": {"fp32": "float32 in, float32 out", "fp64": "float64"},
+           "sweep": []}
     for n_bodies in (1024, 2048, 4096, 8192, 16384):
         sus, lam = S.icosahedra_monolayer(n_bodies=n_bodies)
         sysd = rmb.System.from_suspension(sus)
         lt = torch.tensor(lam, dtype=torch.float64, device="cuda")
         out = torch.empty_like(lt)
+        lt32 = torch.tensor(lam.astype(np.float32), device="cuda")
+        out32 = torch.empty_like(lt32)
         row = {"n_blobs": sus.n_blobs}
         for prec in ("fp32", "fp64"):
-            rmb.mobility_matvec(ctx, sysd, lt, prec, out)
+            def product():
+                if prec == "fp32":
+                    rmb.mobility_matvec_f32(ctx, sysd, lt32, out32)
+                else:
+                    rmb.mobility_matvec(ctx, sysd, lt, prec, out)
+            product()
             torch.cuda.synchronize()
             ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
             for e0, e1 in ev:
                 e0.record()
-                rmb.mobility_matvec(ctx, sysd, lt, prec, out)
+                product()
                 e1.record()
             torch.cuda.synchronize()
             ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
@@ -149,7 +159,7 @@ def matvec_leg(rmb, torch, ctx, S, reps=20):
             log(f"  matvec {sus.n_blobs} blobs {prec}: {ms:.3f} ms, {row[f'{prec}_pairs_per_s']:.3e} pairs/s, "
                 f"{row[f'{prec}_tflops']:.1f} TFLOP/s")
         res["sweep"].append(row)
-        del lt, out
+        del lt, out, lt32, out32
     full = res["sweep"][-1]
     for k in ("fp32_ms", "fp32_pairs_per_s", "fp32_tflops", "fp64_ms", "fp64_pairs_per_s", "fp64_tflops"):
         res[k] = full[k]

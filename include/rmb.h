@@ -213,6 +213,17 @@ rmb_status rmb_ctx_tune_log(rmb_ctx ctx, int32_t capacity, rmb_tune_record *reco
 rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t precision,
                                const double *lambda, double *vel, rmb_stream stream);
 
+/* The FP32-pair product for FP32 data: lambda and vel are device [Nb][3]
+ * float32 (must not alias).  The forces are widened to FP64 (exactly), the
+ * product runs as rmb_mobility_matvec with RMB_PREC_FP32_PAIRS (FP32 pair
+ * blocks, FP32 sums over 64 sources, FP64 beyond), and each velocity is
+ * rounded to float32 once: the result is rmb_mobility_matvec's on the
+ * widened forces, rounded to float32.  Workspace comes from the context
+ * (twice 3 Nb doubles more than rmb_mobility_matvec).  Errors as
+ * rmb_mobility_matvec.  Synchronises `stream` once for validation. */
+rmb_status rmb_mobility_matvec_f32(rmb_ctx ctx, const rmb_system *sys, const float *lambda, float *vel,
+                                   rmb_stream stream);
+
 /* The same product for callers that cannot allocate device memory (code
  * that must not call hipMalloc: a tight serving loop, a harness that forbids
  * allocation, work being captured into a HIP graph).  It allocates nothing:

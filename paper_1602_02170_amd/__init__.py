@@ -34,7 +34,8 @@ EXPORTS = ["rmb_ctx_create", "rmb_ctx_destroy", "rmb_last_error", "rmb_version",
            "rmb_ctx_kernel_time", "rmb_ctx_tuned_panel", "rmb_ctx_tune_log", "rmb_pair_plan",
            "rmb_flow_field", "rmb_precond_factor_shapes", "rmb_precond_set_orientations",
            "rmb_solve_resistance", "rmb_mobility_matvec_noalloc", "rmb_noalloc_workspace_bytes",
-           "rmb_tile_shape_count", "rmb_tile_shape_info", "rmb_ctx_set_tile_shape"]
+           "rmb_tile_shape_count", "rmb_tile_shape_info", "rmb_ctx_set_tile_shape",
+           "rmb_mobility_matvec_f32"]
 KERNELS = {"pair_f32_wall": 0, "pair_f32_free": 1, "pair_f64_wall": 2, "pair_f64_free": 3}
 
 
@@ -98,6 +99,7 @@ def library(path: str = LIB_PATH):
         L.rmb_version.restype = ctypes.c_char_p
         L.rmb_mobility_matvec.argtypes = [vp, sysp, i32, vp, vp, vp]
         L.rmb_mobility_matvec_noalloc.argtypes = [vp, sysp, i32, vp, vp, i32, vp]
+        L.rmb_mobility_matvec_f32.argtypes = [vp, sysp, vp, vp, vp]
         L.rmb_noalloc_workspace_bytes.argtypes = []
         L.rmb_noalloc_workspace_bytes.restype = ctypes.c_size_t
         L.rmb_flow_field.argtypes = [vp, sysp, i32, vp, i32, ctypes.POINTER(ctypes.c_double), ctypes.c_double,
@@ -160,11 +162,11 @@ def _stream(stream=None):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def _dev(t: torch.Tensor, name: str, shape=None):
+def _dev(t: torch.Tensor, name: str, shape=None, dtype=torch.float64):
     if not isinstance(t, torch.Tensor) or not t.is_cuda:
         raise TypeError(f"{name} must be a device tensor")
-    if t.dtype != torch.float64:
-        raise TypeError(f"{name} must be float64")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {str(dtype).replace('torch.', '')}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if shape is not None and tuple(t.shape) != tuple(shape):
@@ -292,6 +294,19 @@ def mobility_matvec(ctx: Context, system: System, lam: torch.Tensor, precision="
     op = _dev(out, "out", (n, 3))
     ctx.check(ctx.lib.rmb_mobility_matvec(ctx.h, ctypes.byref(system.c), _prec(precision), lp, op,
                                           _stream(stream)))
+    return out
+
+
+def mobility_matvec_f32(ctx: Context, system: System, lam: torch.Tensor, out: torch.Tensor = None,
+                        stream=None) -> torch.Tensor:
+    """v = M lambda for float32 forces (Nb, 3), FP32 pairs with FP64
+    accumulation, velocities rounded to float32 (rmb_mobility_matvec_f32)."""
+    n = system.n_blobs
+    lp = _dev(lam, "lambda", (n, 3), torch.float32)
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=lam.device)
+    op = _dev(out, "out", (n, 3), torch.float32)
+    ctx.check(ctx.lib.rmb_mobility_matvec_f32(ctx.h, ctypes.byref(system.c), lp, op, _stream(stream)))
     return out
 
 

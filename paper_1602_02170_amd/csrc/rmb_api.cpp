@@ -418,6 +418,41 @@ rmb_status rmb_mobility_matvec(rmb_ctx ctx, const rmb_system *sys, int32_t preci
 
 __global__ void zero_flag_kernel(int *flag) { *as_global(flag) = 0; }
 
+// FP32 forces in and velocities out around the FP32-pair product: widening
+// to FP64 is exact, and the FP64 sums are rounded to FP32 once at the end.
+__global__ void widen_f32_kernel(const float *__restrict__ x, double *__restrict__ y, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) as_global(y)[e] = (double)as_global(x)[e];
+}
+__global__ void narrow_f64_kernel(const double *__restrict__ x, float *__restrict__ y, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) as_global(y)[e] = (float)as_global(x)[e];
+}
+
+rmb_status rmb_mobility_matvec_f32(rmb_ctx ctx, const rmb_system *sys, const float *lambda, float *vel,
+                                   rmb_stream stream) {
+    if (!ctx) return RMB_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    RMB_TRY(enter(ctx, s));
+    RMB_TRY(check_system(ctx, sys, false));
+    if (!lambda || !vel) return fail(ctx, RMB_EINVAL, "lambda and vel are required");
+    if ((const void *)lambda == (const void *)vel) return fail(ctx, RMB_EINVAL, "vel must not alias lambda");
+    const int64_t n3 = 3 * sys->n_blobs;
+    const size_t work = (product_work_bytes(sys->n_blobs, RMB_PREC_FP32_PAIRS, ctx->sym_band_bytes) + 255) / 256 * 256;
+    const size_t vec = ((size_t)n3 * sizeof(double) + 255) / 256 * 256;
+    char *base = nullptr;
+    RMB_TRY(ctx_scratch(ctx, work + 2 * vec, (void **)&base));
+    RMB_TRY(check_positions(ctx, sys, (int *)base, s));
+    double *lam64 = (double *)(base + work), *vel64 = (double *)(base + work + vec);
+    const unsigned g = (unsigned)((n3 + 255) / 256);
+    hipLaunchKernelGGL(widen_f32_kernel, dim3(g), dim3(256), 0, s, lambda, lam64, n3);
+    RMB_HIP(ctx, hipGetLastError());
+    RMB_TRY(product_enqueue(ctx, sys, RMB_PREC_FP32_PAIRS, lam64, vel64, base, ctx->sym_band_bytes, true, s));
+    hipLaunchKernelGGL(narrow_f64_kernel, dim3(g), dim3(256), 0, s, vel64, vel, n3);
+    RMB_HIP(ctx, hipGetLastError());
+    return RMB_OK;
+}
+
 rmb_status rmb_mobility_matvec_noalloc(rmb_ctx ctx, const rmb_system *sys, int32_t precision, const double *lambda,
                                        double *vel, int32_t validate, rmb_stream stream) {
     if (!ctx) return RMB_EINVAL;

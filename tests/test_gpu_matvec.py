@@ -141,6 +141,31 @@ def test_matvec_million_blobs_sampled_rows(env, prec):
     assert np.all(np.isfinite(v))
 
 
+@pytest.mark.parametrize("case", [0, 1, 3], ids=[CASES[c][0] for c in (0, 1, 3)])
+def test_matvec_float32_data(env, case):
+    """rmb_mobility_matvec_f32 (float32 forces in, float32 velocities out):
+    bitwise the FP32-pair product of the forces widened to float64, rounded
+    to float32 once; and the oracle's FP64 product of those forces within
+    the FP32 bar.  One-sided (96 blobs) and symmetric sizes, the last with a
+    ragged block."""
+    rmb, torch, ctx, orc = env
+    name, sus, lam = CASES[case]
+    print(f"[gpu] float32 data {name} nb={sus.n_blobs}", flush=True)
+    sysd = rmb.System.from_suspension(sus)
+    l32 = torch.tensor(lam.astype(np.float32), device="cuda")
+    v32 = rmb.mobility_matvec_f32(ctx, sysd, l32)
+    v64 = rmb.mobility_matvec(ctx, sysd, l32.double(), "fp32")
+    torch.cuda.synchronize()
+    assert v32.dtype == torch.float32
+    assert torch.equal(v32, v64.float())
+    ref = orc.matvec(sus.pos, lam.astype(np.float32).astype(np.float64), sus.a, sus.eta, sus.wall)
+    err = _rel(v32.cpu().numpy().astype(np.float64), ref)
+    print(f"    rel err {err:.3e}", flush=True)
+    assert err <= TOL["fp32"]
+    with pytest.raises(TypeError):
+        rmb.mobility_matvec_f32(ctx, sysd, l32.double())
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_matvec_edge_cases(env, prec):
     rmb, torch, ctx, O = env
