@@ -302,12 +302,15 @@ struct Pos2 {
 
 struct Pos64 {
     double v[3];
+    double ia;  // 1/a: FP64 differences are formed from physical positions, then scaled
 };
 
 template <>
 struct SymStage<float> {
     float2 xy[128], zx[128], yz[128], fxy[128], fz[128];  // (xh, yh), (zh, xl), (yl, zl), (fx, fy), (fz, 2 zh)
-    __device__ __forceinline__ void put(int l, double px, double py, double pz, float fx, float fy, float gz) {
+    // positions already in units of a (zs, the same height, unused here)
+    __device__ __forceinline__ void put(int l, double px, double py, double pz, float fx, float fy, float gz,
+                                        double /*zs*/) {
         Pos2 q;
         q.set(px, py, pz);
         xy[l] = xy[l + 64] = make_float2(q.xh, q.yh);
@@ -329,21 +332,28 @@ struct SymStage<float> {
     }
 };
 template <>
+// FP64 pairs: physical positions, so that the difference of two nearby
+// positions is exact, scaled by 1/a afterwards (one rounding, relative);
+// scaling the positions first would round each of them at the scale of its
+// own coordinate, an error that grows as 1/a relative to the pair distance.
+// zs: the source's height in units of a.
 struct SymStage<double> {
-    double x[128], y[128], z[128], fx[128], fy[128], fz[128];
-    __device__ __forceinline__ void put(int l, double px, double py, double pz, double gx, double gy, double gz) {
+    double x[128], y[128], z[128], zs[128], fx[128], fy[128], fz[128];
+    __device__ __forceinline__ void put(int l, double px, double py, double pz, double gx, double gy, double gz,
+                                        double pzs) {
         x[l] = x[l + 64] = px;
         y[l] = y[l + 64] = py;
         z[l] = z[l + 64] = pz;
+        zs[l] = zs[l + 64] = pzs;
         fx[l] = fx[l + 64] = gx;
         fy[l] = fy[l + 64] = gy;
         fz[l] = fz[l + 64] = gz;
     }
     __device__ __forceinline__ void diff(int e, const Pos64 &t, double &rx, double &ry, double &rz, double &gx,
                                          double &gy, double &gz, double &zj, double &zj2) const {
-        rx = t.v[0] - x[e], ry = t.v[1] - y[e], rz = t.v[2] - z[e];
+        rx = (t.v[0] - x[e]) * t.ia, ry = (t.v[1] - y[e]) * t.ia, rz = (t.v[2] - z[e]) * t.ia;
         gx = fx[e], gy = fy[e], gz = fz[e];
-        zj = z[e];
+        zj = zs[e];
         zj2 = zj + zj;
     }
 };
@@ -363,7 +373,7 @@ struct TargetPos<float> {
 template <>
 struct TargetPos<double> {
     using T = Pos64;
-    static __device__ __forceinline__ T make(double x, double y, double z) { return Pos64{{x, y, z}}; }
+    static __device__ __forceinline__ T make(double x, double y, double z) { return Pos64{{x, y, z}, 1.0}; }
 };
 
 // One tile per wave.  B: block size (multiple of 64).
@@ -398,8 +408,11 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
     const gptr<double> __restrict__ slam = (gptr<double>)J.lam;
     const bool diag = I == Jb;
     const int64_t s0 = (int64_t)Jb * B, s1 = min(s0 + B, nb);
-    // positions in units of the blob radius (see PairCoef)
+    // lengths in units of the blob radius (see PairCoef): FP32 pairs scale
+    // the positions (ps) before they are split into two floats, FP64 pairs
+    // scale each difference (ds; see SymStage<double>)
     const double inv_a = 1.0 / J.a;
+    const double ps = sizeof(R) == 4 ? inv_a : 1.0, ds = sizeof(R) == 4 ? 1.0 : inv_a;
     const R tiny = sizeof(R) == 4 ? (R)1e-30f : (R)1e-280;
     // tile sums: with FP32 pairs and B = 64 each one is an FP32 sum over 64
     // sources, stored exactly as a float; larger tiles add their groups of 64
@@ -418,9 +431,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
         if ((int64_t)I * B + sub * 64 >= nb) break;  // wave-uniform
         const bool active = i < nb;
         const int64_t ii = active ? i : (int64_t)I * B + sub * 64;
-        const double xi = as_global(J.tpos)[3 * ii] * inv_a, yi = as_global(J.tpos)[3 * ii + 1] * inv_a,
-                     zi = as_global(J.tpos)[3 * ii + 2] * inv_a;
-        const auto tp = TargetPos<R>::make(xi, yi, zi);
+        const double xi = as_global(J.tpos)[3 * ii] * ps, yi = as_global(J.tpos)[3 * ii + 1] * ps,
+                     zi = as_global(J.tpos)[3 * ii + 2] * ps;
+        auto tp = TargetPos<R>::make(xi, yi, zi);
+        if constexpr (sizeof(R) == 8) tp.ia = ds;
         // the target's own force enters the transposed contraction
         const R fix = active ? (R)as_global(J.lam)[3 * ii] : (R)0, fiy = active ? (R)as_global(J.lam)[3 * ii + 1] : (R)0,
                 fiz = active ? (R)as_global(J.lam)[3 * ii + 2] : (R)0;
@@ -434,10 +448,10 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 const int je = (int)min((int64_t)64, s1 - jb);
                 for (int jj = 0; jj < je; ++jj) {
                     const int64_t j = jb + jj;
-                    const double sx = spos[3 * j] * inv_a, sy = spos[3 * j + 1] * inv_a, sz = spos[3 * j + 2] * inv_a;
-                    const R rx = (R)(xi - sx), ry = (R)(yi - sy), rz = (R)(zi - sz);
+                    const double sx = spos[3 * j] * ps, sy = spos[3 * j + 1] * ps, sz = spos[3 * j + 2] * ps;
+                    const R rx = (R)((xi - sx) * ds), ry = (R)((yi - sy) * ds), rz = (R)((zi - sz) * ds);
                     PairCoef<R, WALL> pc;
-                    pc.eval(rx, ry, rz, (R)sz, tiny);
+                    pc.eval(rx, ry, rz, (R)(sz * ds), tiny);
                     pc.template apply<false>(rx, ry, rz, (R)slam[3 * j], (R)slam[3 * j + 1], (R)slam[3 * j + 2], ax, ay,
                                              az);
                 }
@@ -447,11 +461,11 @@ __global__ __launch_bounds__(64) void pair_sym_kernel(const SymJob *__restrict__
                 const int64_t jl = jb + lane;
                 const bool jvalid = jl < s1;
                 const int64_t js = jvalid ? jl : jb;
-                const double px = spos[3 * js] * inv_a, py = spos[3 * js + 1] * inv_a, pz = spos[3 * js + 2] * inv_a;
+                const double px = spos[3 * js] * ps, py = spos[3 * js + 1] * ps, pz = spos[3 * js + 2] * ps;
                 const R gx = jvalid ? (R)slam[3 * js] : (R)0, gy = jvalid ? (R)slam[3 * js + 1] : (R)0,
                         gz = jvalid ? (R)slam[3 * js + 2] : (R)0;
                 __syncthreads();  // the previous group's reads are done
-                st.put(lane, px, py, pz, gx, gy, gz);
+                st.put(lane, px, py, pz, gx, gy, gz, pz * ds);
                 __syncthreads();
                 R ux = 0, uy = 0, uz = 0;
 #pragma unroll 2

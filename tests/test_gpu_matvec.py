@@ -167,6 +167,42 @@ def test_matvec_float32_data(env, case):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("a", [0.002, 30.0])
+def test_matvec_extreme_blob_radius(env, a, prec):
+    """The kernels take lengths in units of the blob radius.  The 203
+    boomerangs over the wall with a = 0.002 (positions up to ~1e5 radii,
+    every pair far apart) and a = 30 (nearly every pair overlapping, the
+    contact branch throughout; heights lifted above a): the oracle's product
+    within the bar of each precision, symmetric (3045 blobs) and one-sided
+    (the first 60 bodies, 900 blobs) paths."""
+    import copy
+    rmb, torch, ctx, orc = env
+    base = CASES[1][1]
+    sus = copy.deepcopy(base)
+    sus.a = a
+    if a > 1.0:
+        sus.pos = sus.pos.copy()
+        sus.pos[:, 2] += a
+    lam = np.random.default_rng(31).standard_normal((sus.n_blobs, 3))
+    for nb_bodies in (sus.n_bodies, 60):
+        part = copy.deepcopy(sus)
+        if nb_bodies < sus.n_bodies:
+            nbl = int(sus.body_off[nb_bodies])
+            part.pos = sus.pos[:nbl].copy()
+            part.body_off = sus.body_off[:nb_bodies + 1].copy()
+            part.q = sus.q[:nb_bodies].copy()
+            part.FT = None if sus.FT is None else sus.FT[:nb_bodies].copy()
+            part.quat = None if getattr(sus, "quat", None) is None else sus.quat[:nb_bodies].copy()
+        l = lam[:part.n_blobs]
+        print(f"[gpu] extreme radius a={a} {prec} nb={part.n_blobs}", flush=True)
+        ref = orc.matvec(part.pos, l, part.a, part.eta, part.wall)
+        v = _run(env, part, l, prec)
+        err = _rel(v, ref)
+        print(f"    rel err {err:.3e}", flush=True)
+        assert err <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_matvec_edge_cases(env, prec):
     rmb, torch, ctx, O = env
     a = 0.5
