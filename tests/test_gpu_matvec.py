@@ -167,19 +167,21 @@ def test_matvec_float32_data(env, case):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("wall", [True, False], ids=["wall", "free"])
 @pytest.mark.parametrize("a", [0.002, 30.0])
-def test_matvec_extreme_blob_radius(env, a, prec):
+def test_matvec_extreme_blob_radius(env, a, wall, prec):
     """The kernels take lengths in units of the blob radius.  The 203
-    boomerangs over the wall with a = 0.002 (positions up to ~1e5 radii,
-    every pair far apart) and a = 30 (nearly every pair overlapping, the
-    contact branch throughout; heights lifted above a): the oracle's product
-    within the bar of each precision, symmetric (3045 blobs) and one-sided
-    (the first 60 bodies, 900 blobs) paths."""
+    boomerangs, over the wall and in free space, with a = 0.002 (positions
+    up to ~1e5 radii, every pair far apart) and a = 30 (nearly every pair
+    overlapping, the contact branch throughout; heights lifted above a):
+    the oracle's product within the bar of each precision, symmetric (3045
+    blobs) and one-sided (the first 60 bodies, 900 blobs) paths."""
     import copy
     rmb, torch, ctx, orc = env
     base = CASES[1][1]
     sus = copy.deepcopy(base)
     sus.a = a
+    sus.wall = wall
     if a > 1.0:
         sus.pos = sus.pos.copy()
         sus.pos[:, 2] += a
